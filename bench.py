@@ -1,0 +1,189 @@
+"""Benchmark of the QUAPI tensor-propagator step on one MI355X.
+
+Workload: spin-boson, M = 2 (N = 4), L = Delta k_max = 15 (4^15 = 1.07e9
+tensor entries), xi = 0.5, omega_c = 10, kT = 0.05, dt = 0.1, 1000 steps by
+default, rho(t_n) extracted at every step ('allPoints').  Inputs are
+synthetic (seeded parameters, no dataset).
+
+A timed "step" is one full-window propagation step: the step kernel reads the
+tensor once, writes it once, and (fused) produces rho(t_n); the rho finalize
+kernel follows.  The growth steps (n < L) and the device setup run first and
+are reported separately.  Both precision tiers run on the same workload:
+complex128 (the reported `value`) and the complex64 tier (`fp32_tier`), with
+max|drho| and trace drift of the tier against complex128.
+
+Metric: Gelem/s = N^L * steps / seconds / 1e9, with the tensor resident in
+HBM.  `roofline` prices the step kernel against the HBM peak: algorithmic
+bytes per launch = 2 * N^L * sizeof(complex) (one read, one write), divided by
+the kernel's average duration from HIP events on the library's stream.
+`cpu_baseline` times the oracle (plain C, OpenMP) on a bounded sample of the
+same workload on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tiers c128,c64]
+                       [--no-cpu-baseline] [--traffic-json FILE]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_tier(w, dtype: str, warmup: int, steps: int):
+    import numpy as np
+    import torch
+    from paper_1205_6872_amd import quapi as Q
+
+    L, N = w.L, w.N
+    p = Q.params_from(w, dtype=dtype)
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    ctx = Q.create_in_torch(p, stream=stream)
+    setup_wall = time.perf_counter() - t0
+    try:
+        ctx.set_timing(True)
+        rho_grow = ctx.propagate(L - 1)                   # growth steps 1 .. L-1
+        rho_warm = ctx.propagate(warmup)                  # first full-window steps
+        tm = ctx.get_timing()
+        grow_ms = tm["grow_ms"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rho_main = ctx.propagate(steps)                   # timed: K full-window steps
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        tm = ctx.get_timing()
+    finally:
+        ctx.destroy()
+        del ctx
+        torch.cuda.empty_cache()
+    entries = N ** L
+    csize = 16 if dtype == "c128" else 8
+    bytes_per_launch = 2 * entries * csize
+    kernel_ms = tm["step_ms"] / max(tm["step_launches"], 1)
+    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    rho = np.concatenate([rho_grow, rho_warm, rho_main])
+    return dict(
+        dtype=dtype, elapsed_s=elapsed, steps=steps, ms_per_step=elapsed * 1e3 / steps,
+        gelem_s=entries * steps / elapsed / 1e9, kernel_ms=kernel_ms, kernel_launches=tm["step_launches"],
+        finalize_ms=tm["finalize_ms"] / max(tm["finalize_launches"], 1), setup_ms=tm["setup_ms"],
+        setup_wall_ms=setup_wall * 1e3, grow_ms=grow_ms, bytes_per_launch=bytes_per_launch,
+        achieved_gbs=achieved, rho=rho)
+
+
+def cpu_baseline(w, n_main: int = 2):
+    """Oracle on the host: growth to L, then n_main full-window steps (timed)."""
+    import numpy as np
+    from oracle.run import oracle_run
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+    rho, secs = oracle_run(w, w.L - 1 + n_main, threads=threads, return_step_seconds=True)
+    main = secs[w.L - 1:]
+    total = float(np.sum(main))
+    value = w.N ** w.L * n_main / total / 1e9
+    return dict(value=value, unit="Gelem/s", cores=threads, kind="oracle",
+                sample=(f"{w.name} complex128: growth steps 1..{w.L - 1} then {n_main} full-window "
+                        f"steps; value over the full-window steps ({total:.1f} s), "
+                        f"growth {float(np.sum(secs[:w.L - 1])):.1f} s untimed"),
+                seconds=total)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed full-window steps")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tiers", default="c128,c64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step_kernel_traffic_l15.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
+              f"multi-GPU path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1205_6872_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    w = W.spin_boson_l15("c128")
+    steps = args.steps if args.steps is not None else w.n_steps - (w.L - 1) - args.warmup
+    tiers = [t for t in args.tiers.split(",") if t]
+    res = {}
+    for t in tiers:
+        log(f"bench: tier {t}: {w.name} N^L={w.N ** w.L}, warmup {args.warmup}, timed {steps} steps")
+        res[t] = run_tier(w, t, args.warmup, steps)
+        r = res[t]
+        log(f"bench: tier {t}: {r['ms_per_step']:.3f} ms/step, {r['gelem_s']:.1f} Gelem/s, kernel "
+            f"{r['kernel_ms']:.3f} ms = {r['achieved_gbs']:.0f} GB/s")
+    main_t = "c128" if "c128" in res else tiers[0]
+    r = res[main_t]
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            with open(args.traffic_json) as f:
+                tj = json.load(f)
+            traffic = tj.get(main_t, {}).get("hbm_bytes_per_launch")
+        except Exception:
+            traffic = None
+    out = {
+        "metric": "QUAPI step Gelem/s + HBM GB/s (FP64 vs FP32) at M=2 dk=15",
+        "value": round(r["gelem_s"], 3),
+        "unit": "Gelem/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_t == "c128" else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "M": w.M, "L": w.L, "entries": w.N ** w.L,
+                   "tensor": main_t, "rho_every_step": True, "total_steps": w.L - 1 + args.warmup + steps,
+                   "xi": w.xi, "omega_c": w.omega_c, "kT": w.kT, "dt": w.dt},
+        "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "step_kernel<4,double,rho,full-window>",
+                     "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_launch": r["bytes_per_launch"]},
+        "setup_ms": round(r["setup_ms"], 3),
+        "growth_ms": round(r["grow_ms"], 3),
+        "finalize_ms": round(r["finalize_ms"], 4),
+    }
+    if "c64" in res and "c128" in res:
+        a, b = res["c64"], res["c128"]
+        d = float(np.abs(a["rho"] - b["rho"]).max())
+        drift = float(np.abs(np.trace(a["rho"], axis1=1, axis2=2) - np.trace(b["rho"], axis1=1, axis2=2)).max())
+        out["fp32_tier"] = {
+            "value": round(a["gelem_s"], 3), "unit": "Gelem/s", "ms_per_step": round(a["ms_per_step"], 4),
+            "roofline": {"bound": "hbm", "achieved": round(a["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(a["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                         "kernel_ms": round(a["kernel_ms"], 4)},
+            "max_abs_drho_vs_f64": d, "trace_drift_vs_f64": drift,
+        }
+    if not args.no_cpu_baseline:
+        log("bench: cpu_baseline (oracle on the host)")
+        cb = cpu_baseline(w.with_(dtype="c128"))
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["value"] = round(cb["value"], 5)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

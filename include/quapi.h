@@ -1,0 +1,190 @@
+/*
+ * quapi.h -- C ABI of the MI355X (gfx950) QUAPI tensor-propagator library.
+ *
+ * The library propagates the reduced density matrix of an open quantum
+ * system in the Feynman-Vernon model (Dattani 2012, Sec. II "Setting"):
+ * given the system coordinate vector s, the system Hamiltonian H, the
+ * spectral density J(omega) of the harmonic bath and its temperature, the
+ * initial density matrix rho(0), and the convergence parameters
+ * {dt, Delta k_max}, it returns rho(t_k) at the grid times t_k = k dt
+ * (Sec. II, last paragraph; Sec. IV 'allPoints' / 'justFinalPoint').
+ *
+ * Method (Sec. II, exact path-sum equation with the discretized influence
+ * functional and the eta_kk' definitions, evaluated by the tensor-propagator
+ * scheme named in the Introduction):
+ *   setup   G(t) = double time integral of the bath response alpha(t), by
+ *           FP64 quadrature over J on the GPU; the eta classes as second
+ *           differences of G; U = exp(-i H dt); K = U (x) conj(U); the
+ *           influence-factor tables.  All on the device, in FP64.
+ *   step    the augmented density tensor over the last Delta k_max path
+ *           points (N^L complex entries, N = M^2, L = Delta k_max) is
+ *           multiplied by K and the influence factors of the new point and
+ *           its oldest index is summed out; rho(t_n) is extracted on
+ *           selected steps from the same pass.
+ *
+ * Units: hbar = k_B = 1; kT is in the energy units of H, time in their inverse.
+ *
+ * Conventions common to every call:
+ *   - Complex numbers are interleaved (re, im) doubles.  Matrices are M x M,
+ *     row-major, in the basis of the coupling coordinate ordered as s.
+ *   - Liouville index o = a*M + b for the path pair (s+ = s[a], s- = s[b]);
+ *     rho(t)[a][b] is element o of an output block of M*M complex values.
+ *   - A call never throws or aborts across the ABI; it returns a status and
+ *     leaves a message for quapi_last_error().
+ *   - One context is used by one thread at a time (QUAPI_ERR_STATE when a
+ *     second call overlaps).  Distinct contexts may run concurrently, each on
+ *     its own HIP stream.
+ */
+#ifndef QUAPI_H
+#define QUAPI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct quapi_ctx quapi_ctx;   /* opaque; owned by the library */
+
+typedef enum {
+    QUAPI_OK = 0,
+    QUAPI_ERR_INVALID = 1,   /* malformed argument (message says which) */
+    QUAPI_ERR_NOMEM = 2,     /* the working set does not fit in free device memory */
+    QUAPI_ERR_DEVICE = 3,    /* HIP runtime / kernel launch failure, or no device */
+    QUAPI_ERR_STATE = 4      /* overlapping use of one context */
+} quapi_status;
+
+typedef enum {
+    QUAPI_C128 = 0,          /* tensor stored and contracted in complex128 */
+    QUAPI_C64 = 1            /* tensor in complex64, FP32 products; tables, eta, G and
+                                the rho reduction stay FP64 */
+} quapi_dtype;
+
+typedef enum {
+    QUAPI_BATH_OHMIC = 0,    /* J(w) = (pi/2) xi w exp(-w / omega_c) */
+    QUAPI_BATH_TABLE = 1     /* J tabulated at n_tab nodes, piecewise linear in w through
+                                the anchor J(0) = 0, and zero beyond the last node */
+} quapi_bath_kind;
+
+/* Spectral density of the bath (Sec. II, spectral-distribution equation). */
+typedef struct {
+    int kind;                 /* quapi_bath_kind */
+    double xi, omega_c;       /* OHMIC: xi >= 0, omega_c > 0 */
+    const double *omega;      /* TABLE: n_tab nodes, strictly increasing, omega[0] > 0 */
+    const double *J;          /* TABLE: J(omega[i]) >= 0 */
+    int n_tab;                /* TABLE: >= 1, <= 1,000,000 */
+} quapi_bath;
+
+/* The problem statement (Sec. II, last paragraph).  Every pointer is read
+ * during quapi_create only; the caller keeps ownership. */
+typedef struct {
+    int M;                    /* system dimension, 1 <= M <= 4 */
+    const double *s;          /* M coupling-coordinate eigenvalues (the basis order) */
+    const double *H;          /* M*M complex, Hermitian (tolerance 1e-12 of max |H_ij|) */
+    const double *rho0;       /* M*M complex initial density matrix */
+    quapi_bath bath;
+    double kT;                /* >= 0; kT = 0 takes coth(w / 2kT) = 1 */
+    double dt;                /* > 0 */
+    int dk_max;               /* memory length L = Delta k_max, 1 <= L <= 30 */
+    int dtype;                /* quapi_dtype */
+} quapi_params;
+
+/* Device bytes that quapi_create needs for these parameters (the two
+ * ping-pong tensors of N^L entries dominate; the rest is tables and
+ * reduction scratch of a few MB at most).  Validates the parameters; needs
+ * no GPU.  INVALID on malformed parameters or size overflow. */
+quapi_status quapi_footprint(const quapi_params *p, size_t *device_bytes);
+
+/* The paper's primary memory cost (primary-memory-cost equation, Sec. II):
+ * 64 * M^(2 (dk_max + 1)) bytes, i.e. four complex128 arrays of
+ * M^(2 (dk_max + 1)) entries, which the paper's program stores.  This library
+ * stores two arrays of M^(2 dk_max) entries instead.  Returns 0 on overflow
+ * or bad arguments.  Needs no GPU. */
+size_t quapi_paper_pmc_bytes(int M, int dk_max);
+
+/* Create a propagation context and run the whole setup on the device:
+ * quadrature of G(t) at t = j dt/2 (j = 0 .. 2L+2), the eta classes, U, K,
+ * the influence tables, and the initial tensor.
+ *   hip_stream  hipStream_t to run on (borrowed; must outlive the context),
+ *               or NULL for a stream owned by the context.
+ *   workspace   device memory of ws_bytes >= quapi_footprint() bytes
+ *               (borrowed, e.g. a torch tensor's data_ptr; must outlive the
+ *               context and be 256-byte aligned), or NULL for the library to
+ *               allocate.  With NULL, NOMEM is returned when the footprint
+ *               exceeds free device memory (or the QUAPI_FAKE_HBM_BYTES
+ *               environment cap), the paper's "did not fit on the GPU".
+ *   out         receives the context (NULL on failure).
+ * Blocks until the setup has finished on the device. */
+quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspace,
+                          size_t ws_bytes, quapi_ctx **out);
+
+/* Advance the context by n_steps >= 0 time steps, from its current global
+ * step c to c + n_steps, and return rho at the selected global steps.
+ *   sel      strictly increasing global step indices k with c < k <= c + n_steps,
+ *            or k == 0 (rho(t_0) = rho0); NULL selects every k in (c, c + n_steps]
+ *            (the paper's 'allPoints'); {c + n_steps} is 'justFinalPoint'.
+ *   n_sel    length of sel (ignored when sel is NULL).
+ *   rho_out  host buffer of n_out * M*M complex (n_out = n_sel, or n_steps when
+ *            sel is NULL), written in selection order; caller-owned.
+ * Blocking: returns when the results are on the host. */
+quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
+                             double *rho_out);
+
+/* As quapi_propagate, but enqueues the work on the context's stream and
+ * returns at once; rho_out_dev is device memory of n_out * M*M complex128
+ * (caller-owned; valid once the stream has reached this point). */
+quapi_status quapi_propagate_async(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
+                                   void *rho_out_dev);
+
+/* Global step index the context has reached (0 after create). */
+quapi_status quapi_step_count(const quapi_ctx *ctx, int *step);
+
+/* Test hooks: copy setup results to host (complex values interleaved).
+ *   what = QUAPI_SETUP_G     G(j dt/2), j = 0 .. 2L+2                  (2L+3 values)
+ *          QUAPI_SETUP_ETA   eta classes: self interior, self end, then
+ *                            lag[1..L], init[1..L], fin[1..L], fin_init[1..L] (4L+2)
+ *          QUAPI_SETUP_U     exp(-i H dt), M x M row-major             (M*M)
+ *          QUAPI_SETUP_K     K[o', o] = U[a',a] conj(U[b',b]), N x N      (N*N)
+ *   out_len  number of doubles available at out (INVALID when too small). */
+enum { QUAPI_SETUP_G = 0, QUAPI_SETUP_ETA = 1, QUAPI_SETUP_U = 2, QUAPI_SETUP_K = 3 };
+quapi_status quapi_get_setup(const quapi_ctx *ctx, int what, double *out, size_t out_len);
+
+/* Test hook: copy entries [first, first + count) of the current augmented
+ * tensor to host as complex128 (widened from complex64 for QUAPI_C64).
+ * Layout after global step c >= 1: the tensor holds path points
+ * max(0, c-L+1) .. c, flat index sum_j o_{p0 + j} N^j (oldest point fastest),
+ * N^min(c+1, L) entries.  INVALID when the range exceeds the tensor. */
+quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count, double *out);
+
+/* Number of entries in the current tensor (N^min(c+1, L)). */
+quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries);
+
+/* Kernel timing with HIP events on the context's stream. */
+typedef struct {
+    double setup_ms;          /* device time of the setup kernels in quapi_create */
+    double step_ms;           /* summed duration of full-window step kernels (n >= L) */
+    long long step_launches;  /* number of those launches */
+    double grow_ms;           /* summed duration of growth-step kernels (n < L) */
+    long long grow_launches;
+    double finalize_ms;       /* summed duration of rho finalize kernels */
+    long long finalize_launches;
+} quapi_timing;
+
+/* enable != 0 records an event pair around every propagation kernel launch. */
+quapi_status quapi_set_timing(quapi_ctx *ctx, int enable);
+/* Waits for the stream, returns the accumulated timings, and resets them
+ * (setup_ms is kept). */
+quapi_status quapi_get_timing(quapi_ctx *ctx, quapi_timing *out);
+
+/* Release the context and everything it allocated (not a caller workspace). */
+quapi_status quapi_destroy(quapi_ctx *ctx);
+
+/* Message of the last failed call on ctx, or of the calling thread's last
+ * failed call when ctx is NULL.  Valid until the next call. */
+const char *quapi_last_error(const quapi_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QUAPI_H */

@@ -1,0 +1,819 @@
+// Host runtime of the QUAPI library: parameter validation, footprint,
+// quadrature planning, workspace layout, step planning, and the C ABI
+// declared in include/quapi.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "quapi.h"
+#include "quapi_internal.h"
+
+using namespace quapi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr size_t kAlign = 256;
+constexpr int kRhoStage = 1024;          // rho slots of the blocking-call staging buffer
+constexpr double kOhmicCutoffFactor = 46.0;  // exp(-46) ~ 1e-20 of the integrand left out
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool checked_pow(size_t base, int e, size_t *out) {
+    size_t r = 1;
+    for (int i = 0; i < e; ++i) {
+        if (base != 0 && r > std::numeric_limits<size_t>::max() / base) return false;
+        r *= base;
+    }
+    *out = r;
+    return true;
+}
+
+long long ipow_ll(int b, int e) {
+    long long r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+// ---------------------------------------------------------------- planning
+// Digit split of the m index of a step (see step_kernel): d_lo digits per
+// thread, d_mid swept by the block loop, the rest indexed by the block.
+struct DigitSplit {
+    int d_lo, d_mid, R, Q, grid;
+};
+
+DigitSplit split_digits(int N, int n_digits) {
+    int d_lo_max = 0, d_mid_target = 0;
+    switch (N) {
+    case 4: d_lo_max = 4; d_mid_target = 3; break;    // R = 256 = block, Q <= 64
+    case 9: d_lo_max = 2; d_mid_target = 2; break;    // R = 81 (243 threads active), Q <= 81
+    case 16: d_lo_max = 1; d_mid_target = 1; break;   // R = 16, Q <= 16 (LDS budget)
+    default: break;                                   // N = 1: a single entry
+    }
+    DigitSplit s;
+    s.d_lo = std::min(d_lo_max, n_digits);
+    const int avail = n_digits - s.d_lo;
+    s.d_mid = std::min(d_mid_target, avail);
+    // keep at least ~1024 blocks in flight when the tensor allows it
+    while (s.d_mid > 0 && ipow_ll(N, avail - s.d_mid) < 1024) --s.d_mid;
+    s.R = (int)ipow_ll(N, s.d_lo);
+    s.Q = (int)ipow_ll(N, s.d_mid);
+    s.grid = (int)ipow_ll(N, avail - s.d_mid);
+    return s;
+}
+
+int max_grid(int N, int L) {
+    int g = 1;
+    for (int nd = 0; nd <= L - 1; ++nd) g = std::max(g, split_digits(N, nd).grid);
+    return g;
+}
+
+// Gauss-Legendre rule on [-1, 1]: nodes are the roots of P_n found by Newton's
+// method from the Chebyshev-like initial guesses cos(pi (i + 3/4) / (n + 1/2)),
+// with P_n from the three-term recurrence k P_k = (2k-1) x P_{k-1} - (k-1) P_{k-2},
+// P_n'(x) = n (x P_n - P_{n-1}) / (x^2 - 1), and weights 2 / ((1 - x^2) P_n'(x)^2).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Panels of the w-quadrature of G(t) for t <= t_max.  Each Gauss-Legendre
+// panel spans at most: one radian of w t_max (oscillation); the distance
+// max(2 pi kT, w) to the nearest pole of coth(w / 2kT) at w = 2 pi kT i
+// (analyticity); omega_c for the Ohmic exp(-w / omega_c) (scale).  Panels
+// never straddle a table node, where J has a kink.
+void plan_panels(const quapi_params &p, double t_max, std::vector<double> &pa,
+                 std::vector<double> &ph, std::vector<int> &pseg) {
+    pa.clear();
+    ph.clear();
+    pseg.clear();
+    const double inf = std::numeric_limits<double>::infinity();
+    const double h_osc = t_max > 0.0 ? 1.0 / t_max : inf;
+    const double d_pole = p.kT > 0.0 ? 2.0 * M_PI * p.kT : inf;
+    std::vector<double> edges{0.0};
+    double h_cut = inf;
+    if (p.bath.kind == QUAPI_BATH_OHMIC) {
+        edges.push_back(kOhmicCutoffFactor * p.bath.omega_c);
+        h_cut = p.bath.omega_c;
+    } else {
+        for (int i = 0; i < p.bath.n_tab; ++i) edges.push_back(p.bath.omega[i]);
+    }
+    for (size_t k = 0; k + 1 < edges.size(); ++k) {
+        const double lo = edges[k], hi = edges[k + 1];
+        double x = lo;
+        while (x < hi) {
+            const double hmax = std::min(std::min(h_osc, h_cut), std::max(d_pole, x));
+            const bool last = hi - x <= hmax * (1.0 + 1e-12);   // no sliver panels
+            const double hh = last ? hi - x : hmax;
+            pa.push_back(x);
+            ph.push_back(hh);
+            pseg.push_back(p.bath.kind == QUAPI_BATH_OHMIC ? -1 : (int)k);
+            x = last ? hi : x + hh;
+        }
+    }
+}
+
+// ------------------------------------------------------------- validation
+std::string validate(const quapi_params *p) {
+    char buf[256];
+    if (!p) return "params is NULL";
+    if (p->M < 1 || p->M > kMaxM) {
+        snprintf(buf, sizeof buf, "M = %d outside 1..%d", p->M, kMaxM);
+        return buf;
+    }
+    if (!p->s || !p->H || !p->rho0) return "s, H and rho0 must be non-NULL";
+    const int M = p->M;
+    for (int i = 0; i < M; ++i)
+        if (!std::isfinite(p->s[i])) return "s has a non-finite entry";
+    double hmax = 0.0;
+    for (int i = 0; i < 2 * M * M; ++i) {
+        if (!std::isfinite(p->H[i])) return "H has a non-finite entry";
+        if (!std::isfinite(p->rho0[i])) return "rho0 has a non-finite entry";
+        hmax = std::max(hmax, std::fabs(p->H[i]));
+    }
+    for (int a = 0; a < M; ++a)
+        for (int b = 0; b < M; ++b) {
+            const double re = p->H[2 * (a * M + b)], im = p->H[2 * (a * M + b) + 1];
+            const double re2 = p->H[2 * (b * M + a)], im2 = p->H[2 * (b * M + a) + 1];
+            if (std::fabs(re - re2) > 1e-12 * hmax || std::fabs(im + im2) > 1e-12 * hmax)
+                return "H is not Hermitian";
+        }
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return "dt must be finite and > 0";
+    if (p->dk_max < 1 || p->dk_max > kMaxL) {
+        snprintf(buf, sizeof buf, "dk_max = %d outside 1..%d", p->dk_max, kMaxL);
+        return buf;
+    }
+    if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return "kT must be finite and >= 0";
+    if (p->dtype != QUAPI_C128 && p->dtype != QUAPI_C64) return "dtype must be QUAPI_C128 or QUAPI_C64";
+    const quapi_bath &b = p->bath;
+    if (b.kind == QUAPI_BATH_OHMIC) {
+        if (!(b.xi >= 0.0) || !std::isfinite(b.xi)) return "Ohmic xi must be finite and >= 0";
+        if (!(b.omega_c > 0.0) || !std::isfinite(b.omega_c)) return "Ohmic omega_c must be finite and > 0";
+    } else if (b.kind == QUAPI_BATH_TABLE) {
+        if (b.n_tab < 1 || b.n_tab > 1000000) return "table n_tab must be in 1..1000000";
+        if (!b.omega || !b.J) return "table omega and J must be non-NULL";
+        for (int i = 0; i < b.n_tab; ++i) {
+            if (!std::isfinite(b.omega[i]) || !std::isfinite(b.J[i])) return "table has a non-finite entry";
+            if (b.J[i] < 0.0) return "table J must be >= 0";
+            if (i == 0 ? !(b.omega[0] > 0.0) : !(b.omega[i] > b.omega[i - 1]))
+                return "table omega must be > 0 and strictly increasing";
+        }
+    } else {
+        return "bath.kind must be QUAPI_BATH_OHMIC or QUAPI_BATH_TABLE";
+    }
+    size_t entries;
+    if (!checked_pow((size_t)M * M, p->dk_max, &entries) || entries > (size_t)1 << 40)
+        return "N^dk_max is too large";
+    return "";
+}
+
+// ------------------------------------------------------------------ layout
+struct Layout {
+    size_t a_bytes;                  // one tensor buffer
+    size_t off_a0, off_a1, off_bank, off_g, off_eta, off_U, off_s, off_H, off_rho0;
+    size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
+    size_t total;
+    int n_panels, n_tables, partial_blocks;
+};
+
+Layout make_layout(const quapi_params &p, int n_panels) {
+    Layout l{};
+    const int M = p.M, N = M * M, L = p.dk_max;
+    size_t entries = 1;
+    checked_pow((size_t)N, L, &entries);
+    const size_t cs = p.dtype == QUAPI_C64 ? 8 : 16;
+    l.n_panels = n_panels;
+    l.n_tables = BankLayout{L}.count();
+    l.partial_blocks = max_grid(N, L);
+    l.a_bytes = entries * cs;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    l.off_a0 = take(l.a_bytes);
+    l.off_a1 = take(l.a_bytes);
+    l.off_bank = take((size_t)l.n_tables * N * N * 16);
+    l.off_g = take((size_t)(2 * L + 3) * 16);
+    l.off_eta = take((size_t)(4 * L + 2) * 16);
+    l.off_U = take((size_t)M * M * 16);
+    l.off_s = take((size_t)M * 8);
+    l.off_H = take((size_t)M * M * 16);
+    l.off_rho0 = take((size_t)N * 16);
+    l.off_pa = take((size_t)n_panels * 8);
+    l.off_ph = take((size_t)n_panels * 8);
+    l.off_pseg = take((size_t)n_panels * 4);
+    const int nt = p.bath.kind == QUAPI_BATH_TABLE ? p.bath.n_tab : 1;
+    l.off_tw = take((size_t)nt * 8);
+    l.off_tJ = take((size_t)nt * 8);
+    l.off_glx = take(kGL * 8);
+    l.off_glw = take(kGL * 8);
+    l.off_partials = take((size_t)l.partial_blocks * N * 16);
+    l.off_stage = take((size_t)kRhoStage * N * 16);
+    l.total = off;
+    return l;
+}
+
+int count_panels(const quapi_params &p) {
+    std::vector<double> a, h;
+    std::vector<int> s;
+    plan_panels(p, (p.dk_max + 1) * p.dt, a, h, s);
+    return (int)a.size();
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- context
+struct quapi_ctx {
+    int M = 0, N = 0, L = 0;
+    bool c64 = false;
+    double dt = 0.0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *ws = nullptr;
+    bool own_ws = false;
+    Layout lay{};
+    void *A[2] = {nullptr, nullptr};
+    int cur = 0;                  // A[cur] holds the tensor after global step `step`
+    int step = 0;
+    double2 *bank = nullptr, *g = nullptr, *eta = nullptr, *U = nullptr, *rho0_d = nullptr;
+    double2 *partials = nullptr, *stage = nullptr;
+    std::vector<double> rho0_h;
+    // host copies of uploaded inputs (kept alive until the uploads complete)
+    std::vector<double> s_h, H_h, pa_h, ph_h, tw_h, tJ_h, glx_h, glw_h;
+    std::vector<int> pseg_h;
+    std::string err;
+    std::atomic<int> busy{0};
+    // timing
+    bool timing = false;
+    double setup_ms = 0.0;
+    struct Rec { int kind; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    double acc_ms[3] = {0, 0, 0};
+    long long acc_n[3] = {0, 0, 0};
+};
+
+namespace {
+
+quapi_status fail(quapi_ctx *ctx, quapi_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+#define HIP_TRY(ctx, call)                                                                    \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ctx, QUAPI_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+struct BusyGuard {
+    quapi_ctx *c;
+    bool ok;
+    explicit BusyGuard(quapi_ctx *cx) : c(cx) {
+        int z = 0;
+        ok = c->busy.compare_exchange_strong(z, 1);
+    }
+    ~BusyGuard() {
+        if (ok) c->busy.store(0);
+    }
+};
+
+hipEvent_t take_event(quapi_ctx *c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Build the step arguments for global step n (1-based).
+struct StepPlan {
+    StepArgs args;
+    DigitSplit split;
+    bool grow;
+};
+
+StepPlan plan_step(const quapi_ctx *c, int n) {
+    const int N = c->N, L = c->L;
+    const BankLayout B{L};
+    StepPlan sp{};
+    StepArgs &a = sp.args;
+    sp.grow = n < L;
+    a.n_digits = sp.grow ? n : L - 1;
+    a.m_count = ipow_ll(N, a.n_digits);
+    sp.split = split_digits(N, a.n_digits);
+    a.d_lo = sp.split.d_lo;
+    a.d_mid = sp.split.d_mid;
+    a.R = sp.split.R;
+    a.Q = sp.split.Q;
+    if (sp.grow) {
+        // digits are points 0 .. n-1; point 0 couples through the initial-point classes
+        for (int j = 0; j < n; ++j) {
+            if (j == 0) {
+                a.tab[j] = (int16_t)(n == 1 ? B.k_init1() : B.init(n));
+                a.tabf[j] = (int16_t)(n == 1 ? B.k_fin_init1() : B.fin_init(n));
+            } else {
+                const int lag = n - j;
+                a.tab[j] = (int16_t)(lag == 1 ? B.k_lag1() : B.lag(lag));
+                a.tabf[j] = (int16_t)(lag == 1 ? B.k_fin1() : B.fin(lag));
+            }
+        }
+        a.old_tab = B.self_int();
+        a.oldf_tab = B.self_end();
+    } else {
+        // digits are points n-L+1 .. n-1 (lags L-1 .. 1); the oldest point n-L is summed
+        for (int j = 0; j < L - 1; ++j) {
+            const int lag = L - 1 - j;
+            a.tab[j] = (int16_t)(lag == 1 ? B.k_lag1() : B.lag(lag));
+            a.tabf[j] = (int16_t)(lag == 1 ? B.k_fin1() : B.fin(lag));
+        }
+        a.old_tab = n == L ? B.old_first() : B.old_main();
+        a.oldf_tab = n == L ? B.oldf_first() : B.oldf_main();
+    }
+    a.bank = c->bank;
+    a.partials = c->partials;
+    return sp;
+}
+
+// Enqueue step n (1-based) and, if out != NULL, rho(t_n) into out[0..N).
+quapi_status enqueue_step(quapi_ctx *c, int n, double2 *out) {
+    StepPlan sp = plan_step(c, n);
+    StepArgs &a = sp.args;
+    const size_t cap = c->lay.a_bytes / (c->c64 ? 8 : 16);
+    const size_t in_entries = (size_t)a.m_count * (sp.grow ? 1 : c->N);
+    const size_t out_entries = (size_t)a.m_count * c->N;
+    const bool rho = out != nullptr;
+    const size_t lds = step_lds_bytes(c->N, c->c64, rho, sp.grow, a.R, a.Q);
+    // host-side launch checks: the grid must tile m exactly and stay in the buffers
+    if ((long long)sp.split.grid * a.R * a.Q != a.m_count || in_entries > cap || out_entries > cap ||
+        sp.split.grid > c->lay.partial_blocks || lds > (size_t)kLdsLimit || kBlock % a.R != 0)
+        return fail(c, QUAPI_ERR_DEVICE, "internal launch check failed at step %d", n);
+    a.a_in = c->A[c->cur];
+    a.a_out = c->A[1 - c->cur];
+    const int kind = sp.grow ? 1 : 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        e0 = take_event(c);
+        e1 = take_event(c);
+        if (e0) (void)hipEventRecord(e0, c->stream);
+    }
+    hipError_t e = launch_step(c->N, c->c64, rho, sp.grow, a, sp.split.grid, c->stream);
+    if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "step kernel launch: %s", hipGetErrorString(e));
+    if (c->timing && e0 && e1) {
+        (void)hipEventRecord(e1, c->stream);
+        c->recs.push_back({kind, e0, e1});
+    }
+    if (rho) {
+        hipEvent_t f0 = nullptr, f1 = nullptr;
+        if (c->timing) {
+            f0 = take_event(c);
+            f1 = take_event(c);
+            if (f0) (void)hipEventRecord(f0, c->stream);
+        }
+        e = launch_rho_finalize(c->N, c->partials, sp.split.grid, out, c->stream);
+        if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "rho finalize launch: %s", hipGetErrorString(e));
+        if (c->timing && f0 && f1) {
+            (void)hipEventRecord(f1, c->stream);
+            c->recs.push_back({2, f0, f1});
+        }
+    }
+    c->cur = 1 - c->cur;
+    c->step = n;
+    return QUAPI_OK;
+}
+
+quapi_status check_selection(quapi_ctx *c, int n_steps, const int *sel, int n_sel, int *n_out) {
+    if (n_steps < 0) return fail(c, QUAPI_ERR_INVALID, "n_steps must be >= 0");
+    if ((long long)c->step + n_steps > std::numeric_limits<int>::max())
+        return fail(c, QUAPI_ERR_INVALID, "step counter would overflow");
+    if (!sel) {
+        *n_out = n_steps;
+        return QUAPI_OK;
+    }
+    if (n_sel < 0) return fail(c, QUAPI_ERR_INVALID, "n_sel must be >= 0");
+    int prev = -1;
+    for (int i = 0; i < n_sel; ++i) {
+        const int k = sel[i];
+        if (k <= prev) return fail(c, QUAPI_ERR_INVALID, "sel must be strictly increasing");
+        if (!(k == 0 || (k > c->step && k <= c->step + n_steps)))
+            return fail(c, QUAPI_ERR_INVALID, "sel[%d] = %d is neither 0 nor in (%d, %d]", i, k, c->step,
+                        c->step + n_steps);
+        prev = k;
+    }
+    *n_out = n_sel;
+    return QUAPI_OK;
+}
+
+// Shared driver of the blocking and asynchronous calls.  dev_out: device
+// output of n_out slots (async), or NULL to stage and copy into host_out.
+quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel, double2 *dev_out,
+                            double *host_out) {
+    int n_out = 0;
+    quapi_status st = check_selection(c, n_steps, sel, n_sel, &n_out);
+    if (st != QUAPI_OK) return st;
+    if (n_out > 0 && !dev_out && !host_out) return fail(c, QUAPI_ERR_INVALID, "rho_out is NULL");
+    const int N = c->N;
+    int si = 0;          // next selection entry
+    int written = 0;     // outputs delivered so far
+    int staged = 0;      // outputs in the staging buffer (blocking call)
+    auto flush = [&]() -> quapi_status {
+        if (!staged) return QUAPI_OK;
+        HIP_TRY(c, hipMemcpyAsync(host_out + (size_t)2 * N * (written - staged), c->stage,
+                                  (size_t)staged * N * 16, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        staged = 0;
+        return QUAPI_OK;
+    };
+    if (sel && si < n_sel && sel[si] == 0) {  // rho(t_0) = rho0
+        if (dev_out)
+            HIP_TRY(c, hipMemcpyAsync(dev_out, c->rho0_d, (size_t)N * 16, hipMemcpyDeviceToDevice, c->stream));
+        else
+            std::memcpy(host_out, c->rho0_h.data(), (size_t)N * 16);
+        ++si;
+        ++written;
+    }
+    const int first = c->step + 1, last = c->step + n_steps;
+    for (int n = first; n <= last; ++n) {
+        const bool selected = !sel || (si < n_sel && sel[si] == n);
+        double2 *slot = nullptr;
+        if (selected) slot = dev_out ? dev_out + (size_t)written * N : c->stage + (size_t)staged * N;
+        st = enqueue_step(c, n, slot);
+        if (st != QUAPI_OK) return st;
+        if (selected) {
+            if (sel) ++si;
+            ++written;
+            if (!dev_out && ++staged == kRhoStage) {
+                st = flush();
+                if (st != QUAPI_OK) return st;
+            }
+        }
+    }
+    if (!dev_out) {
+        st = flush();
+        if (st != QUAPI_OK) return st;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return QUAPI_OK;
+}
+
+void release(quapi_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto &r : c->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+size_t quapi_paper_pmc_bytes(int M, int dk_max) {
+    if (M < 1 || dk_max < 0) return 0;
+    size_t e;
+    if (!checked_pow((size_t)M, 2 * (dk_max + 1), &e)) return 0;
+    if (e > std::numeric_limits<size_t>::max() / 64) return 0;
+    return 64 * e;
+}
+
+quapi_status quapi_footprint(const quapi_params *p, size_t *device_bytes) {
+    const std::string msg = validate(p);
+    if (!msg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", msg.c_str());
+    if (!device_bytes) return fail(nullptr, QUAPI_ERR_INVALID, "device_bytes is NULL");
+    *device_bytes = make_layout(*p, count_panels(*p)).total;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspace, size_t ws_bytes,
+                          quapi_ctx **out) {
+    if (!out) return fail(nullptr, QUAPI_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    const std::string msg = validate(p);
+    if (!msg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", msg.c_str());
+    const int M = p->M, N = M * M, L = p->dk_max;
+    std::vector<double> pa, ph;
+    std::vector<int> pseg;
+    plan_panels(*p, (L + 1) * p->dt, pa, ph, pseg);
+    const Layout lay = make_layout(*p, (int)pa.size());
+    if (workspace) {
+        if (ws_bytes < lay.total)
+            return fail(nullptr, QUAPI_ERR_INVALID, "workspace of %zu bytes is smaller than the footprint %zu",
+                        ws_bytes, lay.total);
+        if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+            return fail(nullptr, QUAPI_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
+    } else if (const char *cap = std::getenv("QUAPI_FAKE_HBM_BYTES")) {
+        const unsigned long long capb = std::strtoull(cap, nullptr, 10);
+        if (lay.total > capb)
+            return fail(nullptr, QUAPI_ERR_NOMEM,
+                        "footprint %zu bytes exceeds the device memory cap %llu (did not fit on the GPU)",
+                        lay.total, capb);
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(nullptr, QUAPI_ERR_DEVICE, "no HIP device available");
+
+    quapi_ctx *c = new quapi_ctx();
+    c->M = M;
+    c->N = N;
+    c->L = L;
+    c->c64 = p->dtype == QUAPI_C64;
+    c->dt = p->dt;
+    c->lay = lay;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(nullptr, QUAPI_ERR_DEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    if (workspace) {
+        c->ws = (char *)workspace;
+    } else {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            release(c);
+            return fail(nullptr, QUAPI_ERR_DEVICE, "hipMemGetInfo failed");
+        }
+        if (lay.total > free_b) {
+            release(c);
+            return fail(nullptr, QUAPI_ERR_NOMEM,
+                        "footprint %zu bytes exceeds free device memory %zu (did not fit on the GPU)",
+                        lay.total, free_b);
+        }
+        if (hipMalloc((void **)&c->ws, lay.total) != hipSuccess) {
+            c->ws = nullptr;
+            release(c);
+            return fail(nullptr, QUAPI_ERR_NOMEM, "hipMalloc of %zu bytes failed", lay.total);
+        }
+        c->own_ws = true;
+    }
+    char *w = c->ws;
+    c->A[0] = w + lay.off_a0;
+    c->A[1] = w + lay.off_a1;
+    c->bank = (double2 *)(w + lay.off_bank);
+    c->g = (double2 *)(w + lay.off_g);
+    c->eta = (double2 *)(w + lay.off_eta);
+    c->U = (double2 *)(w + lay.off_U);
+    c->rho0_d = (double2 *)(w + lay.off_rho0);
+    c->partials = (double2 *)(w + lay.off_partials);
+    c->stage = (double2 *)(w + lay.off_stage);
+
+    c->s_h.assign(p->s, p->s + M);
+    c->H_h.assign(p->H, p->H + 2 * M * M);
+    c->rho0_h.assign(p->rho0, p->rho0 + 2 * N);
+    c->pa_h = std::move(pa);
+    c->ph_h = std::move(ph);
+    c->pseg_h = std::move(pseg);
+    if (p->bath.kind == QUAPI_BATH_TABLE) {
+        c->tw_h.assign(p->bath.omega, p->bath.omega + p->bath.n_tab);
+        c->tJ_h.assign(p->bath.J, p->bath.J + p->bath.n_tab);
+    } else {
+        c->tw_h.assign(1, 0.0);
+        c->tJ_h.assign(1, 0.0);
+    }
+    gauss_legendre(kGL, c->glx_h, c->glw_h);
+
+    auto up = [&](size_t off, const void *src, size_t bytes) {
+        return hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(lay.off_s, c->s_h.data(), (size_t)M * 8);
+    if (e == hipSuccess) e = up(lay.off_H, c->H_h.data(), (size_t)M * M * 16);
+    if (e == hipSuccess) e = up(lay.off_rho0, c->rho0_h.data(), (size_t)N * 16);
+    if (e == hipSuccess) e = up(lay.off_pa, c->pa_h.data(), c->pa_h.size() * 8);
+    if (e == hipSuccess) e = up(lay.off_ph, c->ph_h.data(), c->ph_h.size() * 8);
+    if (e == hipSuccess) e = up(lay.off_pseg, c->pseg_h.data(), c->pseg_h.size() * 4);
+    if (e == hipSuccess) e = up(lay.off_tw, c->tw_h.data(), c->tw_h.size() * 8);
+    if (e == hipSuccess) e = up(lay.off_tJ, c->tJ_h.data(), c->tJ_h.size() * 8);
+    if (e == hipSuccess) e = up(lay.off_glx, c->glx_h.data(), kGL * 8);
+    if (e == hipSuccess) e = up(lay.off_glw, c->glw_h.data(), kGL * 8);
+    if (e != hipSuccess) {
+        release(c);
+        return fail(nullptr, QUAPI_ERR_DEVICE, "input upload failed: %s", hipGetErrorString(e));
+    }
+
+    hipEvent_t s0 = nullptr, s1 = nullptr;
+    (void)hipEventCreate(&s0);
+    (void)hipEventCreate(&s1);
+    if (s0) (void)hipEventRecord(s0, c->stream);
+    QuadArgs qa{};
+    qa.kind = p->bath.kind;
+    qa.xi = p->bath.xi;
+    qa.omega_c = p->bath.omega_c;
+    qa.kT = p->kT;
+    qa.half_dt = 0.5 * p->dt;
+    qa.pa = (const double *)(w + lay.off_pa);
+    qa.ph = (const double *)(w + lay.off_ph);
+    qa.pseg = (const int *)(w + lay.off_pseg);
+    qa.n_panels = lay.n_panels;
+    qa.tw = (const double *)(w + lay.off_tw);
+    qa.tJ = (const double *)(w + lay.off_tJ);
+    qa.n_tab = p->bath.kind == QUAPI_BATH_TABLE ? p->bath.n_tab : 0;
+    qa.glx = (const double *)(w + lay.off_glx);
+    qa.glw = (const double *)(w + lay.off_glw);
+    e = launch_g_quad(qa, 2 * L + 3, c->g, c->stream);
+    TablesArgs ta{};
+    ta.M = M;
+    ta.L = L;
+    ta.dt = p->dt;
+    ta.s = (const double *)(w + lay.off_s);
+    ta.H = (const double2 *)(w + lay.off_H);
+    ta.g = c->g;
+    ta.U = c->U;
+    ta.eta = c->eta;
+    ta.bank = c->bank;
+    if (e == hipSuccess) e = launch_tables(ta, c->stream);
+    if (e == hipSuccess)
+        e = launch_init_tensor(N, c->c64, c->rho0_d, c->bank, BankLayout{L}.self_end(), c->A[0], c->stream);
+    if (s1) (void)hipEventRecord(s1, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        if (s0) (void)hipEventDestroy(s0);
+        if (s1) (void)hipEventDestroy(s1);
+        release(c);
+        return fail(nullptr, QUAPI_ERR_DEVICE, "setup failed: %s", hipGetErrorString(e));
+    }
+    float ms = 0.0f;
+    if (s0 && s1 && hipEventElapsedTime(&ms, s0, s1) == hipSuccess) c->setup_ms = ms;
+    if (s0) (void)hipEventDestroy(s0);
+    if (s1) (void)hipEventDestroy(s1);
+    c->cur = 0;
+    c->step = 0;
+    *out = c;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel, double *rho_out) {
+    if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
+    BusyGuard g(ctx);
+    if (!g.ok) return fail(ctx, QUAPI_ERR_STATE, "context is in use by another call");
+    return propagate_impl(ctx, n_steps, sel, n_sel, nullptr, rho_out);
+}
+
+quapi_status quapi_propagate_async(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
+                                   void *rho_out_dev) {
+    if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
+    BusyGuard g(ctx);
+    if (!g.ok) return fail(ctx, QUAPI_ERR_STATE, "context is in use by another call");
+    int n_out = 0;
+    quapi_status st = check_selection(ctx, n_steps, sel, n_sel, &n_out);
+    if (st != QUAPI_OK) return st;
+    if (n_out > 0 && !rho_out_dev) return fail(ctx, QUAPI_ERR_INVALID, "rho_out_dev is NULL");
+    return propagate_impl(ctx, n_steps, sel, n_sel, (double2 *)rho_out_dev, nullptr);
+}
+
+quapi_status quapi_step_count(const quapi_ctx *ctx, int *step) {
+    if (!ctx || !step) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    *step = ctx->step;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_get_setup(const quapi_ctx *ctx, int what, double *out, size_t out_len) {
+    if (!ctx || !out) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    quapi_ctx *c = const_cast<quapi_ctx *>(ctx);
+    const void *src = nullptr;
+    size_t n = 0;
+    switch (what) {
+    case QUAPI_SETUP_G: src = c->g; n = 2 * c->L + 3; break;
+    case QUAPI_SETUP_ETA: src = c->eta; n = 4 * c->L + 2; break;
+    case QUAPI_SETUP_U: src = c->U; n = (size_t)c->M * c->M; break;
+    case QUAPI_SETUP_K: src = c->bank + (size_t)BankLayout{c->L}.K() * c->N * c->N; n = (size_t)c->N * c->N; break;
+    default: return fail(c, QUAPI_ERR_INVALID, "unknown setup item %d", what);
+    }
+    if (out_len < 2 * n) return fail(c, QUAPI_ERR_INVALID, "out_len %zu < %zu", out_len, 2 * n);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(out, src, n * 16, hipMemcpyDeviceToHost));
+    return QUAPI_OK;
+}
+
+quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries) {
+    if (!ctx || !entries) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    const int axes = std::min(ctx->step + 1, ctx->L);
+    *entries = (size_t)ipow_ll(ctx->N, axes);
+    return QUAPI_OK;
+}
+
+quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count, double *out) {
+    if (!ctx || (!out && count)) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    quapi_ctx *c = const_cast<quapi_ctx *>(ctx);
+    size_t entries = 0;
+    quapi_tensor_size(ctx, &entries);
+    if (first > entries || count > entries - first)
+        return fail(c, QUAPI_ERR_INVALID, "range [%zu, %zu) exceeds the tensor of %zu entries", first,
+                    first + count, entries);
+    if (!count) return QUAPI_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!c->c64) {
+        HIP_TRY(c, hipMemcpy(out, (const char *)c->A[c->cur] + first * 16, count * 16, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(2 * count);
+        HIP_TRY(c, hipMemcpy(tmp.data(), (const char *)c->A[c->cur] + first * 8, count * 8, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < 2 * count; ++i) out[i] = tmp[i];
+    }
+    return QUAPI_OK;
+}
+
+quapi_status quapi_set_timing(quapi_ctx *ctx, int enable) {
+    if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
+    ctx->timing = enable != 0;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_get_timing(quapi_ctx *ctx, quapi_timing *out) {
+    if (!ctx || !out) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &r : ctx->recs) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            ctx->acc_ms[r.kind] += ms;
+            ctx->acc_n[r.kind] += 1;
+        }
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    out->setup_ms = ctx->setup_ms;
+    out->step_ms = ctx->acc_ms[0];
+    out->step_launches = ctx->acc_n[0];
+    out->grow_ms = ctx->acc_ms[1];
+    out->grow_launches = ctx->acc_n[1];
+    out->finalize_ms = ctx->acc_ms[2];
+    out->finalize_launches = ctx->acc_n[2];
+    for (int k = 0; k < 3; ++k) {
+        ctx->acc_ms[k] = 0.0;
+        ctx->acc_n[k] = 0;
+    }
+    return QUAPI_OK;
+}
+
+quapi_status quapi_destroy(quapi_ctx *ctx) {
+    if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
+    if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context is in use by another call");
+    release(ctx);
+    return QUAPI_OK;
+}
+
+const char *quapi_last_error(const quapi_ctx *ctx) {
+    if (ctx) return ctx->err.c_str();
+    return g_last_error.c_str();
+}
+
+}  // extern "C"

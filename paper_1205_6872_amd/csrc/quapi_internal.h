@@ -1,0 +1,89 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace quapi {
+
+constexpr int kMaxM = 4;
+constexpr int kMaxN = kMaxM * kMaxM;
+constexpr int kMaxL = 30;
+constexpr int kBlock = 256;              // threads per block of every propagation kernel
+constexpr int kGL = 16;                  // Gauss-Legendre nodes per quadrature panel
+constexpr int kLdsLimit = 64 * 1024;     // LDS bytes a step block may use
+
+// Influence/propagator table bank.  Every table is N x N complex128, row o
+// (later point) and column p (earlier point), stored at bank[t * N*N + o*N + p].
+struct BankLayout {
+    int L;
+    __host__ __device__ int K() const { return 0; }
+    __host__ __device__ int lag(int D) const { return D; }               // D = 1..L
+    __host__ __device__ int init(int k) const { return L + k; }          // k = 1..L
+    __host__ __device__ int fin(int D) const { return 2 * L + D; }       // D = 1..L
+    __host__ __device__ int fin_init(int n) const { return 3 * L + n; }  // n = 1..L
+    __host__ __device__ int self_int() const { return 4 * L + 1; }       // row o: F_self_interior(o)
+    __host__ __device__ int self_end() const { return 4 * L + 2; }       // row o: F_self_end(o)
+    __host__ __device__ int k_lag1() const { return 4 * L + 3; }         // K * F_lag[1]
+    __host__ __device__ int k_init1() const { return 4 * L + 4; }        // K * F_init[1]
+    __host__ __device__ int k_fin1() const { return 4 * L + 5; }         // K * F_fin[1]
+    __host__ __device__ int k_fin_init1() const { return 4 * L + 6; }    // K * F_fin_init[1]
+    // Oldest-point tables of a full-window step, with the new point's self
+    // factor folded in (and K too when L = 1, where the oldest point is n-1).
+    __host__ __device__ int old_main() const { return 4 * L + 7; }       // n > L, interior
+    __host__ __device__ int old_first() const { return 4 * L + 8; }      // n = L, oldest is point 0
+    __host__ __device__ int oldf_main() const { return 4 * L + 9; }      // n > L, final classes
+    __host__ __device__ int oldf_first() const { return 4 * L + 10; }    // n = L, final classes
+    __host__ __device__ int count() const { return 4 * L + 11; }
+};
+
+// One propagation step: A_out[m + m_count*o] = P(o,m) * sum_i Old[o][i] A_in[i + I*m].
+struct StepArgs {
+    const void *a_in;
+    void *a_out;
+    const double2 *bank;
+    double2 *partials;          // [gridDim.x][N] block partial sums of rho (with_rho)
+    long long m_count;          // N^n_digits
+    int n_digits;               // digits of m
+    int d_lo, d_mid;            // digits owned by the thread / swept by the block loop
+    int R, Q;                   // N^d_lo, N^d_mid
+    int old_tab, oldf_tab;      // bank indices of the oldest-point tables
+    int16_t tab[kMaxL];         // bank index of the interior table for digit j
+    int16_t tabf[kMaxL];        // bank index of the final-point table for digit j
+};
+
+struct QuadArgs {
+    int kind;                   // 0 Ohmic, 1 table
+    double xi, omega_c, kT, half_dt;
+    const double *pa, *ph;      // panel left ends and widths
+    const int *pseg;            // table segment of each panel (-1 for Ohmic)
+    int n_panels;
+    const double *tw, *tJ;      // table nodes and values
+    int n_tab;
+    const double *glx, *glw;    // Gauss-Legendre nodes/weights on [-1, 1]
+};
+
+struct TablesArgs {
+    int M, L;
+    double dt;
+    const double *s;
+    const double2 *H;
+    const double2 *g;           // G(j dt/2), j = 0..2L+2
+    double2 *U;                 // out: M x M
+    double2 *eta;               // out: 4L+2 classes
+    double2 *bank;              // out: BankLayout{L}.count() tables
+};
+
+// Kernel launchers (quapi_kernels.hip).  They return the launch status.
+hipError_t launch_g_quad(const QuadArgs &a, int n_t, double2 *g, hipStream_t st);
+hipError_t launch_tables(const TablesArgs &a, hipStream_t st);
+hipError_t launch_init_tensor(int N, bool c64, const double2 *rho0, const double2 *bank,
+                              int self_end_tab, void *a0, hipStream_t st);
+hipError_t launch_step(int N, bool c64, bool with_rho, bool grow, const StepArgs &a, int grid,
+                       hipStream_t st);
+hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *out,
+                               hipStream_t st);
+size_t step_lds_bytes(int N, bool c64, bool with_rho, bool grow, int R, int Q);
+
+}  // namespace quapi

@@ -1,0 +1,274 @@
+"""Thin Python binding of libquapi.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts NumPy inputs
+into the C structs of include/quapi.h, calls the C ABI through ctypes, and
+turns status codes into exceptions.  The functions keep the C names without
+the ``quapi_`` prefix (``create``, ``propagate``, ``propagate_async``,
+``footprint``, ...).  PyTorch is used only to hand over device memory and
+streams (``workspace=`` / ``stream=``).
+
+The library must be built (``python -m paper_1205_6872_amd.build`` or the
+repository's build step); importing this module on a machine without it
+raises ``ImportError`` -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+from typing import Optional, Sequence
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "_lib" / "libquapi.so"
+
+OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_STATE = 0, 1, 2, 3, 4
+C128, C64 = 0, 1
+BATH_OHMIC, BATH_TABLE = 0, 1
+SETUP_G, SETUP_ETA, SETUP_U, SETUP_K = 0, 1, 2, 3
+
+EXPORTED_SYMBOLS = (
+    "quapi_footprint", "quapi_paper_pmc_bytes", "quapi_create", "quapi_propagate",
+    "quapi_propagate_async", "quapi_step_count", "quapi_get_setup", "quapi_read_tensor",
+    "quapi_tensor_size", "quapi_set_timing", "quapi_get_timing", "quapi_destroy",
+    "quapi_last_error",
+)
+
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+class Bath(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("xi", ctypes.c_double), ("omega_c", ctypes.c_double),
+                ("omega", _DP), ("J", _DP), ("n_tab", ctypes.c_int)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("s", _DP), ("H", _DP), ("rho0", _DP), ("bath", Bath),
+                ("kT", ctypes.c_double), ("dt", ctypes.c_double), ("dk_max", ctypes.c_int),
+                ("dtype", ctypes.c_int)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("setup_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
+                ("step_launches", ctypes.c_longlong), ("grow_ms", ctypes.c_double),
+                ("grow_launches", ctypes.c_longlong), ("finalize_ms", ctypes.c_double),
+                ("finalize_launches", ctypes.c_longlong)]
+
+
+class QuapiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[status {status}] {message}")
+        self.status = status
+
+
+def load_library() -> ctypes.CDLL:
+    if not LIB_PATH.exists():
+        raise ImportError(f"{LIB_PATH} is not built; run the build step (hipcc for gfx950) first")
+    lib = ctypes.CDLL(str(LIB_PATH))
+    vp, sz, ip = ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int)
+    lib.quapi_footprint.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(sz)]
+    lib.quapi_paper_pmc_bytes.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.quapi_paper_pmc_bytes.restype = sz
+    lib.quapi_create.argtypes = [ctypes.POINTER(Params), vp, vp, sz, ctypes.POINTER(vp)]
+    lib.quapi_propagate.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, _DP]
+    lib.quapi_propagate_async.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, vp]
+    lib.quapi_step_count.argtypes = [vp, ip]
+    lib.quapi_get_setup.argtypes = [vp, ctypes.c_int, _DP, sz]
+    lib.quapi_read_tensor.argtypes = [vp, sz, sz, _DP]
+    lib.quapi_tensor_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.quapi_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.quapi_get_timing.argtypes = [vp, ctypes.POINTER(Timing)]
+    lib.quapi_destroy.argtypes = [vp]
+    lib.quapi_last_error.argtypes = [vp]
+    lib.quapi_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED_SYMBOLS:
+        if name not in ("quapi_paper_pmc_bytes", "quapi_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _check(status: int, ctx=None):
+    if status != OK:
+        msg = lib().quapi_last_error(ctx).decode(errors="replace")
+        raise QuapiError(status, msg)
+
+
+def _f64(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _c128_ri(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.complex128)).view(np.float64)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return a.ctypes.data_as(_DP) if a is not None else None
+
+
+class _ParamsHolder:
+    """Params struct plus the arrays it points into (kept alive together)."""
+
+    def __init__(self, M: int, s, H, rho0, kT: float, dt: float, L: int, dtype: str = "c128",
+                 bath_kind: str = "ohmic", xi: float = 0.0, omega_c: float = 1.0,
+                 omega_tab=None, J_tab=None):
+        self.s = _f64(s)
+        self.H = np.ascontiguousarray(_c128_ri(H))
+        self.rho0 = np.ascontiguousarray(_c128_ri(rho0))
+        self.omega = _f64(omega_tab) if omega_tab is not None else None
+        self.J = _f64(J_tab) if J_tab is not None else None
+        kind = {"ohmic": BATH_OHMIC, "table": BATH_TABLE}[bath_kind]
+        n_tab = int(len(self.omega)) if self.omega is not None else 0
+        bath = Bath(kind, float(xi), float(omega_c), _ptr(self.omega), _ptr(self.J), n_tab)
+        self.p = Params(int(M), _ptr(self.s), _ptr(self.H), _ptr(self.rho0), bath, float(kT), float(dt),
+                        int(L), {"c128": C128, "c64": C64}[dtype])
+
+    @classmethod
+    def from_workload(cls, w, **over):
+        kw = dict(M=w.M, s=w.s, H=w.H, rho0=w.rho0, kT=w.kT, dt=w.dt, L=w.L, dtype=w.dtype,
+                  bath_kind=w.bath_kind, xi=w.xi, omega_c=w.omega_c, omega_tab=w.omega_tab,
+                  J_tab=w.J_tab)
+        kw.update(over)
+        return cls(**kw)
+
+
+def params(**kw) -> _ParamsHolder:
+    return _ParamsHolder(**kw)
+
+
+def params_from(w, **over) -> _ParamsHolder:
+    return _ParamsHolder.from_workload(w, **over)
+
+
+def footprint(p: _ParamsHolder) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().quapi_footprint(ctypes.byref(p.p), ctypes.byref(out)))
+    return int(out.value)
+
+
+def paper_pmc_bytes(M: int, dk_max: int) -> int:
+    return int(lib().quapi_paper_pmc_bytes(int(M), int(dk_max)))
+
+
+class Context:
+    """A quapi_ctx.  Use ``create`` to make one."""
+
+    def __init__(self, handle: ctypes.c_void_p, M: int, L: int, keep=()):
+        self._h = handle
+        self.M = M
+        self.N = M * M
+        self.L = L
+        self._keep = keep          # workspace owner (e.g. a torch tensor) stays alive
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _live(self):
+        if not self._h:
+            raise QuapiError(ERR_STATE, "context destroyed")
+        return self._h
+
+    def propagate(self, n_steps: int, sel: Optional[Sequence[int]] = None) -> np.ndarray:
+        """Blocking: rho at the selected steps, shape (n_out, M, M) complex128."""
+        h = self._live()
+        if sel is None:
+            n_out, sel_arr, psel, n_sel = n_steps, None, None, 0
+        else:
+            sel_arr = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
+            n_out = n_sel = len(sel_arr)
+            psel = sel_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        out = np.zeros(2 * self.N * max(n_out, 1), dtype=np.float64)
+        _check(lib().quapi_propagate(h, int(n_steps), psel, n_sel, _ptr(out)), h)
+        return out.view(np.complex128)[: self.N * n_out].reshape(n_out, self.M, self.M)
+
+    def propagate_async(self, n_steps: int, sel: Optional[Sequence[int]], rho_out_dev: int) -> None:
+        """Enqueue on the context's stream; rho goes to device memory at rho_out_dev."""
+        h = self._live()
+        if sel is None:
+            psel, n_sel = None, 0
+        else:
+            sel_arr = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
+            n_sel = len(sel_arr)
+            psel = sel_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        _check(lib().quapi_propagate_async(h, int(n_steps), psel, n_sel, ctypes.c_void_p(rho_out_dev)), h)
+
+    def step_count(self) -> int:
+        v = ctypes.c_int(0)
+        _check(lib().quapi_step_count(self._live(), ctypes.byref(v)))
+        return int(v.value)
+
+    def get_setup(self, what: int) -> np.ndarray:
+        n = {SETUP_G: 2 * self.L + 3, SETUP_ETA: 4 * self.L + 2, SETUP_U: self.M * self.M,
+             SETUP_K: self.N * self.N}[what]
+        out = np.zeros(2 * n, dtype=np.float64)
+        h = self._live()
+        _check(lib().quapi_get_setup(h, int(what), _ptr(out), out.size), h)
+        return out.view(np.complex128).copy()
+
+    def tensor_size(self) -> int:
+        v = ctypes.c_size_t(0)
+        _check(lib().quapi_tensor_size(self._live(), ctypes.byref(v)))
+        return int(v.value)
+
+    def read_tensor(self, first: int, count: int) -> np.ndarray:
+        out = np.zeros(2 * max(count, 1), dtype=np.float64)
+        h = self._live()
+        _check(lib().quapi_read_tensor(h, int(first), int(count), _ptr(out)), h)
+        return out.view(np.complex128)[:count].copy()
+
+    def set_timing(self, enable: bool = True) -> None:
+        _check(lib().quapi_set_timing(self._live(), int(bool(enable))))
+
+    def get_timing(self) -> dict:
+        t = Timing()
+        h = self._live()
+        _check(lib().quapi_get_timing(h, ctypes.byref(t)), h)
+        return {k: getattr(t, k) for k, _ in Timing._fields_}
+
+    def destroy(self) -> None:
+        if self._h:
+            _check(lib().quapi_destroy(self._h))
+            self._h = None
+            self._keep = ()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().quapi_destroy(self._h)
+        except Exception:
+            pass
+
+
+def create(p: _ParamsHolder, stream: Optional[int] = None, workspace: Optional[int] = None,
+           ws_bytes: int = 0, keep=()) -> Context:
+    """quapi_create.  stream: a hipStream_t as int (e.g. torch.cuda.current_stream().cuda_stream);
+    workspace: device pointer of ws_bytes bytes (e.g. a torch tensor's data_ptr())."""
+    h = ctypes.c_void_p(None)
+    _check(lib().quapi_create(ctypes.byref(p.p), ctypes.c_void_p(stream) if stream else None,
+                              ctypes.c_void_p(workspace) if workspace else None, int(ws_bytes),
+                              ctypes.byref(h)))
+    return Context(h, p.p.M, p.p.dk_max, keep=keep)
+
+
+def create_in_torch(p: _ParamsHolder, stream=None, device: str = "cuda:0") -> Context:
+    """quapi_create with the workspace held by a torch uint8 tensor and a torch stream."""
+    import torch
+    nbytes = footprint(p)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    return create(p, stream=st.cuda_stream, workspace=ws.data_ptr(), ws_bytes=nbytes, keep=(ws, st))

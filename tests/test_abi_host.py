@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports
+every function include/quapi.h declares; the paper's primary memory cost
+column (Table 1) is reproduced; parameters are validated; the footprint
+follows the two-buffer layout; the memory cap yields NOMEM before any device
+call; create without a device fails cleanly."""
+import os
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from paper_1205_6872_amd import quapi as Q
+from paper_1205_6872_amd import workloads as W
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def test_library_exports_every_declared_symbol():
+    header = (ROOT / "include" / "quapi.h").read_text()
+    declared = set(re.findall(r"\b(quapi_[a-z_]+)\s*\(", header))
+    assert declared == set(Q.EXPORTED_SYMBOLS)
+    lib = Q.load_library()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _parse_golden():
+    rows = []
+    for line in (ROOT / "tests" / "golden" / "paper_table1_pmc.txt").read_text().splitlines():
+        if line.startswith("#") or not line.strip():
+            continue
+        dk, val, unit = line.split()
+        rows.append((int(dk), float(val), unit))
+    return rows
+
+
+def test_paper_table1_primary_memory_cost():
+    scale = {"KB": 1e3, "MB": 1e6, "GB": 1e9}
+    rows = _parse_golden()
+    assert len(rows) == 11
+    for dk, val, unit in rows:
+        b = Q.paper_pmc_bytes(2, dk)
+        assert b == 64 * 4 ** (dk + 1)
+        printed = b / scale[unit]
+        # the paper prints four significant digits
+        assert float(f"{printed:.4g}") == pytest.approx(val, rel=0, abs=0), (dk, printed, val)
+
+
+def _p(**over):
+    return Q.params_from(W.spin_boson_l7(), **over)
+
+
+def test_footprint_is_two_tensor_buffers_plus_small_tables():
+    for L, dtype, cs in [(7, "c128", 16), (12, "c64", 8), (15, "c128", 16)]:
+        fp = Q.footprint(_p(L=L, dtype=dtype))
+        two = 2 * 4 ** L * cs
+        assert two <= fp <= two + 8 * 2 ** 20
+    fp3 = Q.footprint(Q.params_from(W.three_site_l8()))
+    assert 2 * 9 ** 8 * 16 <= fp3 <= 2 * 9 ** 8 * 16 + 8 * 2 ** 20
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(M=5, s=np.zeros(5), H=np.eye(5), rho0=np.eye(5)), "M = 5"),
+    (dict(H=np.array([[0, 1], [2, 0]])), "Hermitian"),
+    (dict(H=np.array([[0, 1j], [1j, 0]])), "Hermitian"),
+    (dict(dt=0.0), "dt"),
+    (dict(dt=float("nan")), "dt"),
+    (dict(L=0), "dk_max"),
+    (dict(L=31), "dk_max"),
+    (dict(kT=-0.1), "kT"),
+    (dict(xi=-1.0), "xi"),
+    (dict(omega_c=0.0), "omega_c"),
+    (dict(bath_kind="table", omega_tab=np.array([1.0, 0.5]), J_tab=np.array([1.0, 1.0])), "increasing"),
+    (dict(bath_kind="table", omega_tab=np.array([0.0, 0.5]), J_tab=np.array([0.0, 1.0])), "increasing"),
+    (dict(bath_kind="table", omega_tab=np.array([0.5, 1.0]), J_tab=np.array([1.0, -1.0])), "J must be >= 0"),
+    (dict(L=25), "too large"),
+])
+def test_invalid_parameters_are_rejected(over, needle):
+    with pytest.raises(Q.QuapiError) as ei:
+        Q.footprint(_p(**over))
+    assert ei.value.status == Q.ERR_INVALID
+    assert needle in str(ei.value)
+
+
+def test_memory_cap_gives_nomem_before_touching_a_device(monkeypatch):
+    monkeypatch.setenv("QUAPI_FAKE_HBM_BYTES", "100000")
+    with pytest.raises(Q.QuapiError) as ei:
+        Q.create(_p())
+    assert ei.value.status == Q.ERR_NOMEM
+    assert "did not fit" in str(ei.value)
+
+
+def test_create_without_device_fails_cleanly():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except Exception:
+        pass
+    with pytest.raises(Q.QuapiError) as ei:
+        Q.create(_p(L=3))
+    assert ei.value.status == Q.ERR_DEVICE
+
+
+def test_null_context_calls_are_invalid():
+    lib = Q.lib()
+    assert lib.quapi_destroy(None) == Q.ERR_INVALID
+    assert b"NULL" in lib.quapi_last_error(None)

@@ -1,0 +1,205 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (per step n, on rho(t_n) as an M x M matrix):
+  complex128   max|rho_gpu - rho_oracle| <= 1e-12 * max|rho_oracle|
+  complex64    max|rho_c64 - rho_ref| <= 1e-5 (absolute), trace drift <= 1e-6
+Setup values (G, eta, U, K) agree with the oracle to 1e-13 of their scale.
+
+Small cases run the whole propagation through both sides.  At the full
+workload sizes the oracle cannot run every step, so the test compares the
+first steps completely, checks the trace and Hermiticity invariants at every
+step, and checks full-window steps entry by entry on sampled outputs
+(oracle.entry) at the headline size.
+"""
+import numpy as np
+import pytest
+
+from oracle import entry as oentry
+from oracle import run as orun
+from paper_1205_6872_amd import quapi as Q
+from paper_1205_6872_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_C128 = 1e-12
+
+
+def gpu_rho(w, n_steps, sel=None, **over):
+    p = Q.params_from(w, **over)
+    with Q.create(p) as ctx:
+        return ctx.propagate(n_steps, sel)
+
+
+def oracle_rho(w, n_steps, **over):
+    return orun.oracle_run(w.with_(**over) if over else w, n_steps)
+
+
+def rel_err_per_step(a, b):
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)
+
+
+def small_cases():
+    rng = np.random.default_rng(5)
+    w1 = W.spin_boson_l7()
+    yield "spin_boson_l7", w1, 100
+    yield "spin_boson_l7_kT0", w1.with_(kT=0.0), 40
+    yield "spin_boson_l1", w1.with_(L=1), 30
+    yield "spin_boson_l2_complexH", w1.with_(L=2, H=W.random_hermitian(rng, 2)), 30
+    yield "three_site_l4", W.three_site_l8().with_(L=4, xi=0.3), 40
+    yield "four_level_l3", w1.with_(M=4, s=np.linspace(-1, 1, 4), H=W.random_hermitian(rng, 4),
+                                    rho0=np.diag([1.0, 0, 0, 0]).astype(complex), L=3, xi=0.3), 25
+    yield "one_level", w1.with_(M=1, s=np.array([0.5]), H=np.array([[0.3]], dtype=complex),
+                                rho0=np.array([[1.0]], dtype=complex), L=2), 6
+    wt = np.linspace(0.05, 20.0, 120)
+    yield "table_bath_l5", w1.with_(L=5, bath_kind="table", omega_tab=wt,
+                                    J_tab=0.3 * wt ** 3 * np.exp(-(wt / 3.0) ** 2)), 30
+    yield "growth_only", w1.with_(L=9), 6
+
+
+@pytest.mark.parametrize("name,w,n", list(small_cases()), ids=[c[0] for c in small_cases()])
+def test_rho_matches_oracle_every_step(name, w, n):
+    print(f"case {name}: M={w.M} L={w.L} steps={n}", flush=True)
+    g = gpu_rho(w, n, sel=list(range(n + 1)))
+    o = oracle_rho(w, n)
+    err = rel_err_per_step(g, o)
+    assert err.max() <= TOL_C128, (name, err.argmax(), err.max())
+
+
+@pytest.mark.parametrize("name,w", [
+    ("ohmic", W.spin_boson_l7()),
+    ("ohmic_l15", W.spin_boson_l15("c128")),
+    ("ohmic_kT0", W.spin_boson_l7().with_(kT=0.0)),
+    ("three_site", W.three_site_l8()),
+    ("table", W.paper_quantum_dot(L=6, n_tab=400)),
+])
+def test_setup_matches_oracle(name, w):
+    inp = orun.inputs_from(w)
+    g_o, ec, U_o, K_o = orun.setup(inp)
+    with Q.create(Q.params_from(w)) as ctx:
+        g = ctx.get_setup(Q.SETUP_G)
+        eta = ctx.get_setup(Q.SETUP_ETA)
+        U = ctx.get_setup(Q.SETUP_U).reshape(w.M, w.M)
+        K = ctx.get_setup(Q.SETUP_K).reshape(w.N, w.N)
+    scale = np.abs(g_o).max()
+    assert np.abs(g - g_o).max() <= 1e-13 * scale + 1e-15, np.abs(g - g_o).max()
+    L = w.L
+    eta_o = np.concatenate([[ec.self_interior, ec.self_end], ec.lag[1:L + 1], ec.init[1:L + 1],
+                            ec.fin[1:L + 1], ec.fin_init[1:L + 1]])
+    assert np.abs(eta - eta_o).max() <= 1e-13 * scale + 1e-15
+    assert np.abs(U - U_o).max() <= 1e-14
+    assert np.abs(K - K_o).max() <= 1e-14
+
+
+def test_selection_chunking_and_just_final_point():
+    w = W.spin_boson_l7()
+    full = gpu_rho(w, 100, sel=list(range(101)))
+    with Q.create(Q.params_from(w)) as ctx:
+        a = ctx.propagate(37, sel=[0, 5, 37])
+        b = ctx.propagate(63)                        # all of steps 38..100
+        assert ctx.step_count() == 100
+    assert np.array_equal(a, full[[0, 5, 37]])
+    assert np.array_equal(b, full[38:101])
+    with Q.create(Q.params_from(w)) as ctx:
+        last = ctx.propagate(100, sel=[100])         # 'justFinalPoint'
+    assert np.array_equal(last[0], full[100])
+    with Q.create(Q.params_from(w)) as ctx:
+        none = ctx.propagate(0)
+        assert none.shape == (0, 2, 2) and ctx.step_count() == 0
+        with pytest.raises(Q.QuapiError) as ei:
+            ctx.propagate(5, sel=[3, 2])
+        assert ei.value.status == Q.ERR_INVALID
+        with pytest.raises(Q.QuapiError):
+            ctx.propagate(5, sel=[6])
+
+
+def test_bitwise_deterministic():
+    w = W.three_site_l8().with_(L=5, xi=0.3)
+    a = gpu_rho(w, 40)
+    b = gpu_rho(w, 40)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("wf,n_total,n_oracle", [
+    (W.spin_boson_l12, 500, 20),
+    (W.three_site_l8, 300, 11),
+])
+def test_full_size_prefix_and_invariants(wf, n_total, n_oracle):
+    w = wf()
+    print(f"case {w.name}: N^L={w.N ** w.L} steps={n_total}", flush=True)
+    g = gpu_rho(w, n_total, sel=list(range(n_total + 1)))
+    o = oracle_rho(w, n_oracle)
+    err = rel_err_per_step(g[:n_oracle + 1], o)
+    assert err.max() <= TOL_C128, (err.argmax(), err.max())
+    tr = np.trace(g, axis1=1, axis2=2)
+    assert np.abs(tr - 1.0).max() <= 1e-12
+    assert np.abs(g - np.conj(np.swapaxes(g, 1, 2))).max() <= 1e-12
+
+
+def _sampled_entry_check(w, dtype, tol):
+    """Full-window steps at the workload's own size, checked on sampled entries."""
+    rng = np.random.default_rng(17)
+    L, N = w.L, w.N
+    inp = orun.inputs_from(w)
+    _, ec, _, K = orun.setup(inp)
+    mc = N ** (L - 1)
+    ms = np.unique(np.concatenate([[0, 1, mc // 2, mc - 1], rng.integers(0, mc, 48)]))
+    with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
+        rho = ctx.propagate(L, sel=[L])               # growth + first full-window step
+        assert abs(np.trace(rho[0]) - 1) <= (1e-12 if dtype == "c128" else 1e-6)
+        for n in [L + 1, L + 2]:
+            a_in = {int(m): ctx.read_tensor(N * int(m), N) for m in ms}
+            rho = ctx.propagate(1)
+            worst = 0.0
+            for m in ms:
+                got = np.array([ctx.read_tensor(int(m) + mc * o, 1)[0] for o in range(N)])
+                want = np.array([oentry.step_entry(w.s, K, ec, L, n, int(m), o, a_in[int(m)])
+                                 for o in range(N)])
+                worst = max(worst, np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))
+            assert worst <= tol, (n, worst)
+            assert abs(np.trace(rho[0]) - 1) <= (1e-12 if dtype == "c128" else 1e-6)
+
+
+def test_headline_size_sampled_entries_c128():
+    _sampled_entry_check(W.spin_boson_l15("c128"), "c128", 1e-12)
+
+
+def test_headline_size_sampled_entries_c64():
+    _sampled_entry_check(W.spin_boson_l15("c64"), "c64", 2e-5)
+
+
+def test_c64_tier_against_oracle_small():
+    w = W.spin_boson_l7()
+    g = gpu_rho(w, 100, dtype="c64")
+    o = oracle_rho(w, 100)[1:]
+    assert np.abs(g - o).max() <= 1e-5
+    tr = np.trace(g, axis1=1, axis2=2)
+    assert np.abs(tr - 1).max() <= 1e-6
+
+
+def test_c64_tier_against_c128_headline_workload():
+    w = W.spin_boson_l15("c64")
+    n = 150
+    r64 = gpu_rho(w, n, dtype="c64")
+    r128 = gpu_rho(w, n, dtype="c128")
+    d = np.abs(r64 - r128).max()
+    drift = np.abs(np.trace(r64, axis1=1, axis2=2) - np.trace(r128, axis1=1, axis2=2)).max()
+    print(f"c64 vs c128 over {n} steps: max|drho| = {d:.3e}, trace drift = {drift:.3e}", flush=True)
+    assert d <= 1e-5
+    assert drift <= 1e-6
+
+
+def test_async_with_torch_workspace_and_stream():
+    import torch
+    w = W.three_site_l8().with_(L=5, xi=0.3)
+    ref = gpu_rho(w, 30)
+    p = Q.params_from(w)
+    stream = torch.cuda.Stream()
+    ctx = Q.create_in_torch(p, stream=stream)
+    out = torch.zeros((30, w.N, 2), dtype=torch.float64, device="cuda:0")
+    ctx.propagate_async(30, None, out.data_ptr())
+    stream.synchronize()
+    got = out.cpu().numpy().view(np.complex128).reshape(30, w.M, w.M)
+    ctx.destroy()
+    assert np.array_equal(got, ref)
