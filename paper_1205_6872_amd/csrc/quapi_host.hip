@@ -396,7 +396,7 @@ quapi_status enqueue_step(quapi_ctx *c, int n, double2 *out) {
     const size_t lds = step_lds_bytes(c->N, c->c64, rho, sp.grow, a.R, a.Q);
     // host-side launch checks: the grid must tile m exactly and stay in the buffers
     if ((long long)sp.split.grid * a.R * a.Q != a.m_count || in_entries > cap || out_entries > cap ||
-        sp.split.grid > c->lay.partial_blocks || lds > (size_t)kLdsLimit || kBlock % a.R != 0)
+        sp.split.grid > c->lay.partial_blocks || lds > (size_t)kLdsLimit || a.R > kBlock)
         return fail(c, QUAPI_ERR_DEVICE, "internal launch check failed at step %d", n);
     a.a_in = c->A[c->cur];
     a.a_out = c->A[1 - c->cur];
