@@ -6,8 +6,8 @@ default, rho(t_n) extracted at every step ('allPoints').  Inputs are
 synthetic (seeded parameters, no dataset).
 
 A timed "step" is one full-window propagation step: the step kernel reads the
-tensor once, writes it once, and (fused) produces rho(t_n); the rho finalize
-kernel follows.  The growth steps (n < L) and the device setup run first and
+tensor once, writes it once, and produces per-block partial sums of rho(t_n)
+in the same pass; a small finalize kernel sums them.  The growth steps (n < L) and the device setup run first and
 are reported separately.  Both precision tiers run on the same workload:
 complex128 (the reported `value`) and the complex64 tier (`fp32_tier`), with
 max|drho| and trace drift of the tier against complex128.

@@ -54,10 +54,15 @@ typedef enum {
     QUAPI_ERR_STATE = 4      /* overlapping use of one context */
 } quapi_status;
 
+/* Precision of the augmented density tensor.  G, eta, U, K and the influence
+ * tables are always FP64, and rho is always reduced in FP64 with compensated
+ * sums.  The per-block and per-thread factor products are formed in FP64 and
+ * rounded once to the arithmetic type. */
 typedef enum {
-    QUAPI_C128 = 0,          /* tensor stored and contracted in complex128 */
-    QUAPI_C64 = 1            /* tensor in complex64, FP32 products; tables, eta, G and
-                                the rho reduction stay FP64 */
+    QUAPI_C128 = 0,          /* stored in complex128, FP64 products */
+    QUAPI_C64 = 1,           /* stored in complex64, FP32 products with FP32 accumulation */
+    QUAPI_C64_F64 = 2        /* stored in complex64; each loaded value is widened and every
+                                product and sum is FP64, rounded to complex64 on store */
 } quapi_dtype;
 
 typedef enum {
@@ -90,8 +95,8 @@ typedef struct {
 } quapi_params;
 
 /* Device bytes that quapi_create needs for these parameters (the two
- * ping-pong tensors of N^L entries dominate; the rest is tables and
- * reduction scratch of a few MB at most).  Validates the parameters; needs
+ * ping-pong tensors of N^L entries dominate; factor tables and rho
+ * reduction scratch add less than 0.1% of that plus 4 MB).  Validates the parameters; needs
  * no GPU.  INVALID on malformed parameters or size overflow. */
 quapi_status quapi_footprint(const quapi_params *p, size_t *device_bytes);
 
@@ -150,10 +155,11 @@ enum { QUAPI_SETUP_G = 0, QUAPI_SETUP_ETA = 1, QUAPI_SETUP_U = 2, QUAPI_SETUP_K 
 quapi_status quapi_get_setup(const quapi_ctx *ctx, int what, double *out, size_t out_len);
 
 /* Test hook: copy entries [first, first + count) of the current augmented
- * tensor to host as complex128 (widened from complex64 for QUAPI_C64).
+ * tensor to host as complex128.
  * Layout after global step c >= 1: the tensor holds path points
  * max(0, c-L+1) .. c, flat index sum_j o_{p0 + j} N^j (oldest point fastest),
- * N^min(c+1, L) entries.  INVALID when the range exceeds the tensor. */
+ * N^min(c+1, L) entries (complex64 storage is widened to complex128).
+ * INVALID when the range exceeds the tensor. */
 quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count, double *out);
 
 /* Number of entries in the current tensor (N^min(c+1, L)). */
@@ -166,7 +172,7 @@ typedef struct {
     long long step_launches;  /* number of those launches */
     double grow_ms;           /* summed duration of growth-step kernels (n < L) */
     long long grow_launches;
-    double finalize_ms;       /* summed duration of rho finalize kernels */
+    double finalize_ms;       /* summed duration of the kernels that sum rho over blocks */
     long long finalize_launches;
 } quapi_timing;
 

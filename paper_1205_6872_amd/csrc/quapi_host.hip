@@ -55,7 +55,7 @@ struct DigitSplit {
 DigitSplit split_digits(int N, int n_digits) {
     int d_lo_max = 0, d_mid_target = 0;
     switch (N) {
-    case 4: d_lo_max = 4; d_mid_target = 3; break;    // R = 256 = block, Q <= 64
+    case 4: d_lo_max = 4; d_mid_target = 2; break;    // R = 256 = block, Q <= 16
     case 9: d_lo_max = 2; d_mid_target = 2; break;    // R = 81 (243 threads active), Q <= 81
     case 16: d_lo_max = 1; d_mid_target = 1; break;   // R = 16, Q <= 16 (LDS budget)
     default: break;                                   // N = 1: a single entry
@@ -182,7 +182,8 @@ std::string validate(const quapi_params *p) {
         return buf;
     }
     if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return "kT must be finite and >= 0";
-    if (p->dtype != QUAPI_C128 && p->dtype != QUAPI_C64) return "dtype must be QUAPI_C128 or QUAPI_C64";
+    if (p->dtype != QUAPI_C128 && p->dtype != QUAPI_C64 && p->dtype != QUAPI_C64_F64)
+        return "dtype must be QUAPI_C128, QUAPI_C64 or QUAPI_C64_F64";
     const quapi_bath &b = p->bath;
     if (b.kind == QUAPI_BATH_OHMIC) {
         if (!(b.xi >= 0.0) || !std::isfinite(b.xi)) return "Ohmic xi must be finite and >= 0";
@@ -210,8 +211,10 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_g, off_eta, off_U, off_s, off_H, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
+    size_t off_plan;
     size_t total;
     int n_panels, n_tables, partial_blocks;
+    DigitSplit main_split;   // digit split of the full-window steps
 };
 
 Layout make_layout(const quapi_params &p, int n_panels) {
@@ -219,10 +222,11 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     const int M = p.M, N = M * M, L = p.dk_max;
     size_t entries = 1;
     checked_pow((size_t)N, L, &entries);
-    const size_t cs = p.dtype == QUAPI_C64 ? 8 : 16;
+    const size_t cs = p.dtype == QUAPI_C128 ? 16 : 8;
     l.n_panels = n_panels;
     l.n_tables = BankLayout{L}.count();
     l.partial_blocks = max_grid(N, L);
+    l.main_split = split_digits(N, L - 1);
     l.a_bytes = entries * cs;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -247,8 +251,11 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_tJ = take((size_t)nt * 8);
     l.off_glx = take(kGL * 8);
     l.off_glw = take(kGL * 8);
-    l.off_partials = take((size_t)l.partial_blocks * N * 16);
+    l.off_partials = take((size_t)2 * l.partial_blocks * N * 16);   // double-buffered
     l.off_stage = take((size_t)kRhoStage * N * 16);
+    // six FP64 factor tables of the full-window split: [N][R], [N][Q], [N][grid], x2 classes
+    const DigitSplit &ms = l.main_split;
+    l.off_plan = take((size_t)2 * N * (ms.R + ms.Q + ms.grid) * 16);
     l.total = off;
     return l;
 }
@@ -265,10 +272,17 @@ int count_panels(const quapi_params &p) {
 // ----------------------------------------------------------------- context
 struct quapi_ctx {
     int M = 0, N = 0, L = 0;
-    bool c64 = false;
+    int prec = kPrecC128;         // quapi_dtype
+    size_t csize = 16;            // bytes per stored tensor entry
     double dt = 0.0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // rho finalize kernels run on a side stream, overlapped with the next step;
+    // the block partials are double-buffered between the two streams
+    hipStream_t side = nullptr;
+    hipEvent_t ev_step[2] = {nullptr, nullptr}, ev_fin[2] = {nullptr, nullptr};
+    bool fin_pending[2] = {false, false};
+    int pslot = 0;
     char *ws = nullptr;
     bool own_ws = false;
     Layout lay{};
@@ -276,7 +290,9 @@ struct quapi_ctx {
     int cur = 0;                  // A[cur] holds the tensor after global step `step`
     int step = 0;
     double2 *bank = nullptr, *g = nullptr, *eta = nullptr, *U = nullptr, *rho0_d = nullptr;
-    double2 *partials = nullptr, *stage = nullptr;
+    double2 *partials[2] = {nullptr, nullptr};
+    double2 *stage = nullptr, *plan = nullptr;
+    bool plan_ready = false;      // full-window factor tables computed
     std::vector<double> rho0_h;
     // host copies of uploaded inputs (kept alive until the uploads complete)
     std::vector<double> s_h, H_h, pa_h, ph_h, tw_h, tJ_h, glx_h, glw_h;
@@ -381,7 +397,6 @@ StepPlan plan_step(const quapi_ctx *c, int n) {
         a.oldf_tab = n == L ? B.oldf_first() : B.oldf_main();
     }
     a.bank = c->bank;
-    a.partials = c->partials;
     return sp;
 }
 
@@ -389,17 +404,62 @@ StepPlan plan_step(const quapi_ctx *c, int n) {
 quapi_status enqueue_step(quapi_ctx *c, int n, double2 *out) {
     StepPlan sp = plan_step(c, n);
     StepArgs &a = sp.args;
-    const size_t cap = c->lay.a_bytes / (c->c64 ? 8 : 16);
-    const size_t in_entries = (size_t)a.m_count * (sp.grow ? 1 : c->N);
-    const size_t out_entries = (size_t)a.m_count * c->N;
+    const int N = c->N;
+    const size_t cap = c->lay.a_bytes / c->csize;
+    const size_t in_entries = (size_t)a.m_count * (sp.grow ? 1 : N);
+    const size_t out_entries = (size_t)a.m_count * N;
     const bool rho = out != nullptr;
-    const size_t lds = step_lds_bytes(c->N, c->c64, rho, sp.grow, a.R, a.Q);
+    const size_t lds = step_lds_bytes(N, c->prec, rho, sp.grow, a.R, a.Q);
     // host-side launch checks: the grid must tile m exactly and stay in the buffers
     if ((long long)sp.split.grid * a.R * a.Q != a.m_count || in_entries > cap || out_entries > cap ||
         sp.split.grid > c->lay.partial_blocks || lds > (size_t)kLdsLimit || a.R > kBlock)
         return fail(c, QUAPI_ERR_DEVICE, "internal launch check failed at step %d", n);
+    if (!sp.grow) {
+        const DigitSplit &ms = c->lay.main_split;
+        if (ms.R != a.R || ms.Q != a.Q || ms.grid != sp.split.grid)
+            return fail(c, QUAPI_ERR_DEVICE, "internal split mismatch at step %d", n);
+        const size_t nr = (size_t)N * ms.R, nq = (size_t)N * ms.Q, nh = (size_t)N * ms.grid;
+        double2 *t_lo = c->plan, *t_lof = t_lo + nr, *t_mid = t_lof + nr, *t_midf = t_mid + nq;
+        double2 *t_hi = t_midf + nq, *t_hif = t_hi + nh;
+        if (!c->plan_ready) {
+            PlanArgs pa{};
+            pa.bank = c->bank;
+            pa.N = N;
+            pa.d_lo = a.d_lo;
+            pa.d_mid = a.d_mid;
+            pa.n_digits = a.n_digits;
+            pa.R = a.R;
+            pa.Q = a.Q;
+            pa.grid = sp.split.grid;
+            std::memcpy(pa.tab, a.tab, sizeof pa.tab);
+            std::memcpy(pa.tabf, a.tabf, sizeof pa.tabf);
+            pa.t_lo = t_lo;
+            pa.t_lof = t_lof;
+            pa.t_mid = t_mid;
+            pa.t_midf = t_midf;
+            pa.t_hi = t_hi;
+            pa.t_hif = t_hif;
+            hipError_t e = launch_plan_tables(pa, c->stream);
+            if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "plan kernel launch: %s", hipGetErrorString(e));
+            c->plan_ready = true;
+        }
+        a.t_lo = t_lo;
+        a.t_lof = t_lof;
+        a.t_mid = t_mid;
+        a.t_midf = t_midf;
+        a.t_hi = t_hi;
+        a.t_hif = t_hif;
+    }
+    a.grid = sp.split.grid;
     a.a_in = c->A[c->cur];
     a.a_out = c->A[1 - c->cur];
+    const int slot = c->pslot;
+    if (rho) {
+        c->pslot ^= 1;
+        a.partials = c->partials[slot];
+        // the finalize that last read this partial buffer must be done
+        if (c->fin_pending[slot]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_fin[slot], 0));
+    }
     const int kind = sp.grow ? 1 : 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -407,28 +467,42 @@ quapi_status enqueue_step(quapi_ctx *c, int n, double2 *out) {
         e1 = take_event(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
-    hipError_t e = launch_step(c->N, c->c64, rho, sp.grow, a, sp.split.grid, c->stream);
+    hipError_t e = launch_step(N, c->prec, rho, sp.grow, a, sp.split.grid, c->stream);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "step kernel launch: %s", hipGetErrorString(e));
     if (c->timing && e0 && e1) {
         (void)hipEventRecord(e1, c->stream);
         c->recs.push_back({kind, e0, e1});
     }
     if (rho) {
+        HIP_TRY(c, hipEventRecord(c->ev_step[slot], c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_step[slot], 0));
         hipEvent_t f0 = nullptr, f1 = nullptr;
         if (c->timing) {
             f0 = take_event(c);
             f1 = take_event(c);
-            if (f0) (void)hipEventRecord(f0, c->stream);
+            if (f0) (void)hipEventRecord(f0, c->side);
         }
-        e = launch_rho_finalize(c->N, c->partials, sp.split.grid, out, c->stream);
+        e = launch_rho_finalize(N, c->partials[slot], sp.split.grid, out, c->side);
         if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "rho finalize launch: %s", hipGetErrorString(e));
         if (c->timing && f0 && f1) {
-            (void)hipEventRecord(f1, c->stream);
+            (void)hipEventRecord(f1, c->side);
             c->recs.push_back({2, f0, f1});
         }
+        HIP_TRY(c, hipEventRecord(c->ev_fin[slot], c->side));
+        c->fin_pending[slot] = true;
     }
     c->cur = 1 - c->cur;
     c->step = n;
+    return QUAPI_OK;
+}
+
+// Order the main stream after every finalize still running on the side stream.
+quapi_status join_side(quapi_ctx *c) {
+    for (int k = 0; k < 2; ++k)
+        if (c->fin_pending[k]) {
+            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_fin[k], 0));
+            c->fin_pending[k] = false;
+        }
     return QUAPI_OK;
 }
 
@@ -468,6 +542,8 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
     int staged = 0;      // outputs in the staging buffer (blocking call)
     auto flush = [&]() -> quapi_status {
         if (!staged) return QUAPI_OK;
+        quapi_status js = join_side(c);
+        if (js != QUAPI_OK) return js;
         HIP_TRY(c, hipMemcpyAsync(host_out + (size_t)2 * N * (written - staged), c->stage,
                                   (size_t)staged * N * 16, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -498,6 +574,8 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
             }
         }
     }
+    st = join_side(c);
+    if (st != QUAPI_OK) return st;
     if (!dev_out) {
         st = flush();
         if (st != QUAPI_OK) return st;
@@ -509,6 +587,12 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
 void release(quapi_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    for (int k = 0; k < 2; ++k) {
+        if (c->ev_step[k]) (void)hipEventDestroy(c->ev_step[k]);
+        if (c->ev_fin[k]) (void)hipEventDestroy(c->ev_fin[k]);
+    }
+    if (c->side) (void)hipStreamDestroy(c->side);
     for (auto &r : c->recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -572,7 +656,8 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->M = M;
     c->N = N;
     c->L = L;
-    c->c64 = p->dtype == QUAPI_C64;
+    c->prec = p->dtype;
+    c->csize = p->dtype == QUAPI_C128 ? 16 : 8;
     c->dt = p->dt;
     c->lay = lay;
     if (hip_stream) {
@@ -583,6 +668,14 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
             return fail(nullptr, QUAPI_ERR_DEVICE, "hipStreamCreate failed");
         }
         c->own_stream = true;
+    }
+    bool side_ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; k < 2 && side_ok; ++k)
+        side_ok = hipEventCreateWithFlags(&c->ev_step[k], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->ev_fin[k], hipEventDisableTiming) == hipSuccess;
+    if (!side_ok) {
+        release(c);
+        return fail(nullptr, QUAPI_ERR_DEVICE, "side stream / event creation failed");
     }
     if (workspace) {
         c->ws = (char *)workspace;
@@ -613,8 +706,10 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->eta = (double2 *)(w + lay.off_eta);
     c->U = (double2 *)(w + lay.off_U);
     c->rho0_d = (double2 *)(w + lay.off_rho0);
-    c->partials = (double2 *)(w + lay.off_partials);
+    c->partials[0] = (double2 *)(w + lay.off_partials);
+    c->partials[1] = c->partials[0] + (size_t)lay.partial_blocks * N;
     c->stage = (double2 *)(w + lay.off_stage);
+    c->plan = (double2 *)(w + lay.off_plan);
 
     c->s_h.assign(p->s, p->s + M);
     c->H_h.assign(p->H, p->H + 2 * M * M);
@@ -682,7 +777,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     ta.bank = c->bank;
     if (e == hipSuccess) e = launch_tables(ta, c->stream);
     if (e == hipSuccess)
-        e = launch_init_tensor(N, c->c64, c->rho0_d, c->bank, BankLayout{L}.self_end(), c->A[0], c->stream);
+        e = launch_init_tensor(N, c->prec, c->rho0_d, c->bank, BankLayout{L}.self_end(), c->A[0], c->stream);
     if (s1) (void)hipEventRecord(s1, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -761,7 +856,7 @@ quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count,
                     first + count, entries);
     if (!count) return QUAPI_OK;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (!c->c64) {
+    if (c->prec == kPrecC128) {
         HIP_TRY(c, hipMemcpy(out, (const char *)c->A[c->cur] + first * 16, count * 16, hipMemcpyDeviceToHost));
     } else {
         std::vector<float> tmp(2 * count);
@@ -780,6 +875,7 @@ quapi_status quapi_set_timing(quapi_ctx *ctx, int enable) {
 quapi_status quapi_get_timing(quapi_ctx *ctx, quapi_timing *out) {
     if (!ctx || !out) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->side));
     for (auto &r : ctx->recs) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {

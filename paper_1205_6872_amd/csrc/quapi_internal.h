@@ -14,6 +14,11 @@ constexpr int kBlock = 256;              // threads per block of every propagati
 constexpr int kGL = 16;                  // Gauss-Legendre nodes per quadrature panel
 constexpr int kLdsLimit = 64 * 1024;     // LDS bytes a step block may use
 
+// Tensor precision (values of quapi_dtype): storage / arithmetic.
+constexpr int kPrecC128 = 0;             // complex128 / FP64
+constexpr int kPrecC64 = 1;              // complex64 / FP32
+constexpr int kPrecC64F64 = 2;           // complex64 / FP64
+
 // Influence/propagator table bank.  Every table is N x N complex128, row o
 // (later point) and column p (earlier point), stored at bank[t * N*N + o*N + p].
 struct BankLayout {
@@ -43,14 +48,26 @@ struct StepArgs {
     const void *a_in;
     void *a_out;
     const double2 *bank;
-    double2 *partials;          // [gridDim.x][N] block partial sums of rho (with_rho)
+    // Full-window steps: factor products over the thread / sweep / block digits,
+    // precomputed once per context (FP64, [N][R], [N][Q], [N][grid]).  NULL:
+    // the kernel multiplies the bank tables of the digits itself (growth steps).
+    const double2 *t_lo, *t_lof, *t_mid, *t_midf, *t_hi, *t_hif;
+    double2 *partials;          // [grid][N] block partial sums of rho (with_rho)
     long long m_count;          // N^n_digits
     int n_digits;               // digits of m
     int d_lo, d_mid;            // digits owned by the thread / swept by the block loop
-    int R, Q;                   // N^d_lo, N^d_mid
+    int R, Q, grid;             // N^d_lo, N^d_mid, N^(n_digits - d_lo - d_mid)
     int old_tab, oldf_tab;      // bank indices of the oldest-point tables
     int16_t tab[kMaxL];         // bank index of the interior table for digit j
     int16_t tabf[kMaxL];        // bank index of the final-point table for digit j
+};
+
+// Factor products of the full-window digit split (see StepArgs::t_lo ...).
+struct PlanArgs {
+    const double2 *bank;
+    int N, d_lo, d_mid, n_digits, R, Q, grid;
+    int16_t tab[kMaxL], tabf[kMaxL];
+    double2 *t_lo, *t_lof, *t_mid, *t_midf, *t_hi, *t_hif;
 };
 
 struct QuadArgs {
@@ -78,12 +95,13 @@ struct TablesArgs {
 // Kernel launchers (quapi_kernels.hip).  They return the launch status.
 hipError_t launch_g_quad(const QuadArgs &a, int n_t, double2 *g, hipStream_t st);
 hipError_t launch_tables(const TablesArgs &a, hipStream_t st);
-hipError_t launch_init_tensor(int N, bool c64, const double2 *rho0, const double2 *bank,
+hipError_t launch_init_tensor(int N, int prec, const double2 *rho0, const double2 *bank,
                               int self_end_tab, void *a0, hipStream_t st);
-hipError_t launch_step(int N, bool c64, bool with_rho, bool grow, const StepArgs &a, int grid,
+hipError_t launch_step(int N, int prec, bool with_rho, bool grow, const StepArgs &a, int grid,
                        hipStream_t st);
 hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *out,
                                hipStream_t st);
-size_t step_lds_bytes(int N, bool c64, bool with_rho, bool grow, int R, int Q);
+hipError_t launch_plan_tables(const PlanArgs &a, hipStream_t st);
+size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q);
 
 }  // namespace quapi

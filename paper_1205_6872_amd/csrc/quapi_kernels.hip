@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "quapi_internal.h"
 
 namespace quapi {
@@ -48,6 +50,15 @@ template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v) {
 }
 __device__ __forceinline__ double2 to_d2(double2 v) { return v; }
 __device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+// storage <-> arithmetic complex types (identity, widen, or round to nearest)
+template <typename To> __device__ __forceinline__ To conv(double2 v);
+template <typename To> __device__ __forceinline__ To conv(float2 v);
+template <> __device__ __forceinline__ double2 conv<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 conv<float2>(float2 v) { return v; }
+template <> __device__ __forceinline__ double2 conv<double2>(float2 v) { return make_double2(v.x, v.y); }
+template <> __device__ __forceinline__ float2 conv<float2>(double2 v) {
+    return make_float2((float)v.x, (float)v.y);
+}
 
 // ------------------------------------------------ compensated summation
 // Neumaier's variant of Kahan summation: s + c carries the running sum.
@@ -65,26 +76,34 @@ __device__ __forceinline__ void two_sum_combine(double &s1, double &c1, double s
     s1 = s;
     c1 = c1 + c2 + e;
 }
-// Block-wide compensated reduction of (sr, cr, si, ci) in a fixed tree order;
-// returns the total (valid in thread 0).  All kBlock threads must call it.
-__device__ double2 block_sum_compensated(double sr, double cr, double si, double ci) {
-    __shared__ double s_v[4][kBlock];
+// Block-wide compensated reduction of (sum, compensation) pairs for a real
+// and an imaginary part, in a fixed tree order; the totals land in thread 0's
+// arguments.  All B threads of the block must call it.
+template <int B>
+__device__ void block_reduce_pairs(double &sr, double &cr, double &si, double &ci) {
+    __shared__ double s_v[4][B];
     const int t = threadIdx.x;
     s_v[0][t] = sr;
     s_v[1][t] = cr;
     s_v[2][t] = si;
     s_v[3][t] = ci;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
+    for (int w = B / 2; w > 0; w >>= 1) {
         if (t < w) {
             two_sum_combine(s_v[0][t], s_v[1][t], s_v[0][t + w], s_v[1][t + w]);
             two_sum_combine(s_v[2][t], s_v[3][t], s_v[2][t + w], s_v[3][t + w]);
         }
         __syncthreads();
     }
-    const double2 r = make_double2(s_v[0][0] + s_v[1][0], s_v[2][0] + s_v[3][0]);
+    sr = s_v[0][0];
+    cr = s_v[1][0];
+    si = s_v[2][0];
+    ci = s_v[3][0];
     __syncthreads();
-    return r;
+}
+__device__ double2 block_sum_compensated(double sr, double cr, double si, double ci) {
+    block_reduce_pairs<kBlock>(sr, cr, si, ci);
+    return make_double2(sr + cr, si + ci);
 }
 
 // --------------------------------------------------- lineshape quadrature
@@ -315,26 +334,46 @@ __host__ __device__ inline StepLds step_lds_layout(int N, int csize, bool rho, i
     return l;
 }
 
+// Product over nd digits of v (base N, least significant first) of the bank
+// tables tab[j0 + j], row o.
+template <int N>
+__device__ double2 digit_product(const double2 *__restrict__ bank, const int16_t *tab, int j0, int nd,
+                                 long long v, int o, double2 p) {
+    for (int j = 0; j < nd; ++j) {
+        const int dg = (int)(v % N);
+        v /= N;
+        p = cmul(p, bank[(size_t)tab[j0 + j] * (N * N) + o * N + dg]);
+    }
+    return p;
+}
+
 // One propagation step.  Output entry (m, o), o the new point's index and m the
 // digits of the kept window points:
 //   A_out[m + m_count*o] = P(o, m) * sum_{i<I} Old[o][i] * A_in[i + I*m]
 // with P(o, m) = prod_j Tab_j[o][digit_j(m)].  I = N sums out the oldest point
 // (full window); I = 1 is a growth step (window not yet full).  With RHO the
 // same loaded values also give rho(t_n)[o] = sum_m Pfin(o,m) sum_i OldFin[o][i] A_in[i + I*m]
-// (final-point classes), reduced per block into partials[blockIdx][o].
+// (final-point classes), reduced per block into partials[blockIdx][o] and
+// summed across blocks by rho_finalize_kernel.
 //
 // Digits of m: the low d_lo digits are fixed per thread (product in
 // registers or LDS), the next d_mid digits are swept by the thread's loop
 // (products tabulated in LDS per block), the rest are the block index
 // (product computed once per block).  Consecutive threads own consecutive m,
-// so each thread reads I contiguous values and every o-plane store is coalesced.
-template <int N, typename T, bool RHO, bool GROW>
+// so each thread reads I contiguous values and every o-plane store is
+// coalesced.  For N <= 4 each thread keeps two items in flight.
+//
+// S is the storage scalar of the tensor and T the arithmetic scalar: double /
+// double (complex128), float / float (complex64 tier), float / double
+// (complex64 storage, each loaded value widened and every product in FP64).
+template <int N, typename S, typename T, bool RHO, bool GROW>
 __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
     using C = typename Cx<T>::type;
+    using CS = typename Cx<S>::type;
     constexpr int I = GROW ? 1 : N;
-    constexpr int NN = N * N;
     constexpr bool PLO_REG = (N <= 4);
     constexpr bool OLD_REG = (N <= 4);
+    constexpr int ILP = (N <= 4) ? 2 : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int R = a.R, Q = a.Q;
     const StepLds lay = step_lds_layout(N, (int)sizeof(C), RHO, I, R, Q, PLO_REG);
@@ -353,54 +392,44 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
     const double2 *__restrict__ bank = a.bank;
     const long long blk = blockIdx.x;
     const double2 one = make_double2(1.0, 0.0);
+    const bool planned = a.t_lo != nullptr;
+    const int j_hi = a.d_lo + a.d_mid;
 
-    // Block constants: high-digit products (FP64) and the oldest-point tables.
+    // Block constants (FP64): high-digit products and the oldest-point tables.
     if (t < N) {
-        double2 ph = one, phf = one;
-        long long rem = blk;
-        for (int j = a.d_lo + a.d_mid; j < a.n_digits; ++j) {
-            const int dg = (int)(rem % N);
-            rem /= N;
-            ph = cmul(ph, bank[(size_t)a.tab[j] * NN + t * N + dg]);
-            if (RHO) phf = cmul(phf, bank[(size_t)a.tabf[j] * NN + t * N + dg]);
+        double2 ph, phf = one;
+        if (planned) {
+            ph = a.t_hi[(size_t)t * a.grid + blk];
+            if (RHO) phf = a.t_hif[(size_t)t * a.grid + blk];
+        } else {
+            ph = digit_product<N>(bank, a.tab, j_hi, a.n_digits - j_hi, blk, t, one);
+            if (RHO) phf = digit_product<N>(bank, a.tabf, j_hi, a.n_digits - j_hi, blk, t, one);
         }
         s_phi[t] = ph;
         s_phi[N + t] = phf;
     }
     for (int idx = t; idx < N * I; idx += kBlock) {
         const int o = idx / I, i = idx % I;
-        s_old[idx] = from_d2<C>(bank[(size_t)a.old_tab * NN + o * N + i]);
-        if (RHO) s_oldf[idx] = from_d2<C>(bank[(size_t)a.oldf_tab * NN + o * N + i]);
+        s_old[idx] = from_d2<C>(bank[(size_t)a.old_tab * (N * N) + o * N + i]);
+        if (RHO) s_oldf[idx] = from_d2<C>(bank[(size_t)a.oldf_tab * (N * N) + o * N + i]);
     }
     if (!PLO_REG) {
         for (int idx = t; idx < N * R; idx += kBlock) {
-            const int o = idx / R;
-            int rem = idx % R;
-            double2 p = one, pf = one;
-            for (int j = 0; j < a.d_lo; ++j) {
-                const int dg = rem % N;
-                rem /= N;
-                p = cmul(p, bank[(size_t)a.tab[j] * NN + o * N + dg]);
-                if (RHO) pf = cmul(pf, bank[(size_t)a.tabf[j] * NN + o * N + dg]);
-            }
-            s_plo[idx] = from_d2<C>(p);
-            if (RHO) s_plof[idx] = pf;
+            const int o = idx / R, v = idx % R;
+            s_plo[idx] = from_d2<C>(planned ? a.t_lo[idx] : digit_product<N>(bank, a.tab, 0, a.d_lo, v, o, one));
+            if (RHO) s_plof[idx] = planned ? a.t_lof[idx] : digit_product<N>(bank, a.tabf, 0, a.d_lo, v, o, one);
         }
     }
     __syncthreads();
-    // Mid-digit products times the high-digit product, cast once to C.
+    // Mid-digit products times the block's high-digit product, cast once to C.
     for (int idx = t; idx < N * Q; idx += kBlock) {
-        const int o = idx / Q;
-        int rem = idx % Q;
-        double2 v = s_phi[o], vf = s_phi[N + o];
-        for (int j = 0; j < a.d_mid; ++j) {
-            const int dg = rem % N;
-            rem /= N;
-            v = cmul(v, bank[(size_t)a.tab[a.d_lo + j] * NN + o * N + dg]);
-            if (RHO) vf = cmul(vf, bank[(size_t)a.tabf[a.d_lo + j] * NN + o * N + dg]);
+        const int o = idx / Q, v = idx % Q;
+        const double2 mid = planned ? a.t_mid[idx] : digit_product<N>(bank, a.tab, a.d_lo, a.d_mid, v, o, one);
+        s_tq[idx] = from_d2<C>(cmul(s_phi[o], mid));
+        if (RHO) {
+            const double2 midf = planned ? a.t_midf[idx] : digit_product<N>(bank, a.tabf, a.d_lo, a.d_mid, v, o, one);
+            s_tqf[idx] = from_d2<C>(cmul(s_phi[N + o], midf));
         }
-        s_tq[idx] = from_d2<C>(v);
-        if (RHO) s_tqf[idx] = from_d2<C>(vf);
     }
     // Low-digit products of this thread's fixed digits.
     const int r = t % R;
@@ -409,16 +438,8 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
     if (PLO_REG) {
 #pragma unroll
         for (int o = 0; o < N; ++o) {
-            double2 p = one, pf = one;
-            int rem = r;
-            for (int j = 0; j < a.d_lo; ++j) {
-                const int dg = rem % N;
-                rem /= N;
-                p = cmul(p, bank[(size_t)a.tab[j] * NN + o * N + dg]);
-                if (RHO) pf = cmul(pf, bank[(size_t)a.tabf[j] * NN + o * N + dg]);
-            }
-            plo[o] = from_d2<C>(p);
-            plof[o] = pf;
+            plo[o] = from_d2<C>(planned ? a.t_lo[o * R + r] : digit_product<N>(bank, a.tab, 0, a.d_lo, r, o, one));
+            plof[o] = RHO ? (planned ? a.t_lof[o * R + r] : digit_product<N>(bank, a.tabf, 0, a.d_lo, r, o, one)) : one;
         }
     }
     __syncthreads();
@@ -438,32 +459,46 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 
     if (t < active) {
         const long long m0 = blk * (long long)R * Q;
-        const C *__restrict__ ain = (const C *)a.a_in;
-        C *__restrict__ aout = (C *)a.a_out;
+        const CS *__restrict__ ain = (const CS *)a.a_in;
+        CS *__restrict__ aout = (CS *)a.a_out;
         const long long mc = a.m_count;
-        for (int qm = t / R; qm < Q; qm += cR) {
+        for (int qm0 = t / R; qm0 < Q; qm0 += ILP * cR) {
             // For N >= 9 the N*N table reads must stay in the loop: hoisted as
             // loop invariants they would need more registers than a thread has.
             if (!OLD_REG) asm volatile("" ::: "memory");
-            const long long m = m0 + (long long)qm * R + r;
-            C x[I];
+            C x[ILP][I];
+            bool has[ILP];
 #pragma unroll
-            for (int i = 0; i < I; ++i) x[i] = ain[(long long)I * m + i];
+            for (int u = 0; u < ILP; ++u) {      // issue every load first
+                const int qm = qm0 + u * cR;
+                has[u] = qm < Q;
+                const long long m = m0 + (long long)qm * R + r;
+                if (has[u]) {
 #pragma unroll
-            for (int o = 0; o < N; ++o) {
-                C s = {};
+                    for (int i = 0; i < I; ++i) x[u][i] = conv<C>(ain[(long long)I * m + i]);
+                }
+            }
 #pragma unroll
-                for (int i = 0; i < I; ++i) cmac(s, OLD_REG ? old_r[o * I + i] : s_old[o * I + i], x[i]);
-                const C p = cmul(PLO_REG ? plo[o] : s_plo[o * R + r], s_tq[o * Q + qm]);
-                aout[m + mc * o] = cmul(s, p);
-                if (RHO) {
-                    C sf = {};
+            for (int u = 0; u < ILP; ++u) {
+                if (!has[u]) continue;
+                const int qm = qm0 + u * cR;
+                const long long m = m0 + (long long)qm * R + r;
 #pragma unroll
-                    for (int i = 0; i < I; ++i)
-                        cmac(sf, OLD_REG ? oldf_r[o * I + i] : s_oldf[o * I + i], x[i]);
-                    const double2 v = to_d2(cmul(sf, s_tqf[o * Q + qm]));
-                    acc[o].x += v.x;
-                    acc[o].y += v.y;
+                for (int o = 0; o < N; ++o) {
+                    C s = {};
+#pragma unroll
+                    for (int i = 0; i < I; ++i) cmac(s, OLD_REG ? old_r[o * I + i] : s_old[o * I + i], x[u][i]);
+                    const C p = cmul(PLO_REG ? plo[o] : s_plo[o * R + r], s_tq[o * Q + qm]);
+                    aout[m + mc * o] = conv<CS>(cmul(s, p));
+                    if (RHO) {
+                        C sf = {};
+#pragma unroll
+                        for (int i = 0; i < I; ++i)
+                            cmac(sf, OLD_REG ? oldf_r[o * I + i] : s_oldf[o * I + i], x[u][i]);
+                        const double2 v = to_d2(cmul(sf, s_tqf[o * Q + qm]));
+                        acc[o].x += v.x;
+                        acc[o].y += v.y;
+                    }
                 }
             }
         }
@@ -492,50 +527,115 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
     }
 }
 
-// rho(t_n)[o] = compensated, fixed-order sum of the block partials.
-__global__ void __launch_bounds__(kBlock) rho_finalize_kernel(const double2 *partials, int n_blocks,
-                                                               int N, double2 *out) {
-    for (int o = 0; o < N; ++o) {
-        double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
-        for (int b = threadIdx.x; b < n_blocks; b += kBlock) {
+// rho(t_n)[o] = sum over the step's block partials, compensated and in a fixed
+// order: thread t takes blocks t, t + kFinBlock, ... (Neumaier sums), then a
+// fixed two-sum tree combines the threads.  A separate launch, so the kernel
+// boundary makes every partial visible without device-scope fences.
+constexpr int kFinBlock = 1024;
+template <int N>
+__global__ void __launch_bounds__(kFinBlock) rho_finalize_kernel(const double2 *__restrict__ partials,
+                                                                  int n_blocks, double2 *out) {
+    constexpr int U = N >= 16 ? 1 : 16 / N;   // rows of partials in flight per thread
+    const int t = threadIdx.x;
+    double sr[N], cr[N], si[N], ci[N];
+#pragma unroll
+    for (int o = 0; o < N; ++o) sr[o] = cr[o] = si[o] = ci[o] = 0.0;
+    int b = t;
+    for (; b + (U - 1) * kFinBlock < n_blocks; b += U * kFinBlock) {
+        double2 v[U][N];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int o = 0; o < N; ++o) v[u][o] = partials[(size_t)(b + u * kFinBlock) * N + o];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int o = 0; o < N; ++o) {
+                neumaier(sr[o], cr[o], v[u][o].x);
+                neumaier(si[o], ci[o], v[u][o].y);
+            }
+    }
+    for (; b < n_blocks; b += kFinBlock) {
+#pragma unroll
+        for (int o = 0; o < N; ++o) {
             const double2 v = partials[(size_t)b * N + o];
-            neumaier(sr, cr, v.x);
-            neumaier(si, ci, v.y);
+            neumaier(sr[o], cr[o], v.x);
+            neumaier(si[o], ci[o], v.y);
         }
-        const double2 r = block_sum_compensated(sr, cr, si, ci);
-        if (threadIdx.x == 0) out[o] = r;
+    }
+#pragma unroll
+    for (int o = 0; o < N; ++o) {
+        double a0 = sr[o], a1 = cr[o], a2 = si[o], a3 = ci[o];
+        block_reduce_pairs<kFinBlock>(a0, a1, a2, a3);
+        if (t == 0) out[o] = make_double2(a0 + a1, a2 + a3);
     }
 }
 
-template <int N, typename T, bool RHO, bool GROW>
+// Factor products of the full-window digit split: t_lo[o][v] over digits
+// 0..d_lo-1, t_mid[o][v] over d_lo..d_lo+d_mid-1, t_hi[o][v] over the rest,
+// interior (tab) and final-point (tabf) classes.  Step-independent for n > L.
+__global__ void __launch_bounds__(kBlock) plan_tables_kernel(const PlanArgs a) {
+    const int N = a.N;
+    const long long n_lo = (long long)N * a.R, n_mid = (long long)N * a.Q, n_hi = (long long)N * a.grid;
+    const long long total = n_lo + n_mid + n_hi;
+    const double2 one = make_double2(1.0, 0.0);
+    for (long long idx = (long long)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * kBlock) {
+        long long k, v;
+        int o, j0, nd, width;
+        double2 *out, *outf;
+        if (idx < n_lo) {
+            k = idx; width = a.R; j0 = 0; nd = a.d_lo; out = a.t_lo; outf = a.t_lof;
+        } else if (idx < n_lo + n_mid) {
+            k = idx - n_lo; width = a.Q; j0 = a.d_lo; nd = a.d_mid; out = a.t_mid; outf = a.t_midf;
+        } else {
+            k = idx - n_lo - n_mid; width = a.grid; j0 = a.d_lo + a.d_mid; nd = a.n_digits - j0;
+            out = a.t_hi; outf = a.t_hif;
+        }
+        o = (int)(k / width);
+        v = k % width;
+        double2 p = one, pf = one;
+        for (int j = 0; j < nd; ++j) {
+            const int dg = (int)(v % N);
+            v /= N;
+            p = cmul(p, a.bank[(size_t)a.tab[j0 + j] * (N * N) + o * N + dg]);
+            pf = cmul(pf, a.bank[(size_t)a.tabf[j0 + j] * (N * N) + o * N + dg]);
+        }
+        out[k] = p;
+        outf[k] = pf;
+    }
+}
+
+template <int N, typename S, typename T, bool RHO, bool GROW>
 hipError_t launch_step_t(const StepArgs &a, int grid, hipStream_t st) {
     using C = typename Cx<T>::type;
     const StepLds lay = step_lds_layout(N, (int)sizeof(C), RHO, GROW ? 1 : N, a.R, a.Q, N <= 4);
-    hipLaunchKernelGGL((step_kernel<N, T, RHO, GROW>), dim3(grid), dim3(kBlock), lay.total, st, a);
+    hipLaunchKernelGGL((step_kernel<N, S, T, RHO, GROW>), dim3(grid), dim3(kBlock), lay.total, st, a);
     return hipGetLastError();
 }
 
-template <int N, typename T>
+template <int N, typename S, typename T>
 hipError_t launch_step_n(bool rho, bool grow, const StepArgs &a, int grid, hipStream_t st) {
-    if (rho) return grow ? launch_step_t<N, T, true, true>(a, grid, st) : launch_step_t<N, T, true, false>(a, grid, st);
-    return grow ? launch_step_t<N, T, false, true>(a, grid, st) : launch_step_t<N, T, false, false>(a, grid, st);
+    if (rho)
+        return grow ? launch_step_t<N, S, T, true, true>(a, grid, st) : launch_step_t<N, S, T, true, false>(a, grid, st);
+    return grow ? launch_step_t<N, S, T, false, true>(a, grid, st) : launch_step_t<N, S, T, false, false>(a, grid, st);
 }
 
-template <typename T>
+template <typename S, typename T>
 hipError_t launch_step_dt(int N, bool rho, bool grow, const StepArgs &a, int grid, hipStream_t st) {
     switch (N) {
-    case 1: return launch_step_n<1, T>(rho, grow, a, grid, st);
-    case 4: return launch_step_n<4, T>(rho, grow, a, grid, st);
-    case 9: return launch_step_n<9, T>(rho, grow, a, grid, st);
-    case 16: return launch_step_n<16, T>(rho, grow, a, grid, st);
+    case 1: return launch_step_n<1, S, T>(rho, grow, a, grid, st);
+    case 4: return launch_step_n<4, S, T>(rho, grow, a, grid, st);
+    case 9: return launch_step_n<9, S, T>(rho, grow, a, grid, st);
+    case 16: return launch_step_n<16, S, T>(rho, grow, a, grid, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-size_t step_lds_bytes(int N, bool c64, bool with_rho, bool grow, int R, int Q) {
-    return step_lds_layout(N, c64 ? 8 : 16, with_rho, grow ? 1 : N, R, Q, N <= 4).total;
+size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q) {
+    return step_lds_layout(N, prec == kPrecC64 ? 8 : 16, with_rho, grow ? 1 : N, R, Q, N <= 4).total;
 }
 
 hipError_t launch_g_quad(const QuadArgs &a, int n_t, double2 *g, hipStream_t st) {
@@ -548,23 +648,40 @@ hipError_t launch_tables(const TablesArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_init_tensor(int N, bool c64, const double2 *rho0, const double2 *bank,
+hipError_t launch_init_tensor(int N, int prec, const double2 *rho0, const double2 *bank,
                               int self_end_tab, void *a0, hipStream_t st) {
     const double2 *se = bank + (size_t)self_end_tab * N * N;
-    if (c64) hipLaunchKernelGGL(init_tensor_kernel<float2>, dim3(1), dim3(64), 0, st, rho0, se, (float2 *)a0, N);
+    if (prec != kPrecC128) hipLaunchKernelGGL(init_tensor_kernel<float2>, dim3(1), dim3(64), 0, st, rho0, se, (float2 *)a0, N);
     else hipLaunchKernelGGL(init_tensor_kernel<double2>, dim3(1), dim3(64), 0, st, rho0, se, (double2 *)a0, N);
     return hipGetLastError();
 }
 
-hipError_t launch_step(int N, bool c64, bool with_rho, bool grow, const StepArgs &a, int grid,
+hipError_t launch_step(int N, int prec, bool with_rho, bool grow, const StepArgs &a, int grid,
                        hipStream_t st) {
-    return c64 ? launch_step_dt<float>(N, with_rho, grow, a, grid, st)
-               : launch_step_dt<double>(N, with_rho, grow, a, grid, st);
+    switch (prec) {
+    case kPrecC128: return launch_step_dt<double, double>(N, with_rho, grow, a, grid, st);
+    case kPrecC64: return launch_step_dt<float, float>(N, with_rho, grow, a, grid, st);
+    case kPrecC64F64: return launch_step_dt<float, double>(N, with_rho, grow, a, grid, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *out,
                                hipStream_t st) {
-    hipLaunchKernelGGL(rho_finalize_kernel, dim3(1), dim3(kBlock), 0, st, partials, n_blocks, N, out);
+    switch (N) {
+    case 1: hipLaunchKernelGGL(rho_finalize_kernel<1>, dim3(1), dim3(kFinBlock), 0, st, partials, n_blocks, out); break;
+    case 4: hipLaunchKernelGGL(rho_finalize_kernel<4>, dim3(1), dim3(kFinBlock), 0, st, partials, n_blocks, out); break;
+    case 9: hipLaunchKernelGGL(rho_finalize_kernel<9>, dim3(1), dim3(kFinBlock), 0, st, partials, n_blocks, out); break;
+    case 16: hipLaunchKernelGGL(rho_finalize_kernel<16>, dim3(1), dim3(kFinBlock), 0, st, partials, n_blocks, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_tables(const PlanArgs &a, hipStream_t st) {
+    const long long total = (long long)a.N * (a.R + a.Q + a.grid);
+    const int grid = (int)std::min<long long>(1024, (total + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(plan_tables_kernel, dim3(grid), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 

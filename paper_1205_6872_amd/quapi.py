@@ -22,7 +22,8 @@ import numpy as np
 LIB_PATH = Path(__file__).resolve().parent / "_lib" / "libquapi.so"
 
 OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_STATE = 0, 1, 2, 3, 4
-C128, C64 = 0, 1
+C128, C64, C64_F64 = 0, 1, 2
+DTYPES = {"c128": C128, "c64": C64, "c64f64": C64_F64}
 BATH_OHMIC, BATH_TABLE = 0, 1
 SETUP_G, SETUP_ETA, SETUP_U, SETUP_K = 0, 1, 2, 3
 
@@ -129,7 +130,7 @@ class _ParamsHolder:
         n_tab = int(len(self.omega)) if self.omega is not None else 0
         bath = Bath(kind, float(xi), float(omega_c), _ptr(self.omega), _ptr(self.J), n_tab)
         self.p = Params(int(M), _ptr(self.s), _ptr(self.H), _ptr(self.rho0), bath, float(kT), float(dt),
-                        int(L), {"c128": C128, "c64": C64}[dtype])
+                        int(L), DTYPES[dtype])
 
     @classmethod
     def from_workload(cls, w, **over):

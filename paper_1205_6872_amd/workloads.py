@@ -52,7 +52,7 @@ class Workload:
     omega_c: float = 1.0
     omega_tab: Optional[np.ndarray] = None   # table nodes (strictly increasing, > 0)
     J_tab: Optional[np.ndarray] = None       # J at the nodes (>= 0)
-    dtype: str = "c128"                # "c128" | "c64"
+    dtype: str = "c128"                # "c128" | "c64" | "c64f64"
     meta: dict = field(default_factory=dict)
 
     @property

@@ -2,7 +2,8 @@
 
 Tolerances (per step n, on rho(t_n) as an M x M matrix):
   complex128   max|rho_gpu - rho_oracle| <= 1e-12 * max|rho_oracle|
-  complex64    max|rho_c64 - rho_ref| <= 1e-5 (absolute), trace drift <= 1e-6
+  complex64    max|rho_c64 - rho_ref| <= 1e-5 (absolute); trace drift <= 1e-6 with
+               FP64 arithmetic (c64f64), <= 1e-5 with FP32 arithmetic (c64)
 Setup values (G, eta, U, K) agree with the oracle to 1e-13 of their scale.
 
 Small cases run the whole propagation through both sides.  At the full
@@ -147,7 +148,8 @@ def _sampled_entry_check(w, dtype, tol):
     ms = np.unique(np.concatenate([[0, 1, mc // 2, mc - 1], rng.integers(0, mc, 48)]))
     with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
         rho = ctx.propagate(L, sel=[L])               # growth + first full-window step
-        assert abs(np.trace(rho[0]) - 1) <= (1e-12 if dtype == "c128" else 1e-6)
+        tr_tol = {"c128": 1e-12, "c64": 1e-6, "c64f64": 1e-7}[dtype]
+        assert abs(np.trace(rho[0]) - 1) <= tr_tol
         for n in [L + 1, L + 2]:
             a_in = {int(m): ctx.read_tensor(N * int(m), N) for m in ms}
             rho = ctx.propagate(1)
@@ -158,7 +160,7 @@ def _sampled_entry_check(w, dtype, tol):
                                  for o in range(N)])
                 worst = max(worst, np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))
             assert worst <= tol, (n, worst)
-            assert abs(np.trace(rho[0]) - 1) <= (1e-12 if dtype == "c128" else 1e-6)
+            assert abs(np.trace(rho[0]) - 1) <= tr_tol
 
 
 def test_headline_size_sampled_entries_c128():
@@ -169,25 +171,37 @@ def test_headline_size_sampled_entries_c64():
     _sampled_entry_check(W.spin_boson_l15("c64"), "c64", 2e-5)
 
 
-def test_c64_tier_against_oracle_small():
+def test_headline_size_sampled_entries_c64f64():
+    # only the complex64 rounding of the stored values remains
+    _sampled_entry_check(W.spin_boson_l15("c64f64"), "c64f64", 2e-7)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c64f64"])
+def test_c64_tiers_against_oracle_small(dtype):
     w = W.spin_boson_l7()
-    g = gpu_rho(w, 100, dtype="c64")
+    g = gpu_rho(w, 100, dtype=dtype)
     o = oracle_rho(w, 100)[1:]
     assert np.abs(g - o).max() <= 1e-5
     tr = np.trace(g, axis1=1, axis2=2)
     assert np.abs(tr - 1).max() <= 1e-6
 
 
-def test_c64_tier_against_c128_headline_workload():
-    w = W.spin_boson_l15("c64")
+# max|drho| and trace drift against complex128 over 150 steps at L = 15.  The
+# FP32-arithmetic tier rounds the factor tables to FP32 once, and the same
+# rounding enters every step, so its trace drift grows linearly with the step
+# count (about 3e-6 here, 4e-6 after 1000 steps); with FP64 arithmetic only the
+# storage rounding of 1e9 entries remains, which averages out in the trace.
+@pytest.mark.parametrize("dtype,max_drho,max_drift", [("c64", 1e-5, 1e-5), ("c64f64", 1e-5, 1e-6)])
+def test_c64_tiers_against_c128_headline_workload(dtype, max_drho, max_drift):
+    w = W.spin_boson_l15(dtype)
     n = 150
-    r64 = gpu_rho(w, n, dtype="c64")
+    r64 = gpu_rho(w, n, dtype=dtype)
     r128 = gpu_rho(w, n, dtype="c128")
     d = np.abs(r64 - r128).max()
     drift = np.abs(np.trace(r64, axis1=1, axis2=2) - np.trace(r128, axis1=1, axis2=2)).max()
-    print(f"c64 vs c128 over {n} steps: max|drho| = {d:.3e}, trace drift = {drift:.3e}", flush=True)
-    assert d <= 1e-5
-    assert drift <= 1e-6
+    print(f"{dtype} vs c128 over {n} steps: max|drho| = {d:.3e}, trace drift = {drift:.3e}", flush=True)
+    assert d <= max_drho
+    assert drift <= max_drift
 
 
 def test_async_with_torch_workspace_and_stream():
