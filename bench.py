@@ -8,9 +8,12 @@ synthetic (seeded parameters, no dataset).
 A timed "step" is one full-window propagation step: the step kernel reads the
 tensor once, writes it once, and produces per-block partial sums of rho(t_n)
 in the same pass; a small finalize kernel sums them.  The growth steps (n < L) and the device setup run first and
-are reported separately.  Both precision tiers run on the same workload:
-complex128 (the reported `value`) and the complex64 tier (`fp32_tier`), with
-max|drho| and trace drift of the tier against complex128.
+are reported separately.  Three precisions run on the same workload:
+complex128 (the reported `value`), the complex64 tier with FP32 arithmetic
+(`fp32_tier`), and complex64 storage with FP64 arithmetic
+(`c64_storage_f64_math`), each complex64 run with max|drho| and trace drift
+against complex128.  `copy_ceiling` is a plain device copy (torch copy_ of
+16 GiB) timed on the same GPU, for reference.
 
 Metric: Gelem/s = N^L * steps / seconds / 1e9, with the tensor resident in
 HBM.  `roofline` prices the step kernel against the HBM peak: algorithmic
@@ -19,7 +22,7 @@ the kernel's average duration from HIP events on the library's stream.
 `cpu_baseline` times the oracle (plain C, OpenMP) on a bounded sample of the
 same workload on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tiers c128,c64]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tiers c128,c64,c64f64]
                        [--no-cpu-baseline] [--traffic-json FILE]
 """
 from __future__ import annotations
@@ -69,7 +72,7 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
         del ctx
         torch.cuda.empty_cache()
     entries = N ** L
-    csize = 16 if dtype == "c128" else 8
+    csize = 16 if dtype == "c128" else 8   # bytes per stored entry
     bytes_per_launch = 2 * entries * csize
     kernel_ms = tm["step_ms"] / max(tm["step_launches"], 1)
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
@@ -80,6 +83,45 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
         finalize_ms=tm["finalize_ms"] / max(tm["finalize_launches"], 1), setup_ms=tm["setup_ms"],
         setup_wall_ms=setup_wall * 1e3, grow_ms=grow_ms, bytes_per_launch=bytes_per_launch,
         achieved_gbs=achieved, rho=rho)
+
+
+def measured_traffic(path: str, tier: str):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            tj = json.load(f)
+        src = os.path.join(ROOT, "paper_1205_6872_amd", "csrc", "quapi_kernels.hip")
+        with open(src, "rb") as f:
+            cur = hashlib.sha256(f.read()).hexdigest()
+        if tj.get("kernel_source_sha256") != cur:
+            return None
+        return tj.get(tier, {}).get("hbm_bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+
+
+def copy_ceiling(nbytes: int = 2 ** 34):
+    """Plain device read+write copy (torch copy_), GB/s counting read + write."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del a, b
+    torch.cuda.empty_cache()
+    return {"achieved": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "unit": "GB/s", "bytes": 2 * nbytes,
+            "kernel_ms": round(ms, 4), "kernel": "torch copy_ of 16 GiB float64"}
 
 
 def cpu_baseline(w, n_main: int = 2):
@@ -104,7 +146,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed full-window steps")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--tiers", default="c128,c64")
+    ap.add_argument("--tiers", default="c128,c64,c64f64")
+    ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step_kernel_traffic_l15.json"))
     args = ap.parse_args()
@@ -133,14 +176,7 @@ def main() -> int:
             f"{r['kernel_ms']:.3f} ms = {r['achieved_gbs']:.0f} GB/s")
     main_t = "c128" if "c128" in res else tiers[0]
     r = res[main_t]
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            with open(args.traffic_json) as f:
-                tj = json.load(f)
-            traffic = tj.get(main_t, {}).get("hbm_bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic(args.traffic_json, main_t)
     out = {
         "metric": "QUAPI step Gelem/s + HBM GB/s (FP64 vs FP32) at M=2 dk=15",
         "value": round(r["gelem_s"], 3),
@@ -165,17 +201,23 @@ def main() -> int:
         "growth_ms": round(r["grow_ms"], 3),
         "finalize_ms": round(r["finalize_ms"], 4),
     }
-    if "c64" in res and "c128" in res:
-        a, b = res["c64"], res["c128"]
+    for key, t in (("fp32_tier", "c64"), ("c64_storage_f64_math", "c64f64")):
+        if t not in res or "c128" not in res:
+            continue
+        a, b = res[t], res["c128"]
         d = float(np.abs(a["rho"] - b["rho"]).max())
         drift = float(np.abs(np.trace(a["rho"], axis1=1, axis2=2) - np.trace(b["rho"], axis1=1, axis2=2)).max())
-        out["fp32_tier"] = {
+        out[key] = {
+            "dtype": "f32" if t == "c64" else "f64", "storage": "complex64",
             "value": round(a["gelem_s"], 3), "unit": "Gelem/s", "ms_per_step": round(a["ms_per_step"], 4),
             "roofline": {"bound": "hbm", "achieved": round(a["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(a["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                         "kernel_ms": round(a["kernel_ms"], 4)},
-            "max_abs_drho_vs_f64": d, "trace_drift_vs_f64": drift,
+                         "traffic": measured_traffic(args.traffic_json, t),
+                         "kernel_ms": round(a["kernel_ms"], 4), "bytes_per_launch": a["bytes_per_launch"]},
+            "max_abs_drho_vs_f64": d, "trace_drift_vs_f64": drift, "steps_compared": len(a["rho"]),
         }
+    if not args.no_copy_ceiling:
+        out["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu_baseline:
         log("bench: cpu_baseline (oracle on the host)")
         cb = cpu_baseline(w.with_(dtype="c128"))
