@@ -211,7 +211,7 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_g, off_eta, off_U, off_s, off_H, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
-    size_t off_plan;
+    size_t off_plan, off_pairs;
     size_t total;
     int n_panels, n_tables, partial_blocks;
     DigitSplit main_split;   // digit split of the full-window steps
@@ -253,6 +253,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_glw = take(kGL * 8);
     l.off_partials = take((size_t)2 * l.partial_blocks * N * 16);   // double-buffered
     l.off_stage = take((size_t)kRhoStage * N * 16);
+    l.off_pairs = take((size_t)kRhoSlices * N * 2 * 16);
     // six FP64 factor tables of the full-window split: [N][R], [N][Q], [N][grid], x2 classes
     const DigitSplit &ms = l.main_split;
     l.off_plan = take((size_t)2 * N * (ms.R + ms.Q + ms.grid) * 16);
@@ -291,7 +292,7 @@ struct quapi_ctx {
     int step = 0;
     double2 *bank = nullptr, *g = nullptr, *eta = nullptr, *U = nullptr, *rho0_d = nullptr;
     double2 *partials[2] = {nullptr, nullptr};
-    double2 *stage = nullptr, *plan = nullptr;
+    double2 *stage = nullptr, *plan = nullptr, *pairs = nullptr;
     bool plan_ready = false;      // full-window factor tables computed
     std::vector<double> rho0_h;
     // host copies of uploaded inputs (kept alive until the uploads complete)
@@ -482,7 +483,7 @@ quapi_status enqueue_step(quapi_ctx *c, int n, double2 *out) {
             f1 = take_event(c);
             if (f0) (void)hipEventRecord(f0, c->side);
         }
-        e = launch_rho_finalize(N, c->partials[slot], sp.split.grid, out, c->side);
+        e = launch_rho_finalize(N, c->partials[slot], sp.split.grid, c->pairs, out, c->side);
         if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "rho finalize launch: %s", hipGetErrorString(e));
         if (c->timing && f0 && f1) {
             (void)hipEventRecord(f1, c->side);
@@ -709,6 +710,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->partials[0] = (double2 *)(w + lay.off_partials);
     c->partials[1] = c->partials[0] + (size_t)lay.partial_blocks * N;
     c->stage = (double2 *)(w + lay.off_stage);
+    c->pairs = (double2 *)(w + lay.off_pairs);
     c->plan = (double2 *)(w + lay.off_plan);
 
     c->s_h.assign(p->s, p->s + M);

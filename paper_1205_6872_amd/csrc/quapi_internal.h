@@ -99,7 +99,10 @@ hipError_t launch_init_tensor(int N, int prec, const double2 *rho0, const double
                               int self_end_tab, void *a0, hipStream_t st);
 hipError_t launch_step(int N, int prec, bool with_rho, bool grow, const StepArgs &a, int grid,
                        hipStream_t st);
-hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *out,
+// Sums the block partials of rho into out[0..N): two launches on st, using
+// pairs (kRhoSlices * N * 2 complex) as scratch.
+constexpr int kRhoSlices = 256;
+hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *pairs, double2 *out,
                                hipStream_t st);
 hipError_t launch_plan_tables(const PlanArgs &a, hipStream_t st);
 size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q);

@@ -527,26 +527,32 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
     }
 }
 
-// rho(t_n)[o] = sum over the step's block partials, compensated and in a fixed
-// order: thread t takes blocks t, t + kFinBlock, ... (Neumaier sums), then a
-// fixed two-sum tree combines the threads.  A separate launch, so the kernel
-// boundary makes every partial visible without device-scope fences.
-constexpr int kFinBlock = 1024;
+// rho(t_n)[o] = sum over the step's block partials, compensated, in a fixed
+// order, in two launches on the side stream (each launch boundary makes the
+// previous writes visible without device-scope fences):
+//   rho_slice_kernel   kSlices blocks; block b sums rows [b*rows/kSlices,
+//                      (b+1)*rows/kSlices) -- thread t takes rows t, t+kBlock, ...
+//                      with Neumaier sums, then a fixed two-sum tree -- and
+//                      writes a (sum, compensation) pair per o;
+//   rho_final_kernel   one block combines the kSlices pairs in a fixed tree.
+constexpr int kSlices = kRhoSlices;
 template <int N>
-__global__ void __launch_bounds__(kFinBlock) rho_finalize_kernel(const double2 *__restrict__ partials,
-                                                                  int n_blocks, double2 *out) {
-    constexpr int U = N >= 16 ? 1 : 16 / N;   // rows of partials in flight per thread
+__global__ void __launch_bounds__(kBlock) rho_slice_kernel(const double2 *__restrict__ partials, int rows,
+                                                            double2 *__restrict__ pairs) {
     const int t = threadIdx.x;
+    const int b = blockIdx.x;
+    const long long r0 = (long long)rows * b / kSlices, r1 = (long long)rows * (b + 1) / kSlices;
+    constexpr int U = N >= 16 ? 1 : 16 / N;   // rows in flight per thread
     double sr[N], cr[N], si[N], ci[N];
 #pragma unroll
     for (int o = 0; o < N; ++o) sr[o] = cr[o] = si[o] = ci[o] = 0.0;
-    int b = t;
-    for (; b + (U - 1) * kFinBlock < n_blocks; b += U * kFinBlock) {
+    long long r = r0 + t;
+    for (; r + (long long)(U - 1) * kBlock < r1; r += (long long)U * kBlock) {
         double2 v[U][N];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int o = 0; o < N; ++o) v[u][o] = partials[(size_t)(b + u * kFinBlock) * N + o];
+            for (int o = 0; o < N; ++o) v[u][o] = partials[(size_t)(r + (long long)u * kBlock) * N + o];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -555,10 +561,10 @@ __global__ void __launch_bounds__(kFinBlock) rho_finalize_kernel(const double2 *
                 neumaier(si[o], ci[o], v[u][o].y);
             }
     }
-    for (; b < n_blocks; b += kFinBlock) {
+    for (; r < r1; r += kBlock) {
 #pragma unroll
         for (int o = 0; o < N; ++o) {
-            const double2 v = partials[(size_t)b * N + o];
+            const double2 v = partials[(size_t)r * N + o];
             neumaier(sr[o], cr[o], v.x);
             neumaier(si[o], ci[o], v.y);
         }
@@ -566,7 +572,22 @@ __global__ void __launch_bounds__(kFinBlock) rho_finalize_kernel(const double2 *
 #pragma unroll
     for (int o = 0; o < N; ++o) {
         double a0 = sr[o], a1 = cr[o], a2 = si[o], a3 = ci[o];
-        block_reduce_pairs<kFinBlock>(a0, a1, a2, a3);
+        block_reduce_pairs<kBlock>(a0, a1, a2, a3);
+        if (t == 0) {
+            pairs[((size_t)b * N + o) * 2] = make_double2(a0, a2);
+            pairs[((size_t)b * N + o) * 2 + 1] = make_double2(a1, a3);
+        }
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kSlices) rho_final_kernel(const double2 *__restrict__ pairs, double2 *out) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int o = 0; o < N; ++o) {
+        const double2 sv = pairs[((size_t)t * N + o) * 2], cv = pairs[((size_t)t * N + o) * 2 + 1];
+        double a0 = sv.x, a1 = cv.x, a2 = sv.y, a3 = cv.y;
+        block_reduce_pairs<kSlices>(a0, a1, a2, a3);
         if (t == 0) out[o] = make_double2(a0 + a1, a2 + a3);
     }
 }
@@ -666,13 +687,19 @@ hipError_t launch_step(int N, int prec, bool with_rho, bool grow, const StepArgs
     }
 }
 
-hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *out,
+hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *pairs, double2 *out,
                                hipStream_t st) {
     switch (N) {
-    case 1: hipLaunchKernelGGL(rho_finalize_kernel<1>, dim3(1), dim3(kFinBlock), 0, st, partials, n_blocks, out); break;
-    case 4: hipLaunchKernelGGL(rho_finalize_kernel<4>, dim3(1), dim3(kFinBlock), 0, st, partials, n_blocks, out); break;
-    case 9: hipLaunchKernelGGL(rho_finalize_kernel<9>, dim3(1), dim3(kFinBlock), 0, st, partials, n_blocks, out); break;
-    case 16: hipLaunchKernelGGL(rho_finalize_kernel<16>, dim3(1), dim3(kFinBlock), 0, st, partials, n_blocks, out); break;
+#define QUAPI_FIN(NV)                                                                                  \
+    case NV:                                                                                           \
+        hipLaunchKernelGGL(rho_slice_kernel<NV>, dim3(kSlices), dim3(kBlock), 0, st, partials, n_blocks, pairs); \
+        hipLaunchKernelGGL(rho_final_kernel<NV>, dim3(1), dim3(kSlices), 0, st, pairs, out);           \
+        break;
+        QUAPI_FIN(1)
+        QUAPI_FIN(4)
+        QUAPI_FIN(9)
+        QUAPI_FIN(16)
+#undef QUAPI_FIN
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

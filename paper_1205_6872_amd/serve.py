@@ -1,0 +1,192 @@
+"""Continuous-batching server for QUAPI propagation requests on one GPU.
+
+Requests (different M, L, bath, kT, step counts and precisions) arrive over
+time.  The server:
+
+* admits them in arrival order whenever a slot is free and the request's
+  device footprint (the library's ``footprint``) fits in the remaining HBM
+  budget -- the paper's "did not fit on the GPU" becomes "wait for memory";
+* keeps every admitted request's tensor resident in its own workspace (a
+  torch uint8 tensor) and runs it on its own HIP stream, so the work of
+  different requests overlaps on the device;
+* enqueues each request's steps in chunks through ``propagate_async``,
+  round-robin over the active requests, at most two chunks in flight per
+  request, so a long request never blocks a short one behind it;
+* records arrival, admission and completion times and reports p50/p99
+  latency (arrival -> rho on the host) and aggregate throughput.
+
+Every request returns rho(t_k) for k = 0..n_steps ('allPoints', Sec. IV of
+the paper).  The kernels are deterministic and each request has its own
+context, so a request's result does not depend on what else is running.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import quapi as Q
+
+__all__ = ["Server", "RequestResult", "work_entries", "summarize"]
+
+
+def work_entries(N: int, L: int, n_steps: int) -> int:
+    """Tensor entries written over a run: step n writes N^min(n+1, L) entries."""
+    return int(sum(N ** min(n + 1, L) for n in range(1, n_steps + 1)))
+
+
+@dataclass
+class RequestResult:
+    index: int
+    name: str
+    M: int
+    L: int
+    dtype: str
+    n_steps: int
+    arrival_s: float
+    admit_s: float
+    finish_s: float
+    rho: np.ndarray
+    entries: int
+
+    @property
+    def latency_s(self) -> float:
+        return self.finish_s - self.arrival_s
+
+
+@dataclass
+class _Active:
+    w: object
+    index: int
+    ctx: Q.Context
+    stream: object
+    rho_dev: object
+    slot: int
+    fp: int
+    admit_s: float
+    enqueued: int = 0
+    events: deque = field(default_factory=deque)
+
+
+class Server:
+    """Admission by footprint, one stream and context per active request."""
+
+    def __init__(self, max_active: int = 8, hbm_budget: Optional[int] = None, chunk_steps: int = 32,
+                 device: str = "cuda:0", progress: bool = False):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.max_active = max_active
+        self.chunk = chunk_steps
+        self.progress = progress
+        self.streams = [torch.cuda.Stream(device) for _ in range(max_active)]
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(device)
+            hbm_budget = int(free * 0.85)
+        self.budget = int(hbm_budget)
+
+    def _admit(self, w, index: int, slot: int, now: float) -> _Active:
+        torch = self.torch
+        p = Q.params_from(w)
+        stream = self.streams[slot]
+        ctx = Q.create_in_torch(p, stream=stream, device=self.device)
+        rho_dev = torch.empty((w.n_steps + 1, w.N, 2), dtype=torch.float64, device=self.device)
+        ctx.propagate_async(0, [0], rho_dev.data_ptr())          # rho(t_0)
+        return _Active(w=w, index=index, ctx=ctx, stream=stream, rho_dev=rho_dev, slot=slot,
+                       fp=Q.footprint(p), admit_s=now)
+
+    def run(self, requests, realtime: bool = True) -> list[RequestResult]:
+        """Serve the requests (each with meta['arrival_s']); returns results in index order."""
+        torch = self.torch
+        order = sorted(range(len(requests)), key=lambda i: requests[i].meta.get("arrival_s", 0.0))
+        pending = deque(order)
+        waiting: deque = deque()
+        active: dict[int, _Active] = {}
+        free_slots = list(range(self.max_active))[::-1]
+        used = 0
+        fps = {}
+        results: list[RequestResult] = []
+        t0 = time.perf_counter()
+
+        def now() -> float:
+            return time.perf_counter() - t0
+
+        while pending or waiting or active:
+            progressed = False
+            t = now()
+            while pending and (not realtime or requests[pending[0]].meta.get("arrival_s", 0.0) <= t):
+                waiting.append(pending.popleft())
+            # admission in arrival order, by slot and HBM footprint
+            while waiting and free_slots:
+                i = waiting[0]
+                if i not in fps:
+                    fps[i] = Q.footprint(Q.params_from(requests[i]))
+                if fps[i] > self.budget:
+                    raise Q.QuapiError(Q.ERR_NOMEM, f"request {i} needs {fps[i]} bytes, more than the budget")
+                if used + fps[i] > self.budget:
+                    break
+                waiting.popleft()
+                slot = free_slots.pop()
+                a = self._admit(requests[i], i, slot, now())
+                used += a.fp
+                active[slot] = a
+                progressed = True
+            # enqueue the next chunk of every active request (two chunks in flight at most)
+            for a in active.values():
+                while a.events and a.events[0].query():
+                    a.events.popleft()
+                if a.enqueued < a.w.n_steps and len(a.events) < 2:
+                    k = min(self.chunk, a.w.n_steps - a.enqueued)
+                    off = (a.enqueued + 1) * a.w.N * 16
+                    a.ctx.propagate_async(k, None, a.rho_dev.data_ptr() + off)
+                    a.enqueued += k
+                    ev = torch.cuda.Event()
+                    ev.record(a.stream)
+                    a.events.append(ev)
+                    progressed = True
+            # completions
+            for slot in list(active):
+                a = active[slot]
+                if a.enqueued == a.w.n_steps and all(e.query() for e in a.events):
+                    with torch.cuda.stream(a.stream):
+                        rho = a.rho_dev.cpu().numpy()
+                    finish = now()
+                    a.ctx.destroy()
+                    used -= a.fp
+                    free_slots.append(slot)
+                    del active[slot]
+                    w = a.w
+                    results.append(RequestResult(
+                        index=a.index, name=w.name, M=w.M, L=w.L, dtype=w.dtype, n_steps=w.n_steps,
+                        arrival_s=(w.meta.get("arrival_s", 0.0) if realtime else 0.0), admit_s=a.admit_s,
+                        finish_s=finish, rho=rho.view(np.complex128).reshape(w.n_steps + 1, w.M, w.M),
+                        entries=work_entries(w.N, w.L, w.n_steps)))
+                    progressed = True
+                    if self.progress and len(results) % 16 == 0:
+                        print(f"serve: {len(results)} done at {finish:.1f} s, {len(active)} active, "
+                              f"{len(waiting)} waiting", flush=True)
+            if not progressed:
+                if not active and pending and realtime:
+                    time.sleep(max(0.0, min(0.01, requests[pending[0]].meta.get("arrival_s", 0.0) - now())))
+                else:
+                    time.sleep(0.0002)
+        results.sort(key=lambda r: r.index)
+        return results
+
+
+def summarize(results: list[RequestResult]) -> dict:
+    lat = np.array([r.latency_s for r in results])
+    makespan = max(r.finish_s for r in results) - min(r.arrival_s for r in results)
+    total = sum(r.entries for r in results)
+    return {
+        "requests": len(results),
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_latency_s": float(lat.mean()),
+        "makespan_s": float(makespan),
+        "gelem_s": total / makespan / 1e9,
+        "entries": int(total),
+    }

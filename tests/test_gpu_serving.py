@@ -1,0 +1,58 @@
+"""Serving loop: each request's result is the same alone and in the mix, and
+admission by HBM footprint holds requests back without changing results."""
+import numpy as np
+import pytest
+
+from paper_1205_6872_amd import quapi as Q
+from paper_1205_6872_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_trace(n=12):
+    reqs = W.serving_requests(n=n, L_range=(3, 7), steps_range=(20, 80), max_entries=2 ** 20)
+    return reqs
+
+
+def _alone(w):
+    with Q.create(Q.params_from(w)) as ctx:
+        r = ctx.propagate(w.n_steps, sel=list(range(w.n_steps + 1)))
+    return r
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix():
+    from paper_1205_6872_amd.serve import Server, summarize
+    reqs = _small_trace()
+    print("requests:", [(w.M, w.L, w.dtype, w.n_steps) for w in reqs], flush=True)
+    res = Server(max_active=4, chunk_steps=7).run(reqs, realtime=False)
+    assert [r.index for r in res] == list(range(len(reqs)))
+    for w, r in zip(reqs, res):
+        alone = _alone(w)
+        assert np.array_equal(r.rho, alone), (w.name, np.abs(r.rho - alone).max())
+        tr = np.trace(r.rho, axis1=1, axis2=2)
+        # FP32 arithmetic (c64) drifts the trace by up to ~1e-6 per 100 steps
+        assert np.abs(tr - 1).max() <= {"c128": 1e-12, "c64": 1e-5, "c64f64": 1e-6}[w.dtype]
+    s = summarize(res)
+    assert s["requests"] == len(reqs) and s["p99_latency_s"] >= s["p50_latency_s"] > 0
+
+
+def test_admission_waits_for_memory():
+    from paper_1205_6872_amd.serve import Server
+    reqs = _small_trace(6)
+    fps = [Q.footprint(Q.params_from(w)) for w in reqs]
+    budget = max(fps) + min(fps)        # at most a couple of requests resident at once
+    res = Server(max_active=6, hbm_budget=budget, chunk_steps=16).run(reqs, realtime=False)
+    for w, r in zip(reqs, res):
+        assert np.array_equal(r.rho, _alone(w))
+    # with the cap, some request was admitted only after another one finished
+    admits = sorted(r.admit_s for r in res)
+    finishes = sorted(r.finish_s for r in res)
+    assert admits[-1] >= finishes[0]
+
+
+def test_request_larger_than_budget_is_refused():
+    from paper_1205_6872_amd.serve import Server
+    reqs = _small_trace(2)
+    with pytest.raises(Q.QuapiError) as ei:
+        Server(max_active=2, hbm_budget=1000).run(reqs, realtime=False)
+    assert ei.value.status == Q.ERR_NOMEM
