@@ -15,6 +15,13 @@ complex128 (the reported `value`), the complex64 tier with FP32 arithmetic
 against complex128.  `copy_ceiling` is a plain device copy (torch copy_ of
 16 GiB) timed on the same GPU, for reference.
 
+`serving` replays the seeded Poisson trace of mixed requests (M in {2,3,4},
+L up to N^L <= 2^28, 50-1000 steps, complex64/complex128, 20 requests/s) in
+real time through the continuous-batching server and reports p50/p99
+latency (arrival -> rho on the host) and aggregate Gelem/s.  By default it
+serves the first 64 requests of the 512-request trace (about 3 s of
+arrivals) so the run stays within minutes; --serve-requests 512 serves all.
+
 Metric: Gelem/s = N^L * steps / seconds / 1e9, with the tensor resident in
 HBM.  `roofline` prices the step kernel against the HBM peak: algorithmic
 bytes per launch = 2 * N^L * sizeof(complex) (one read, one write), divided by
@@ -124,6 +131,20 @@ def copy_ceiling(nbytes: int = 2 ** 34):
             "kernel_ms": round(ms, 4), "kernel": "torch copy_ of 16 GiB float64"}
 
 
+def serve_trace(n_requests: int):
+    """Serve the first n_requests of the seeded 512-request trace in real time."""
+    from paper_1205_6872_amd import workloads as W
+    from paper_1205_6872_amd.serve import Server, summarize
+    reqs = W.serving_requests()[:n_requests]
+    log(f"bench: serving {len(reqs)} requests ({reqs[-1].meta['arrival_s']:.1f} s of arrivals)")
+    res = Server(max_active=8, chunk_steps=32, progress=True).run(reqs, realtime=True)
+    s = summarize(res)
+    s.update({"trace": "seeded Poisson, 20 requests/s, seed 2026", "sample": f"first {len(reqs)} of 512",
+              "max_active": 8, "rho_every_step": True,
+              "by_dtype": {d: sum(1 for r in res if r.dtype == d) for d in sorted({r.dtype for r in res})}})
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+
+
 def cpu_baseline(w, n_main: int = 2):
     """Oracle on the host: growth to L, then n_main full-window steps (timed)."""
     import numpy as np
@@ -148,6 +169,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tiers", default="c128,c64,c64f64")
     ap.add_argument("--no-copy-ceiling", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64, help="0 skips the serving run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step_kernel_traffic_l15.json"))
     args = ap.parse_args()
@@ -218,6 +240,8 @@ def main() -> int:
         }
     if not args.no_copy_ceiling:
         out["copy_ceiling"] = copy_ceiling()
+    if args.serve_requests > 0:
+        out["serving"] = serve_trace(args.serve_requests)
     if not args.no_cpu_baseline:
         log("bench: cpu_baseline (oracle on the host)")
         cb = cpu_baseline(w.with_(dtype="c128"))

@@ -26,6 +26,9 @@ thread_local std::string g_last_error;
 constexpr size_t kAlign = 256;
 constexpr int kRhoStage = 1024;          // rho slots of the blocking-call staging buffer
 constexpr double kOhmicCutoffFactor = 46.0;  // exp(-46) ~ 1e-20 of the integrand left out
+// Full-window steps of tensors up to this many entries are replayed from a
+// captured graph of two steps: they are launch-bound, not HBM-bound.
+constexpr size_t kGraphMaxEntries = size_t(1) << 22;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -211,7 +214,7 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_g, off_eta, off_U, off_s, off_H, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
-    size_t off_plan, off_pairs;
+    size_t off_plan, off_pairs, off_sink;
     size_t total;
     int n_panels, n_tables, partial_blocks;
     DigitSplit main_split;   // digit split of the full-window steps
@@ -254,6 +257,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_partials = take((size_t)2 * l.partial_blocks * N * 16);   // double-buffered
     l.off_stage = take((size_t)kRhoStage * N * 16);
     l.off_pairs = take((size_t)kRhoSlices * N * 2 * 16);
+    l.off_sink = take(sizeof(RhoSink));
     // six FP64 factor tables of the full-window split: [N][R], [N][Q], [N][grid], x2 classes
     const DigitSplit &ms = l.main_split;
     l.off_plan = take((size_t)2 * N * (ms.R + ms.Q + ms.grid) * 16);
@@ -293,6 +297,10 @@ struct quapi_ctx {
     double2 *bank = nullptr, *g = nullptr, *eta = nullptr, *U = nullptr, *rho0_d = nullptr;
     double2 *partials[2] = {nullptr, nullptr};
     double2 *stage = nullptr, *plan = nullptr, *pairs = nullptr;
+    RhoSink *sink = nullptr;
+    // two captured full-window steps (A[0] -> A[1] -> A[0]), without / with rho
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    bool graph_failed = false;
     bool plan_ready = false;      // full-window factor tables computed
     std::vector<double> rho0_h;
     // host copies of uploaded inputs (kept alive until the uploads complete)
@@ -401,15 +409,15 @@ StepPlan plan_step(const quapi_ctx *c, int n) {
     return sp;
 }
 
-// Enqueue step n (1-based) and, if out != NULL, rho(t_n) into out[0..N).
-quapi_status enqueue_step(quapi_ctx *c, int n, double2 *out) {
+// Step arguments of global step n, checked against the buffers, with the
+// full-window factor tables (computed on first use).
+quapi_status prepare_step(quapi_ctx *c, int n, bool rho, StepPlan *out) {
     StepPlan sp = plan_step(c, n);
     StepArgs &a = sp.args;
     const int N = c->N;
     const size_t cap = c->lay.a_bytes / c->csize;
     const size_t in_entries = (size_t)a.m_count * (sp.grow ? 1 : N);
     const size_t out_entries = (size_t)a.m_count * N;
-    const bool rho = out != nullptr;
     const size_t lds = step_lds_bytes(N, c->prec, rho, sp.grow, a.R, a.Q);
     // host-side launch checks: the grid must tile m exactly and stay in the buffers
     if ((long long)sp.split.grid * a.R * a.Q != a.m_count || in_entries > cap || out_entries > cap ||
@@ -452,6 +460,18 @@ quapi_status enqueue_step(quapi_ctx *c, int n, double2 *out) {
         a.t_hif = t_hif;
     }
     a.grid = sp.split.grid;
+    *out = sp;
+    return QUAPI_OK;
+}
+
+// Enqueue step n (1-based); with rho, also rho(t_n) into the sink's next slot.
+// The finalize runs on the side stream, overlapped with the next step.
+quapi_status enqueue_step(quapi_ctx *c, int n, bool rho) {
+    StepPlan sp;
+    quapi_status st = prepare_step(c, n, rho, &sp);
+    if (st != QUAPI_OK) return st;
+    StepArgs &a = sp.args;
+    const int N = c->N;
     a.a_in = c->A[c->cur];
     a.a_out = c->A[1 - c->cur];
     const int slot = c->pslot;
@@ -483,7 +503,7 @@ quapi_status enqueue_step(quapi_ctx *c, int n, double2 *out) {
             f1 = take_event(c);
             if (f0) (void)hipEventRecord(f0, c->side);
         }
-        e = launch_rho_finalize(N, c->partials[slot], sp.split.grid, c->pairs, out, c->side);
+        e = launch_rho_finalize(N, c->partials[slot], sp.split.grid, c->pairs, c->sink, c->side);
         if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "rho finalize launch: %s", hipGetErrorString(e));
         if (c->timing && f0 && f1) {
             (void)hipEventRecord(f1, c->side);
@@ -494,6 +514,40 @@ quapi_status enqueue_step(quapi_ctx *c, int n, double2 *out) {
     }
     c->cur = 1 - c->cur;
     c->step = n;
+    return QUAPI_OK;
+}
+
+// Capture two full-window steps A[0] -> A[1] -> A[0] (finalizes on the same
+// stream) into an executable graph.  Every argument of every node is fixed:
+// the step tables are the same for all n > L and rho goes through the sink.
+quapi_status build_graph(quapi_ctx *c, bool rho) {
+    StepPlan sp;
+    quapi_status st = prepare_step(c, c->L + 1, rho, &sp);  // plan tables exist by now
+    if (st != QUAPI_OK) return st;
+    hipGraph_t g = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        StepArgs a = sp.args;
+        a.a_in = c->A[k];
+        a.a_out = c->A[1 - k];
+        a.partials = c->partials[k];
+        e = launch_step(c->N, c->prec, rho, false, a, sp.split.grid, c->stream);
+        if (e == hipSuccess && rho)
+            e = launch_rho_finalize(c->N, c->partials[k], sp.split.grid, c->pairs, c->sink, c->stream);
+    }
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(c, QUAPI_ERR_DEVICE, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&c->graph[rho ? 1 : 0], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->graph[rho ? 1 : 0] = nullptr;
+        return fail(c, QUAPI_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
     return QUAPI_OK;
 }
 
@@ -549,6 +603,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
                                   (size_t)staged * N * 16, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         staged = 0;
+        HIP_TRY(c, launch_set_sink(c->sink, c->stage, c->stream));
         return QUAPI_OK;
     };
     if (sel && si < n_sel && sel[si] == 0) {  // rho(t_0) = rho0
@@ -559,12 +614,39 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
         ++si;
         ++written;
     }
+    // finalized rho values land at sink->base + k*N in step order
+    HIP_TRY(c, launch_set_sink(c->sink, dev_out ? dev_out + (size_t)written * N : c->stage, c->stream));
+    const size_t entries = (size_t)ipow_ll(c->N, c->L);
+    const bool graphs = !c->timing && !c->graph_failed && entries <= kGraphMaxEntries;
     const int first = c->step + 1, last = c->step + n_steps;
     for (int n = first; n <= last; ++n) {
         const bool selected = !sel || (si < n_sel && sel[si] == n);
-        double2 *slot = nullptr;
-        if (selected) slot = dev_out ? dev_out + (size_t)written * N : c->stage + (size_t)staged * N;
-        st = enqueue_step(c, n, slot);
+        // two full-window steps with the same selection from A[0]: replay the graph
+        if (graphs && n > c->L && n < last && c->cur == 0) {
+            const bool next_sel = !sel || (si + (selected ? 1 : 0) < n_sel && sel[si + (selected ? 1 : 0)] == n + 1);
+            if (next_sel == selected && (dev_out || !selected || staged + 2 <= kRhoStage)) {
+                const int gi = selected ? 1 : 0;
+                if (!c->graph[gi] && build_graph(c, selected) != QUAPI_OK) {
+                    c->graph_failed = true;   // stay on direct launches
+                } else {
+                    st = join_side(c);        // the graph reuses both partial buffers
+                    if (st != QUAPI_OK) return st;
+                    HIP_TRY(c, hipGraphLaunch(c->graph[gi], c->stream));
+                    c->step = n + 1;
+                    if (selected) {
+                        if (sel) si += 2;
+                        written += 2;
+                        if (!dev_out && (staged += 2) == kRhoStage) {
+                            st = flush();
+                            if (st != QUAPI_OK) return st;
+                        }
+                    }
+                    ++n;
+                    continue;
+                }
+            }
+        }
+        st = enqueue_step(c, n, selected);
         if (st != QUAPI_OK) return st;
         if (selected) {
             if (sel) ++si;
@@ -594,6 +676,8 @@ void release(quapi_ctx *c) {
         if (c->ev_fin[k]) (void)hipEventDestroy(c->ev_fin[k]);
     }
     if (c->side) (void)hipStreamDestroy(c->side);
+    for (auto &g : c->graph)
+        if (g) (void)hipGraphExecDestroy(g);
     for (auto &r : c->recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -711,6 +795,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->partials[1] = c->partials[0] + (size_t)lay.partial_blocks * N;
     c->stage = (double2 *)(w + lay.off_stage);
     c->pairs = (double2 *)(w + lay.off_pairs);
+    c->sink = (RhoSink *)(w + lay.off_sink);
     c->plan = (double2 *)(w + lay.off_plan);
 
     c->s_h.assign(p->s, p->s + M);

@@ -99,11 +99,20 @@ hipError_t launch_init_tensor(int N, int prec, const double2 *rho0, const double
                               int self_end_tab, void *a0, hipStream_t st);
 hipError_t launch_step(int N, int prec, bool with_rho, bool grow, const StepArgs &a, int grid,
                        hipStream_t st);
-// Sums the block partials of rho into out[0..N): two launches on st, using
-// pairs (kRhoSlices * N * 2 complex) as scratch.
+// Where finalized rho values go: rho of the k-th finalize after a reset is
+// written to base + k*N.  Device-resident, so graph replays need no new arguments.
+struct RhoSink {
+    double2 *base;
+    unsigned long long count;
+};
+
+// Sums the block partials of rho into the sink's next slot: two launches on
+// st, using pairs (kRhoSlices * N * 2 complex) as scratch.
 constexpr int kRhoSlices = 256;
-hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *pairs, double2 *out,
+hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *pairs, RhoSink *sink,
                                hipStream_t st);
+// sink = {base, 0}, as a kernel (no memset node) so that it is capture-safe.
+hipError_t launch_set_sink(RhoSink *sink, double2 *base, hipStream_t st);
 hipError_t launch_plan_tables(const PlanArgs &a, hipStream_t st);
 size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q);
 

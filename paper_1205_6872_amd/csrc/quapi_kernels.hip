@@ -534,7 +534,9 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 //                      (b+1)*rows/kSlices) -- thread t takes rows t, t+kBlock, ...
 //                      with Neumaier sums, then a fixed two-sum tree -- and
 //                      writes a (sum, compensation) pair per o;
-//   rho_final_kernel   one block combines the kSlices pairs in a fixed tree.
+//   rho_final_kernel   one block combines the kSlices pairs in a fixed tree and
+//                      writes rho to sink->base + sink->count * N, then advances
+//                      sink->count (so a captured graph can replay it unchanged).
 constexpr int kSlices = kRhoSlices;
 template <int N>
 __global__ void __launch_bounds__(kBlock) rho_slice_kernel(const double2 *__restrict__ partials, int rows,
@@ -581,14 +583,28 @@ __global__ void __launch_bounds__(kBlock) rho_slice_kernel(const double2 *__rest
 }
 
 template <int N>
-__global__ void __launch_bounds__(kSlices) rho_final_kernel(const double2 *__restrict__ pairs, double2 *out) {
+__global__ void __launch_bounds__(kSlices) rho_final_kernel(const double2 *__restrict__ pairs, RhoSink *sink) {
     const int t = threadIdx.x;
+    double2 *out = nullptr;
+    unsigned long long count = 0;
+    if (t == 0) {
+        count = sink->count;
+        out = sink->base + count * N;
+    }
 #pragma unroll
     for (int o = 0; o < N; ++o) {
         const double2 sv = pairs[((size_t)t * N + o) * 2], cv = pairs[((size_t)t * N + o) * 2 + 1];
         double a0 = sv.x, a1 = cv.x, a2 = sv.y, a3 = cv.y;
         block_reduce_pairs<kSlices>(a0, a1, a2, a3);
         if (t == 0) out[o] = make_double2(a0 + a1, a2 + a3);
+    }
+    if (t == 0) sink->count = count + 1;
+}
+
+__global__ void set_sink_kernel(RhoSink *sink, double2 *base) {
+    if (threadIdx.x == 0) {
+        sink->base = base;
+        sink->count = 0;
     }
 }
 
@@ -687,13 +703,18 @@ hipError_t launch_step(int N, int prec, bool with_rho, bool grow, const StepArgs
     }
 }
 
-hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *pairs, double2 *out,
+hipError_t launch_set_sink(RhoSink *sink, double2 *base, hipStream_t st) {
+    hipLaunchKernelGGL(set_sink_kernel, dim3(1), dim3(64), 0, st, sink, base);
+    return hipGetLastError();
+}
+
+hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, double2 *pairs, RhoSink *sink,
                                hipStream_t st) {
     switch (N) {
 #define QUAPI_FIN(NV)                                                                                  \
     case NV:                                                                                           \
         hipLaunchKernelGGL(rho_slice_kernel<NV>, dim3(kSlices), dim3(kBlock), 0, st, partials, n_blocks, pairs); \
-        hipLaunchKernelGGL(rho_final_kernel<NV>, dim3(1), dim3(kSlices), 0, st, pairs, out);           \
+        hipLaunchKernelGGL(rho_final_kernel<NV>, dim3(1), dim3(kSlices), 0, st, pairs, sink);          \
         break;
         QUAPI_FIN(1)
         QUAPI_FIN(4)

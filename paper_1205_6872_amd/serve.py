@@ -21,6 +21,7 @@ context, so a request's result does not depend on what else is running.
 """
 from __future__ import annotations
 
+import sys
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -167,7 +168,7 @@ class Server:
                     progressed = True
                     if self.progress and len(results) % 16 == 0:
                         print(f"serve: {len(results)} done at {finish:.1f} s, {len(active)} active, "
-                              f"{len(waiting)} waiting", flush=True)
+                              f"{len(waiting)} waiting", file=sys.stderr, flush=True)
             if not progressed:
                 if not active and pending and realtime:
                     time.sleep(max(0.0, min(0.01, requests[pending[0]].meta.get("arrival_s", 0.0) - now())))
