@@ -5,9 +5,12 @@ tensor entries), xi = 0.5, omega_c = 10, kT = 0.05, dt = 0.1, 1000 steps by
 default, rho(t_n) extracted at every step ('allPoints').  Inputs are
 synthetic (seeded parameters, no dataset).
 
-A timed "step" is one full-window propagation step: the step kernel reads the
-tensor once, writes it once, and produces per-block partial sums of rho(t_n)
-in the same pass; a small finalize kernel sums them.  The growth steps (n < L) and the device setup run first and
+A timed "step" is one full-window propagation step.  For M = 2 the library
+fuses two consecutive steps into one kernel launch: it reads the tensor
+once, keeps the intermediate tensor in registers, writes the tensor two steps
+later once, and produces per-block partial sums of rho at both steps in the
+same pass; a small finalize kernel on a side stream sums them.  So one launch
+moves 2 * N^L * sizeof(complex) bytes and covers two steps.  The growth steps (n < L) and the device setup run first and
 are reported separately.  Three precisions run on the same workload:
 complex128 (the reported `value`), the complex64 tier with FP32 arithmetic
 (`fp32_tier`), and complex64 storage with FP64 arithmetic
@@ -24,8 +27,9 @@ arrivals) so the run stays within minutes; --serve-requests 512 serves all.
 
 Metric: Gelem/s = N^L * steps / seconds / 1e9, with the tensor resident in
 HBM.  `roofline` prices the step kernel against the HBM peak: algorithmic
-bytes per launch = 2 * N^L * sizeof(complex) (one read, one write), divided by
-the kernel's average duration from HIP events on the library's stream.
+bytes per launch = 2 * N^L * sizeof(complex) (one read, one write of the
+tensor), divided by the kernel's average duration per launch from HIP events
+on the library's stream (`steps_per_launch` says how many steps a launch covers).
 `cpu_baseline` times the oracle (plain C, OpenMP) on a bounded sample of the
 same workload on the host.
 
@@ -81,15 +85,25 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
     entries = N ** L
     csize = 16 if dtype == "c128" else 8   # bytes per stored entry
     bytes_per_launch = 2 * entries * csize
-    kernel_ms = tm["step_ms"] / max(tm["step_launches"], 1)
+    launches = max(tm["step_launches"], 1)
+    kernel_ms = tm["step_ms"] / launches                  # per full-window launch
+    steps_per_launch = tm["step_steps"] / launches        # 2 when two steps are fused
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     rho = np.concatenate([rho_grow, rho_warm, rho_main])
     return dict(
         dtype=dtype, elapsed_s=elapsed, steps=steps, ms_per_step=elapsed * 1e3 / steps,
         gelem_s=entries * steps / elapsed / 1e9, kernel_ms=kernel_ms, kernel_launches=tm["step_launches"],
+        steps_per_launch=steps_per_launch,
         finalize_ms=tm["finalize_ms"] / max(tm["finalize_launches"], 1), setup_ms=tm["setup_ms"],
         setup_wall_ms=setup_wall * 1e3, grow_ms=grow_ms, bytes_per_launch=bytes_per_launch,
         achieved_gbs=achieved, rho=rho)
+
+
+def kernel_name(tier: str, steps_per_launch: float) -> str:
+    st = {"c128": "double, double", "c64": "float, float", "c64f64": "float, double"}[tier]
+    if steps_per_launch > 1.5:
+        return f"step2_kernel<{st}, rho> (two steps fused per launch)"
+    return f"step_kernel<4, {st}, rho, full-window>"
 
 
 def measured_traffic(path: str, tier: str):
@@ -217,8 +231,9 @@ def main() -> int:
                    "xi": w.xi, "omega_c": w.omega_c, "kT": w.kT, "dt": w.dt},
         "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "step_kernel<4,double,rho,full-window>",
-                     "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_launch": r["bytes_per_launch"]},
+                     "traffic": traffic, "kernel": kernel_name(main_t, r["steps_per_launch"]),
+                     "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_launch": r["bytes_per_launch"],
+                     "steps_per_launch": round(r["steps_per_launch"], 3)},
         "setup_ms": round(r["setup_ms"], 3),
         "growth_ms": round(r["grow_ms"], 3),
         "finalize_ms": round(r["finalize_ms"], 4),
@@ -235,7 +250,9 @@ def main() -> int:
             "roofline": {"bound": "hbm", "achieved": round(a["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(a["achieved_gbs"] / HBM_PEAK_GBS, 4),
                          "traffic": measured_traffic(args.traffic_json, t),
-                         "kernel_ms": round(a["kernel_ms"], 4), "bytes_per_launch": a["bytes_per_launch"]},
+                         "kernel": kernel_name(t, a["steps_per_launch"]),
+                         "kernel_ms": round(a["kernel_ms"], 4), "bytes_per_launch": a["bytes_per_launch"],
+                         "steps_per_launch": round(a["steps_per_launch"], 3)},
             "max_abs_drho_vs_f64": d, "trace_drift_vs_f64": drift, "steps_compared": len(a["rho"]),
         }
     if not args.no_copy_ceiling:

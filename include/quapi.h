@@ -96,7 +96,7 @@ typedef struct {
 
 /* Device bytes that quapi_create needs for these parameters (the two
  * ping-pong tensors of N^L entries dominate; factor tables and rho
- * reduction scratch add less than 0.1% of that plus 4 MB).  Validates the parameters; needs
+ * reduction scratch add less than 0.2% of that plus 4 MB).  Validates the parameters; needs
  * no GPU.  INVALID on malformed parameters or size overflow. */
 quapi_status quapi_footprint(const quapi_params *p, size_t *device_bytes);
 
@@ -131,7 +131,11 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
  *   n_sel    length of sel (ignored when sel is NULL).
  *   rho_out  host buffer of n_out * M*M complex (n_out = n_sel, or n_steps when
  *            sel is NULL), written in selection order; caller-owned.
- * Blocking: returns when the results are on the host. */
+ * Blocking: returns when the results are on the host.
+ * Results are deterministic.  For M = 2 (L >= 2) full-window steps run as fused
+ * pairs (L+1, L+2), (L+3, L+4), ...; a sequence of calls gives bit-identical
+ * results to one call when every call ends at step c <= L or with c - L even
+ * (otherwise the split step runs unfused and rounds differently, within 1e-15). */
 quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
                              double *rho_out);
 
@@ -170,6 +174,7 @@ typedef struct {
     double setup_ms;          /* device time of the setup kernels in quapi_create */
     double step_ms;           /* summed duration of full-window step kernels (n >= L) */
     long long step_launches;  /* number of those launches */
+    long long step_steps;     /* full-window steps they covered (a fused launch covers two) */
     double grow_ms;           /* summed duration of growth-step kernels (n < L) */
     long long grow_launches;
     double finalize_ms;       /* summed duration of the kernels that sum rho over blocks */

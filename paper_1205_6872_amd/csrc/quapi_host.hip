@@ -75,9 +75,30 @@ DigitSplit split_digits(int N, int n_digits) {
     return s;
 }
 
+// Digit split of m for the fused two-step kernel (N = 4, L - 2 digits): the
+// low digits per thread (R <= 64, so that the four tables of per-thread
+// products fit in LDS), two sweep digits, the rest per block.
+DigitSplit split_digits2(int n_digits) {
+    constexpr int N = 4;
+    DigitSplit s;
+    s.d_lo = std::min(3, n_digits);
+    const int avail = n_digits - s.d_lo;
+    s.d_mid = std::min(2, avail);
+    while (s.d_mid > 0 && ipow_ll(N, avail - s.d_mid) < 1024) --s.d_mid;
+    s.R = (int)ipow_ll(N, s.d_lo);
+    s.Q = (int)ipow_ll(N, s.d_mid);
+    s.grid = (int)ipow_ll(N, avail - s.d_mid);
+    return s;
+}
+
+// The fused two-step kernel applies to N = 4 (its N^2 inputs per item fit in
+// registers) and L >= 2 (two points to sum out).
+bool fused_ok(int N, int L) { return N == 4 && L >= 2; }
+
 int max_grid(int N, int L) {
     int g = 1;
     for (int nd = 0; nd <= L - 1; ++nd) g = std::max(g, split_digits(N, nd).grid);
+    if (fused_ok(N, L)) g = std::max(g, split_digits2(L - 2).grid);
     return g;
 }
 
@@ -214,11 +235,14 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_g, off_eta, off_U, off_s, off_H, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
-    size_t off_plan, off_pairs, off_sink;
+    size_t off_plan, off_plan2, off_pairs, off_sink;
     size_t total;
     int n_panels, n_tables, partial_blocks;
     DigitSplit main_split;   // digit split of the full-window steps
+    DigitSplit split2;       // digit split of the fused two-step kernel
 };
+
+constexpr int kSlots = 4;    // rho partial buffers: a fused launch takes two
 
 Layout make_layout(const quapi_params &p, int n_panels) {
     Layout l{};
@@ -230,6 +254,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.n_tables = BankLayout{L}.count();
     l.partial_blocks = max_grid(N, L);
     l.main_split = split_digits(N, L - 1);
+    l.split2 = fused_ok(N, L) ? split_digits2(L - 2) : DigitSplit{0, 0, 1, 1, 1};
     l.a_bytes = entries * cs;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -254,13 +279,16 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_tJ = take((size_t)nt * 8);
     l.off_glx = take(kGL * 8);
     l.off_glw = take(kGL * 8);
-    l.off_partials = take((size_t)2 * l.partial_blocks * N * 16);   // double-buffered
+    l.off_partials = take((size_t)kSlots * l.partial_blocks * N * 16);
     l.off_stage = take((size_t)kRhoStage * N * 16);
     l.off_pairs = take((size_t)kRhoSlices * N * 2 * 16);
     l.off_sink = take(sizeof(RhoSink));
     // six FP64 factor tables of the full-window split: [N][R], [N][Q], [N][grid], x2 classes
     const DigitSplit &ms = l.main_split;
     l.off_plan = take((size_t)2 * N * (ms.R + ms.Q + ms.grid) * 16);
+    // four table sets (interior / final, steps n and n+1) of the fused split
+    const DigitSplit &s2 = l.split2;
+    l.off_plan2 = take(fused_ok(N, L) ? (size_t)4 * N * (s2.R + s2.Q + s2.grid) * 16 : 0);
     l.total = off;
     return l;
 }
@@ -282,12 +310,12 @@ struct quapi_ctx {
     double dt = 0.0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // rho finalize kernels run on a side stream, overlapped with the next step;
-    // the block partials are double-buffered between the two streams
+    // rho finalize kernels run on a side stream, overlapped with the next
+    // step; the block partials rotate over kSlots buffers between the streams
     hipStream_t side = nullptr;
-    hipEvent_t ev_step[2] = {nullptr, nullptr}, ev_fin[2] = {nullptr, nullptr};
-    bool fin_pending[2] = {false, false};
-    int pslot = 0;
+    hipEvent_t ev_step[kSlots] = {}, ev_fin[kSlots] = {};
+    bool fin_pending[kSlots] = {};
+    int next_slot = 0;
     char *ws = nullptr;
     bool own_ws = false;
     Layout lay{};
@@ -295,13 +323,15 @@ struct quapi_ctx {
     int cur = 0;                  // A[cur] holds the tensor after global step `step`
     int step = 0;
     double2 *bank = nullptr, *g = nullptr, *eta = nullptr, *U = nullptr, *rho0_d = nullptr;
-    double2 *partials[2] = {nullptr, nullptr};
-    double2 *stage = nullptr, *plan = nullptr, *pairs = nullptr;
+    double2 *partials[kSlots] = {};
+    double2 *stage = nullptr, *plan = nullptr, *plan2 = nullptr, *pairs = nullptr;
     RhoSink *sink = nullptr;
-    // two captured full-window steps (A[0] -> A[1] -> A[0]), without / with rho
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // captured full-window steps, [without / with rho]: graph1 two single steps
+    // A[0] -> A[1] -> A[0]; graph2[.][p] one fused launch A[p] -> A[1-p]
+    hipGraphExec_t graph1[2] = {}, graph2[2][2] = {};
     bool graph_failed = false;
     bool plan_ready = false;      // full-window factor tables computed
+    bool plan2_ready = false;     // fused-step factor tables computed
     std::vector<double> rho0_h;
     // host copies of uploaded inputs (kept alive until the uploads complete)
     std::vector<double> s_h, H_h, pa_h, ph_h, tw_h, tJ_h, glx_h, glw_h;
@@ -311,11 +341,12 @@ struct quapi_ctx {
     // timing
     bool timing = false;
     double setup_ms = 0.0;
-    struct Rec { int kind; hipEvent_t a, b; };
+    struct Rec { int kind; hipEvent_t a, b; int steps; };   // steps: full-window steps covered
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     double acc_ms[3] = {0, 0, 0};
     long long acc_n[3] = {0, 0, 0};
+    long long acc_steps = 0;      // full-window steps covered by timed step launches
 };
 
 namespace {
@@ -464,6 +495,56 @@ quapi_status prepare_step(quapi_ctx *c, int n, bool rho, StepPlan *out) {
     return QUAPI_OK;
 }
 
+// Partial-buffer slots rotate; a slot may be rewritten only after the
+// finalize that reads it (on the side stream) is done.
+int take_slot(quapi_ctx *c) {
+    const int s = c->next_slot;
+    c->next_slot = (s + 1) % kSlots;
+    return s;
+}
+
+quapi_status wait_slot(quapi_ctx *c, int s) {
+    if (c->fin_pending[s]) {
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_fin[s], 0));
+        c->fin_pending[s] = false;
+    }
+    return QUAPI_OK;
+}
+
+// Order the main stream after every finalize still running on the side stream.
+quapi_status join_side(quapi_ctx *c) {
+    for (int k = 0; k < kSlots; ++k) {
+        quapi_status st = wait_slot(c, k);
+        if (st != QUAPI_OK) return st;
+    }
+    return QUAPI_OK;
+}
+
+// Finalize the rho partials of `slots` (in order) on the side stream, after
+// the step kernel that wrote them.
+quapi_status finalize_side(quapi_ctx *c, const int *slots, int n, int grid) {
+    HIP_TRY(c, hipEventRecord(c->ev_step[slots[0]], c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_step[slots[0]], 0));
+    for (int k = 0; k < n; ++k) {
+        const int sl = slots[k];
+        hipEvent_t f0 = nullptr, f1 = nullptr;
+        if (c->timing) {
+            f0 = take_event(c);
+            f1 = take_event(c);
+            if (f0) (void)hipEventRecord(f0, c->side);
+        }
+        hipError_t e = launch_rho_finalize(c->N, c->partials[sl], grid, c->pairs, c->sink, c->side);
+        if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "rho finalize launch: %s", hipGetErrorString(e));
+        if (c->timing && f0 && f1) {
+            (void)hipEventRecord(f1, c->side);
+            c->recs.push_back({2, f0, f1, 0});
+        }
+        HIP_TRY(c, hipEventRecord(c->ev_fin[sl], c->side));
+        c->fin_pending[sl] = true;
+    }
+    return QUAPI_OK;
+}
+
 // Enqueue step n (1-based); with rho, also rho(t_n) into the sink's next slot.
 // The finalize runs on the side stream, overlapped with the next step.
 quapi_status enqueue_step(quapi_ctx *c, int n, bool rho) {
@@ -471,70 +552,173 @@ quapi_status enqueue_step(quapi_ctx *c, int n, bool rho) {
     quapi_status st = prepare_step(c, n, rho, &sp);
     if (st != QUAPI_OK) return st;
     StepArgs &a = sp.args;
-    const int N = c->N;
     a.a_in = c->A[c->cur];
     a.a_out = c->A[1 - c->cur];
-    const int slot = c->pslot;
+    int slot = -1;
     if (rho) {
-        c->pslot ^= 1;
+        slot = take_slot(c);
+        st = wait_slot(c, slot);
+        if (st != QUAPI_OK) return st;
         a.partials = c->partials[slot];
-        // the finalize that last read this partial buffer must be done
-        if (c->fin_pending[slot]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_fin[slot], 0));
     }
-    const int kind = sp.grow ? 1 : 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         e0 = take_event(c);
         e1 = take_event(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
-    hipError_t e = launch_step(N, c->prec, rho, sp.grow, a, sp.split.grid, c->stream);
+    hipError_t e = launch_step(c->N, c->prec, rho, sp.grow, a, sp.split.grid, c->stream);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "step kernel launch: %s", hipGetErrorString(e));
     if (c->timing && e0 && e1) {
         (void)hipEventRecord(e1, c->stream);
-        c->recs.push_back({kind, e0, e1});
+        c->recs.push_back({sp.grow ? 1 : 0, e0, e1, sp.grow ? 0 : 1});
     }
     if (rho) {
-        HIP_TRY(c, hipEventRecord(c->ev_step[slot], c->stream));
-        HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_step[slot], 0));
-        hipEvent_t f0 = nullptr, f1 = nullptr;
-        if (c->timing) {
-            f0 = take_event(c);
-            f1 = take_event(c);
-            if (f0) (void)hipEventRecord(f0, c->side);
-        }
-        e = launch_rho_finalize(N, c->partials[slot], sp.split.grid, c->pairs, c->sink, c->side);
-        if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "rho finalize launch: %s", hipGetErrorString(e));
-        if (c->timing && f0 && f1) {
-            (void)hipEventRecord(f1, c->side);
-            c->recs.push_back({2, f0, f1});
-        }
-        HIP_TRY(c, hipEventRecord(c->ev_fin[slot], c->side));
-        c->fin_pending[slot] = true;
+        st = finalize_side(c, &slot, 1, sp.split.grid);
+        if (st != QUAPI_OK) return st;
     }
     c->cur = 1 - c->cur;
     c->step = n;
     return QUAPI_OK;
 }
 
-// Capture two full-window steps A[0] -> A[1] -> A[0] (finalizes on the same
-// stream) into an executable graph.  Every argument of every node is fixed:
-// the step tables are the same for all n > L and rho goes through the sink.
-quapi_status build_graph(quapi_ctx *c, bool rho) {
-    StepPlan sp;
-    quapi_status st = prepare_step(c, c->L + 1, rho, &sp);  // plan tables exist by now
+// Arguments of a fused launch of steps n, n+1 (n > L); the four factor-table
+// sets are computed on first use.
+quapi_status prepare_step2(quapi_ctx *c, bool rho, Step2Args *out) {
+    const int N = c->N, L = c->L;
+    const BankLayout B{L};
+    const DigitSplit &sp = c->lay.split2;
+    const int nd = L - 2;
+    Step2Args a{};
+    a.bank = c->bank;
+    a.m_count = ipow_ll(N, nd);
+    a.R = sp.R;
+    a.Q = sp.Q;
+    a.grid = sp.grid;
+    const size_t cap = c->lay.a_bytes / c->csize;
+    const size_t lds = step2_lds_bytes(c->prec, rho, a.R, a.Q);
+    if ((long long)a.grid * a.R * a.Q != a.m_count || (size_t)a.m_count * N * N > cap ||
+        a.grid > c->lay.partial_blocks || lds > (size_t)kLdsLimit || a.R > kBlock)
+        return fail(c, QUAPI_ERR_DEVICE, "internal fused launch check failed");
+    // sets 0, 1, 2, 3 = interior n, interior n+1, final n, final n+1; each [N][R] [N][Q] [N][grid]
+    const size_t per = (size_t)N * (sp.R + sp.Q + sp.grid);
+    for (int k = 0; k < 4; ++k) {
+        double2 *base = c->plan2 + per * k;
+        a.t_lo[k] = base;
+        a.t_mid[k] = base + (size_t)N * sp.R;
+        a.t_hi[k] = base + (size_t)N * (sp.R + sp.Q);
+    }
+    if (!c->plan2_ready) {
+        // digit j of m is point n-L+2+j: lag L-2-j from n, L-1-j from n+1
+        for (int step = 0; step < 2; ++step) {
+            PlanArgs pa{};
+            pa.bank = c->bank;
+            pa.N = N;
+            pa.d_lo = sp.d_lo;
+            pa.d_mid = sp.d_mid;
+            pa.n_digits = nd;
+            pa.R = sp.R;
+            pa.Q = sp.Q;
+            pa.grid = sp.grid;
+            for (int j = 0; j < nd; ++j) {
+                const int lag = (step == 0 ? L - 2 : L - 1) - j;
+                pa.tab[j] = (int16_t)(lag == 1 ? B.k_lag1() : B.lag(lag));
+                pa.tabf[j] = (int16_t)(lag == 1 ? B.k_fin1() : B.fin(lag));
+            }
+            pa.t_lo = (double2 *)a.t_lo[step];
+            pa.t_lof = (double2 *)a.t_lo[step + 2];
+            pa.t_mid = (double2 *)a.t_mid[step];
+            pa.t_midf = (double2 *)a.t_mid[step + 2];
+            pa.t_hi = (double2 *)a.t_hi[step];
+            pa.t_hif = (double2 *)a.t_hi[step + 2];
+            hipError_t e = launch_plan_tables(pa, c->stream);
+            if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "plan kernel launch: %s", hipGetErrorString(e));
+        }
+        c->plan2_ready = true;
+    }
+    a.old_tab = B.old_main();
+    a.oldf_tab = B.oldf_main();
+    a.an_tab = L - 1 == 1 ? B.k_lag1() : B.lag(L - 1);       // point n-L+1 seen from n
+    a.anf_tab = L - 1 == 1 ? B.k_fin1() : B.fin(L - 1);
+    a.d_tab = B.k_lag1();                                   // point n seen from n+1
+    a.df_tab = B.k_fin1();
+    *out = a;
+    return QUAPI_OK;
+}
+
+// Enqueue the fused steps n, n+1 (n > L); rho of the selected ones goes to
+// the sink in step order.
+quapi_status enqueue_step2(quapi_ctx *c, int n, bool sel_n, bool sel_n1) {
+    const bool rho = sel_n || sel_n1;
+    Step2Args a;
+    quapi_status st = prepare_step2(c, rho, &a);
+    if (st != QUAPI_OK) return st;
+    a.a_in = c->A[c->cur];
+    a.a_out = c->A[1 - c->cur];
+    int slots[2] = {-1, -1};
+    if (rho) {
+        for (int k = 0; k < 2; ++k) {
+            slots[k] = take_slot(c);
+            st = wait_slot(c, slots[k]);
+            if (st != QUAPI_OK) return st;
+            a.partials[k] = c->partials[slots[k]];
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        e0 = take_event(c);
+        e1 = take_event(c);
+        if (e0) (void)hipEventRecord(e0, c->stream);
+    }
+    hipError_t e = launch_step2(c->prec, rho, a, c->stream);
+    if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "fused step launch: %s", hipGetErrorString(e));
+    if (c->timing && e0 && e1) {
+        (void)hipEventRecord(e1, c->stream);
+        c->recs.push_back({0, e0, e1, 2});
+    }
+    if (rho) {
+        int fin[2], nf = 0;
+        if (sel_n) fin[nf++] = slots[0];
+        if (sel_n1) fin[nf++] = slots[1];
+        st = finalize_side(c, fin, nf, a.grid);
+        if (st != QUAPI_OK) return st;
+    }
+    c->cur = 1 - c->cur;
+    c->step = n + 1;
+    return QUAPI_OK;
+}
+
+// Capture full-window steps into an executable graph whose node arguments
+// never change (the step tables are the same for all n > L, and rho goes
+// through the sink); finalizes run on the same stream.
+//   fused == false: two single steps A[0] -> A[1] -> A[0]
+//   fused == true:  one fused launch A[par] -> A[1 - par]
+quapi_status build_graph(quapi_ctx *c, bool rho, bool fused, int par, hipGraphExec_t *out) {
+    StepPlan sp{};
+    Step2Args a2{};
+    quapi_status st = fused ? prepare_step2(c, rho, &a2) : prepare_step(c, c->L + 1, rho, &sp);
     if (st != QUAPI_OK) return st;
     hipGraph_t g = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-        StepArgs a = sp.args;
-        a.a_in = c->A[k];
-        a.a_out = c->A[1 - k];
-        a.partials = c->partials[k];
-        e = launch_step(c->N, c->prec, rho, false, a, sp.split.grid, c->stream);
-        if (e == hipSuccess && rho)
-            e = launch_rho_finalize(c->N, c->partials[k], sp.split.grid, c->pairs, c->sink, c->stream);
+    if (fused) {
+        a2.a_in = c->A[par];
+        a2.a_out = c->A[1 - par];
+        a2.partials[0] = c->partials[0];
+        a2.partials[1] = c->partials[1];
+        e = launch_step2(c->prec, rho, a2, c->stream);
+        for (int k = 0; k < 2 && rho && e == hipSuccess; ++k)
+            e = launch_rho_finalize(c->N, c->partials[k], a2.grid, c->pairs, c->sink, c->stream);
+    } else {
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            StepArgs a = sp.args;
+            a.a_in = c->A[k];
+            a.a_out = c->A[1 - k];
+            a.partials = c->partials[k];
+            e = launch_step(c->N, c->prec, rho, false, a, sp.split.grid, c->stream);
+            if (e == hipSuccess && rho)
+                e = launch_rho_finalize(c->N, c->partials[k], sp.split.grid, c->pairs, c->sink, c->stream);
+        }
     }
     hipError_t e2 = hipStreamEndCapture(c->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -542,22 +726,12 @@ quapi_status build_graph(quapi_ctx *c, bool rho) {
         return fail(c, QUAPI_ERR_DEVICE, "graph capture failed: %s",
                     hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    e = hipGraphInstantiate(&c->graph[rho ? 1 : 0], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        c->graph[rho ? 1 : 0] = nullptr;
+        *out = nullptr;
         return fail(c, QUAPI_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
     }
-    return QUAPI_OK;
-}
-
-// Order the main stream after every finalize still running on the side stream.
-quapi_status join_side(quapi_ctx *c) {
-    for (int k = 0; k < 2; ++k)
-        if (c->fin_pending[k]) {
-            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_fin[k], 0));
-            c->fin_pending[k] = false;
-        }
     return QUAPI_OK;
 }
 
@@ -585,13 +759,18 @@ quapi_status check_selection(quapi_ctx *c, int n_steps, const int *sel, int n_se
 
 // Shared driver of the blocking and asynchronous calls.  dev_out: device
 // output of n_out slots (async), or NULL to stage and copy into host_out.
+//
+// Dispatch per step n: growth steps and the first full-window step run one
+// launch each; later full-window steps run in fused pairs when N = 4 (one pass
+// per two steps), else singly; small tensors replay captured graphs of two
+// steps.  A call that ends inside a pair runs its last step singly.
 quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel, double2 *dev_out,
                             double *host_out) {
     int n_out = 0;
     quapi_status st = check_selection(c, n_steps, sel, n_sel, &n_out);
     if (st != QUAPI_OK) return st;
     if (n_out > 0 && !dev_out && !host_out) return fail(c, QUAPI_ERR_INVALID, "rho_out is NULL");
-    const int N = c->N;
+    const int N = c->N, L = c->L;
     int si = 0;          // next selection entry
     int written = 0;     // outputs delivered so far
     int staged = 0;      // outputs in the staging buffer (blocking call)
@@ -606,6 +785,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
         HIP_TRY(c, launch_set_sink(c->sink, c->stage, c->stream));
         return QUAPI_OK;
     };
+    auto is_sel = [&](int k, int from) { return !sel || (from < n_sel && sel[from] == k); };
     if (sel && si < n_sel && sel[si] == 0) {  // rho(t_0) = rho0
         if (dev_out)
             HIP_TRY(c, hipMemcpyAsync(dev_out, c->rho0_d, (size_t)N * 16, hipMemcpyDeviceToDevice, c->stream));
@@ -616,45 +796,59 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
     }
     // finalized rho values land at sink->base + k*N in step order
     HIP_TRY(c, launch_set_sink(c->sink, dev_out ? dev_out + (size_t)written * N : c->stage, c->stream));
-    const size_t entries = (size_t)ipow_ll(c->N, c->L);
+    const size_t entries = (size_t)ipow_ll(N, L);
+    const bool fused = fused_ok(N, L);
     const bool graphs = !c->timing && !c->graph_failed && entries <= kGraphMaxEntries;
     const int first = c->step + 1, last = c->step + n_steps;
     for (int n = first; n <= last; ++n) {
-        const bool selected = !sel || (si < n_sel && sel[si] == n);
-        // two full-window steps with the same selection from A[0]: replay the graph
-        if (graphs && n > c->L && n < last && c->cur == 0) {
-            const bool next_sel = !sel || (si + (selected ? 1 : 0) < n_sel && sel[si + (selected ? 1 : 0)] == n + 1);
-            if (next_sel == selected && (dev_out || !selected || staged + 2 <= kRhoStage)) {
-                const int gi = selected ? 1 : 0;
-                if (!c->graph[gi] && build_graph(c, selected) != QUAPI_OK) {
-                    c->graph_failed = true;   // stay on direct launches
-                } else {
-                    st = join_side(c);        // the graph reuses both partial buffers
-                    if (st != QUAPI_OK) return st;
-                    HIP_TRY(c, hipGraphLaunch(c->graph[gi], c->stream));
-                    c->step = n + 1;
-                    if (selected) {
-                        if (sel) si += 2;
-                        written += 2;
-                        if (!dev_out && (staged += 2) == kRhoStage) {
-                            st = flush();
-                            if (st != QUAPI_OK) return st;
-                        }
-                    }
-                    ++n;
-                    continue;
-                }
-            }
-        }
-        st = enqueue_step(c, n, selected);
-        if (st != QUAPI_OK) return st;
-        if (selected) {
-            if (sel) ++si;
-            ++written;
-            if (!dev_out && ++staged == kRhoStage) {
+        const bool s0 = is_sel(n, si);
+        // Two full-window steps n, n+1.  Pairs are fixed by the global step
+        // number -- (L+1, L+2), (L+3, L+4), ... -- so a run gives the same bits
+        // however it is split into calls, as long as no call ends inside a pair.
+        if (n > L && n < last && (n - L - 1) % 2 == 0) {
+            const bool s1 = is_sel(n + 1, si + (s0 ? 1 : 0));
+            const int nsel = (s0 ? 1 : 0) + (s1 ? 1 : 0);
+            if (!dev_out && staged + nsel > kRhoStage) {
                 st = flush();
                 if (st != QUAPI_OK) return st;
             }
+            bool done = false;
+            if (graphs && s0 == s1 && (fused || c->cur == 0)) {
+                hipGraphExec_t &gx = fused ? c->graph2[s0 ? 1 : 0][c->cur] : c->graph1[s0 ? 1 : 0];
+                if (!gx && build_graph(c, s0, fused, c->cur, &gx) != QUAPI_OK) {
+                    c->graph_failed = true;   // stay on direct launches
+                } else {
+                    st = join_side(c);        // the graph reuses partial buffers 0 and 1
+                    if (st != QUAPI_OK) return st;
+                    HIP_TRY(c, hipGraphLaunch(gx, c->stream));
+                    if (fused) c->cur = 1 - c->cur;
+                    c->step = n + 1;
+                    done = true;
+                }
+            }
+            if (!done && fused) {
+                st = enqueue_step2(c, n, s0, s1);
+                if (st != QUAPI_OK) return st;
+                done = true;
+            }
+            if (done) {
+                si += sel ? nsel : 0;
+                written += nsel;
+                if (!dev_out) staged += nsel;
+                ++n;
+                continue;
+            }
+        }
+        if (!dev_out && s0 && staged + 1 > kRhoStage) {
+            st = flush();
+            if (st != QUAPI_OK) return st;
+        }
+        st = enqueue_step(c, n, s0);
+        if (st != QUAPI_OK) return st;
+        if (s0) {
+            if (sel) ++si;
+            ++written;
+            if (!dev_out) ++staged;
         }
     }
     st = join_side(c);
@@ -671,13 +865,16 @@ void release(quapi_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->side) (void)hipStreamSynchronize(c->side);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kSlots; ++k) {
         if (c->ev_step[k]) (void)hipEventDestroy(c->ev_step[k]);
         if (c->ev_fin[k]) (void)hipEventDestroy(c->ev_fin[k]);
     }
     if (c->side) (void)hipStreamDestroy(c->side);
-    for (auto &g : c->graph)
+    for (auto &g : c->graph1)
         if (g) (void)hipGraphExecDestroy(g);
+    for (auto &row : c->graph2)
+        for (auto &g : row)
+            if (g) (void)hipGraphExecDestroy(g);
     for (auto &r : c->recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -755,7 +952,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
         c->own_stream = true;
     }
     bool side_ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
-    for (int k = 0; k < 2 && side_ok; ++k)
+    for (int k = 0; k < kSlots && side_ok; ++k)
         side_ok = hipEventCreateWithFlags(&c->ev_step[k], hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&c->ev_fin[k], hipEventDisableTiming) == hipSuccess;
     if (!side_ok) {
@@ -791,8 +988,9 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->eta = (double2 *)(w + lay.off_eta);
     c->U = (double2 *)(w + lay.off_U);
     c->rho0_d = (double2 *)(w + lay.off_rho0);
-    c->partials[0] = (double2 *)(w + lay.off_partials);
-    c->partials[1] = c->partials[0] + (size_t)lay.partial_blocks * N;
+    for (int k = 0; k < kSlots; ++k)
+        c->partials[k] = (double2 *)(w + lay.off_partials) + (size_t)k * lay.partial_blocks * N;
+    c->plan2 = (double2 *)(w + lay.off_plan2);
     c->stage = (double2 *)(w + lay.off_stage);
     c->pairs = (double2 *)(w + lay.off_pairs);
     c->sink = (RhoSink *)(w + lay.off_sink);
@@ -968,6 +1166,7 @@ quapi_status quapi_get_timing(quapi_ctx *ctx, quapi_timing *out) {
         if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
             ctx->acc_ms[r.kind] += ms;
             ctx->acc_n[r.kind] += 1;
+            ctx->acc_steps += r.steps;
         }
         ctx->pool.push_back(r.a);
         ctx->pool.push_back(r.b);
@@ -976,6 +1175,7 @@ quapi_status quapi_get_timing(quapi_ctx *ctx, quapi_timing *out) {
     out->setup_ms = ctx->setup_ms;
     out->step_ms = ctx->acc_ms[0];
     out->step_launches = ctx->acc_n[0];
+    out->step_steps = ctx->acc_steps;
     out->grow_ms = ctx->acc_ms[1];
     out->grow_launches = ctx->acc_n[1];
     out->finalize_ms = ctx->acc_ms[2];
@@ -984,6 +1184,7 @@ quapi_status quapi_get_timing(quapi_ctx *ctx, quapi_timing *out) {
         ctx->acc_ms[k] = 0.0;
         ctx->acc_n[k] = 0;
     }
+    ctx->acc_steps = 0;
     return QUAPI_OK;
 }
 

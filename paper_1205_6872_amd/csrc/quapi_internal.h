@@ -62,6 +62,24 @@ struct StepArgs {
     int16_t tabf[kMaxL];        // bank index of the final-point table for digit j
 };
 
+// Two consecutive full-window steps n, n+1 (n > L, N = 4) in one pass:
+// A_out[m + m_count*(o + N*o')] from the N^2 contiguous inputs A_in[i + N*i' + N^2*m],
+// m the digits of points n-L+2 .. n-1 (m_count = N^(L-2)); A_n stays in registers.
+struct Step2Args {
+    const void *a_in;
+    void *a_out;
+    const double2 *bank;
+    // factor products over the digits of m, per table set: 0 interior step n,
+    // 1 interior step n+1, 2 final step n, 3 final step n+1 ([N][R], [N][Q], [N][grid])
+    const double2 *t_lo[4], *t_mid[4], *t_hi[4];
+    double2 *partials[2];       // block partials of rho(t_n), rho(t_{n+1}) [grid][N]
+    long long m_count;
+    int R, Q, grid;
+    // bank indices: oldest point (interior / final; both steps), point n-L+1 for
+    // step n (interior / final), point n for step n+1 (interior / final, K folded)
+    int old_tab, oldf_tab, an_tab, anf_tab, d_tab, df_tab;
+};
+
 // Factor products of the full-window digit split (see StepArgs::t_lo ...).
 struct PlanArgs {
     const double2 *bank;
@@ -115,5 +133,7 @@ hipError_t launch_rho_finalize(int N, const double2 *partials, int n_blocks, dou
 hipError_t launch_set_sink(RhoSink *sink, double2 *base, hipStream_t st);
 hipError_t launch_plan_tables(const PlanArgs &a, hipStream_t st);
 size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q);
+hipError_t launch_step2(int prec, bool with_rho, const Step2Args &a, hipStream_t st);
+size_t step2_lds_bytes(int prec, bool with_rho, int R, int Q);
 
 }  // namespace quapi

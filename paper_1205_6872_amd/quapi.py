@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("setup_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
-                ("step_launches", ctypes.c_longlong), ("grow_ms", ctypes.c_double),
+                ("step_launches", ctypes.c_longlong), ("step_steps", ctypes.c_longlong),
+                ("grow_ms", ctypes.c_double),
                 ("grow_launches", ctypes.c_longlong), ("finalize_ms", ctypes.c_double),
                 ("finalize_launches", ctypes.c_longlong)]
 

@@ -81,7 +81,7 @@ class Server:
         self.torch = torch
         self.device = device
         self.max_active = max_active
-        self.chunk = chunk_steps
+        self.chunk = max(2, chunk_steps)
         self.progress = progress
         self.streams = [torch.cuda.Stream(device) for _ in range(max_active)]
         if hbm_budget is None:
@@ -140,7 +140,12 @@ class Server:
                 while a.events and a.events[0].query():
                     a.events.popleft()
                 if a.enqueued < a.w.n_steps and len(a.events) < 2:
-                    k = min(self.chunk, a.w.n_steps - a.enqueued)
+                    end = min(a.enqueued + self.chunk, a.w.n_steps)
+                    # never end a chunk inside a fused step pair (L+1, L+2), ...:
+                    # the run then has the same bits as one call of all steps
+                    if end < a.w.n_steps and end > a.w.L and (end - a.w.L) % 2 == 1:
+                        end -= 1
+                    k = end - a.enqueued
                     off = (a.enqueued + 1) * a.w.N * 16
                     a.ctx.propagate_async(k, None, a.rho_dev.data_ptr() + off)
                     a.enqueued += k

@@ -55,10 +55,10 @@ def test_footprint_is_two_tensor_buffers_plus_small_tables():
     for L, dtype, cs in [(7, "c128", 16), (12, "c64", 8), (15, "c128", 16)]:
         fp = Q.footprint(_p(L=L, dtype=dtype))
         two = 2 * 4 ** L * cs
-        assert two <= fp <= two + two // 1000 + 4 * 2 ** 20
+        assert two <= fp <= two + two // 500 + 4 * 2 ** 20
     fp3 = Q.footprint(Q.params_from(W.three_site_l8()))
     two3 = 2 * 9 ** 8 * 16
-    assert two3 <= fp3 <= two3 + two3 // 1000 + 4 * 2 ** 20
+    assert two3 <= fp3 <= two3 + two3 // 500 + 4 * 2 ** 20
 
 
 @pytest.mark.parametrize("over,needle", [

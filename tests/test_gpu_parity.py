@@ -163,6 +163,42 @@ def _sampled_entry_check(w, dtype, tol):
             assert abs(np.trace(rho[0]) - 1) <= tr_tol
 
 
+def _sampled_fused_check(w, dtype, tol):
+    """Two full-window steps done by one fused launch, at the workload's size,
+    checked on sampled entries by applying the one-step entry formula twice."""
+    rng = np.random.default_rng(19)
+    L, N = w.L, w.N
+    inp = orun.inputs_from(w)
+    _, ec, _, K = orun.setup(inp)
+    mr = N ** (L - 2)                       # items: digits of points n-L+2 .. n-1
+    ms = np.unique(np.concatenate([[0, mr - 1], rng.integers(0, mr, 14)]))
+    with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
+        ctx.propagate(L + 1, sel=[L + 1])   # through the first full-window steps
+        n = L + 2                           # the fused pair is (n, n + 1)
+        a_in = {int(m): ctx.read_tensor(N * N * int(m), N * N) for m in ms}
+        rho = ctx.propagate(2)
+        assert np.abs(np.trace(rho, axis1=1, axis2=2) - 1).max() <= (1e-12 if dtype == "c128" else 1e-6)
+        worst = 0.0
+        for m in ms:
+            x = a_in[int(m)]
+            got, want = [], []
+            for o in range(N):
+                # A_n entries (i', m, o) for i' = 0..N-1
+                y = np.array([oentry.step_entry(w.s, K, ec, L, n, ip + N * int(m), o, x[N * ip:N * ip + N])
+                              for ip in range(N)])
+                for op in range(N):
+                    want.append(oentry.step_entry(w.s, K, ec, L, n + 1, int(m) + mr * o, op, y))
+                    got.append(ctx.read_tensor(int(m) + mr * (o + N * op), 1)[0])
+            got, want = np.array(got), np.array(want)
+            worst = max(worst, np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))
+        assert worst <= tol, worst
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 3e-5), ("c64f64", 3e-7)])
+def test_headline_size_fused_pair_sampled_entries(dtype, tol):
+    _sampled_fused_check(W.spin_boson_l15(dtype), dtype, tol)
+
+
 def test_headline_size_sampled_entries_c128():
     _sampled_entry_check(W.spin_boson_l15("c128"), "c128", 1e-12)
 
