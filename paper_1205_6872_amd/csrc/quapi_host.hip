@@ -83,7 +83,7 @@ DigitSplit split_digits2(int n_digits) {
     DigitSplit s;
     s.d_lo = std::min(3, n_digits);
     const int avail = n_digits - s.d_lo;
-    s.d_mid = std::min(2, avail);
+    s.d_mid = std::min(3, avail);
     while (s.d_mid > 0 && ipow_ll(N, avail - s.d_mid) < 1024) --s.d_mid;
     s.R = (int)ipow_ll(N, s.d_lo);
     s.Q = (int)ipow_ll(N, s.d_mid);
@@ -235,7 +235,7 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_g, off_eta, off_U, off_s, off_H, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
-    size_t off_plan, off_plan2, off_pairs, off_sink;
+    size_t off_plan, off_plan2, off_coef, off_pairs, off_sink;
     size_t total;
     int n_panels, n_tables, partial_blocks;
     DigitSplit main_split;   // digit split of the full-window steps
@@ -289,6 +289,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     // four table sets (interior / final, steps n and n+1) of the fused split
     const DigitSplit &s2 = l.split2;
     l.off_plan2 = take(fused_ok(N, L) ? (size_t)4 * N * (s2.R + s2.Q + s2.grid) * 16 : 0);
+    l.off_coef = take(fused_ok(N, L) ? (size_t)kCoefCount * 16 : 0);
     l.total = off;
     return l;
 }
@@ -325,6 +326,7 @@ struct quapi_ctx {
     double2 *bank = nullptr, *g = nullptr, *eta = nullptr, *U = nullptr, *rho0_d = nullptr;
     double2 *partials[kSlots] = {};
     double2 *stage = nullptr, *plan = nullptr, *plan2 = nullptr, *pairs = nullptr;
+    void *coef = nullptr;         // fused-step coefficients (compute precision)
     RhoSink *sink = nullptr;
     // captured full-window steps, [without / with rho]: graph1 two single steps
     // A[0] -> A[1] -> A[0]; graph2[.][p] one fused launch A[p] -> A[1-p]
@@ -634,14 +636,21 @@ quapi_status prepare_step2(quapi_ctx *c, bool rho, Step2Args *out) {
             hipError_t e = launch_plan_tables(pa, c->stream);
             if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "plan kernel launch: %s", hipGetErrorString(e));
         }
+        CoefArgs ca{};
+        ca.bank = c->bank;
+        ca.old_tab = B.old_main();
+        ca.oldf_tab = B.oldf_main();
+        ca.an_tab = L - 1 == 1 ? B.k_lag1() : B.lag(L - 1);    // point n-L+1 seen from n
+        ca.anf_tab = L - 1 == 1 ? B.k_fin1() : B.fin(L - 1);
+        ca.d_tab = B.k_lag1();                                // point n seen from n+1
+        ca.df_tab = B.k_fin1();
+        ca.prec = c->prec;
+        ca.out = c->coef;
+        hipError_t e = launch_step2_coef(ca, c->stream);
+        if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "coefficient kernel launch: %s", hipGetErrorString(e));
         c->plan2_ready = true;
     }
-    a.old_tab = B.old_main();
-    a.oldf_tab = B.oldf_main();
-    a.an_tab = L - 1 == 1 ? B.k_lag1() : B.lag(L - 1);       // point n-L+1 seen from n
-    a.anf_tab = L - 1 == 1 ? B.k_fin1() : B.fin(L - 1);
-    a.d_tab = B.k_lag1();                                   // point n seen from n+1
-    a.df_tab = B.k_fin1();
+    a.coef = c->coef;
     *out = a;
     return QUAPI_OK;
 }
@@ -991,6 +1000,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     for (int k = 0; k < kSlots; ++k)
         c->partials[k] = (double2 *)(w + lay.off_partials) + (size_t)k * lay.partial_blocks * N;
     c->plan2 = (double2 *)(w + lay.off_plan2);
+    c->coef = w + lay.off_coef;
     c->stage = (double2 *)(w + lay.off_stage);
     c->pairs = (double2 *)(w + lay.off_pairs);
     c->sink = (RhoSink *)(w + lay.off_sink);

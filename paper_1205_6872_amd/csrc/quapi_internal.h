@@ -75,9 +75,25 @@ struct Step2Args {
     double2 *partials[2];       // block partials of rho(t_n), rho(t_{n+1}) [grid][N]
     long long m_count;
     int R, Q, grid;
+    const void *coef;           // kCoefCount complex entries in the compute precision
+};
+
+// Coefficients of the fused step in the compute precision, grouped by the new
+// point o of step n so that one o reads one contiguous stretch of kCoefPerO:
+//   OA[o][i'][i]   an[o][i'] old[o][i]    (step-n entry y(o, i') from x(i, i'))
+//   W[o][i + N i'] anf[o][i'] oldf[o][i]  (rho(t_n) weight of x(i, i'))
+//   DO[o][o'][i']  dT[o][o'] old[o'][i']  (step-(n+1) entry (o, o') from y(o, i'))
+//   V[o][o'][i']   df[o'][o] oldf[o'][i'] (rho(t_{n+1}) weight of y(o, i'))
+// old: oldest point seen from the new point (both steps); an: point n-L+1 seen
+// from o (step n); dT[o][o']: point n (= o) seen from o' (step n+1, K folded in).
+constexpr int kCoefOA = 0, kCoefW = 16, kCoefDO = 32, kCoefV = 48, kCoefPerO = 64, kCoefCount = 4 * kCoefPerO;
+struct CoefArgs {
+    const double2 *bank;
     // bank indices: oldest point (interior / final; both steps), point n-L+1 for
     // step n (interior / final), point n for step n+1 (interior / final, K folded)
     int old_tab, oldf_tab, an_tab, anf_tab, d_tab, df_tab;
+    int prec;
+    void *out;
 };
 
 // Factor products of the full-window digit split (see StepArgs::t_lo ...).
@@ -134,6 +150,7 @@ hipError_t launch_set_sink(RhoSink *sink, double2 *base, hipStream_t st);
 hipError_t launch_plan_tables(const PlanArgs &a, hipStream_t st);
 size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q);
 hipError_t launch_step2(int prec, bool with_rho, const Step2Args &a, hipStream_t st);
+hipError_t launch_step2_coef(const CoefArgs &a, hipStream_t st);
 size_t step2_lds_bytes(int prec, bool with_rho, int R, int Q);
 
 }  // namespace quapi

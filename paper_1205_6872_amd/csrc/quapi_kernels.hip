@@ -610,20 +610,52 @@ __global__ void set_sink_kernel(RhoSink *sink, double2 *base) {
 
 // ------------------------------------------------- fused two-step (N = 4)
 struct Step2Lds {
-    unsigned tab, tq, plo, phi, red, total;
+    unsigned tq, plo, phi, red, total;
 };
 __host__ __device__ inline Step2Lds step2_lds_layout(int csize, bool rho, int R, int Q) {
     constexpr int N = 4;
     const int ns = rho ? 4 : 2;
     Step2Lds l;
     unsigned off = 0;
-    l.tab = lds_take(off, 6 * N * N * csize);
     l.tq = lds_take(off, ns * N * Q * csize);
     l.plo = lds_take(off, ns * N * R * csize);
     l.phi = lds_take(off, ns * N * 16);
     l.red = lds_take(off, rho ? 2 * (kBlock / 64) * N * 16 : 0);
     l.total = off;
     return l;
+}
+
+// Wave-uniform read of a coefficient through the constant address space, so
+// that it is fetched by a scalar load into scalar registers (the FMAs then
+// take it as their scalar operand) instead of being broadcast to all 64 lanes
+// from LDS.
+template <typename T>
+__device__ __forceinline__ typename Cx<T>::type coef_ld(const T *p, int k) {
+    const __attribute__((address_space(4))) T *q = (const __attribute__((address_space(4))) T *)p;
+    typename Cx<T>::type v;
+    v.x = q[2 * k];
+    v.y = q[2 * k + 1];
+    return v;
+}
+
+// The fused-step coefficients (layout at kCoefOA ..), computed in FP64 and
+// rounded once to the compute precision.
+template <typename T>
+__global__ void step2_coef_kernel(const CoefArgs a) {
+    constexpr int N = 4, NN = 16;
+    using C = typename Cx<T>::type;
+    const int k = threadIdx.x;
+    if (k >= kCoefCount) return;
+    const double2 *old = a.bank + (size_t)a.old_tab * NN, *oldf = a.bank + (size_t)a.oldf_tab * NN;
+    const double2 *an = a.bank + (size_t)a.an_tab * NN, *anf = a.bank + (size_t)a.anf_tab * NN;
+    const double2 *d = a.bank + (size_t)a.d_tab * NN, *df = a.bank + (size_t)a.df_tab * NN;
+    const int o = k / kCoefPerO, part = k % kCoefPerO / NN, e = k % NN, hi = e / N, lo = e % N;
+    double2 v;
+    if (part * NN == kCoefOA) v = cmul(an[o * N + hi], old[o * N + lo]);             // i' = hi, i = lo
+    else if (part * NN == kCoefW) v = cmul(anf[o * N + hi], oldf[o * N + lo]);       // i' = hi, i = lo
+    else if (part * NN == kCoefDO) v = cmul(d[hi * N + o], old[hi * N + lo]);        // o' = hi, i' = lo
+    else v = cmul(df[hi * N + o], oldf[hi * N + lo]);                               // o' = hi, i' = lo
+    ((C *)a.out)[k] = conv<C>(v);
 }
 
 // Steps n and n+1 (both full-window, n > L) in one pass over the tensor.
@@ -636,6 +668,8 @@ __host__ __device__ inline Step2Lds step2_lds_layout(int csize, bool rho, int R,
 // factor of point n (K folded in); Bn, Cn1 are the products over the digits of m.
 // With RHO, rho(t_n) comes from x with the final-point classes of step n, and
 // rho(t_{n+1}) from y with those of step n+1; both are reduced per block.
+// The coefficients that do not depend on m are read per use through scalar
+// loads; the m-dependent digit products come from LDS.
 template <typename S, typename T, bool RHO>
 __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
     constexpr int N = 4, NN = 16;
@@ -645,13 +679,11 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int R = a.R, Q = a.Q;
     const Step2Lds lay = step2_lds_layout((int)sizeof(C), RHO, R, Q);
-    C *s_tab = (C *)(smem + lay.tab);          // [6][N][N]: old, oldf, an, anf, d, df
     C *s_tq = (C *)(smem + lay.tq);            // [NS][N][Q]
     C *s_plo = (C *)(smem + lay.plo);          // [NS][N][R]
     double2 *s_phi = (double2 *)(smem + lay.phi);
     double2 *s_red = (double2 *)(smem + lay.red);
-    const C *T_old = s_tab, *T_oldf = s_tab + NN, *T_an = s_tab + 2 * NN, *T_anf = s_tab + 3 * NN;
-    const C *T_d = s_tab + 4 * NN, *T_df = s_tab + 5 * NN;
+    const T *coef = (const T *)a.coef;
 
     const int t = threadIdx.x;
     const int cR = kBlock / R, active = cR * R;
@@ -659,12 +691,6 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
     if (t < NS * N) {
         const int s = t / N, o = t % N;
         s_phi[t] = a.t_hi[s][(size_t)o * a.grid + blk];
-    }
-    if (t < 6 * NN) {
-        const int which = t / NN, e = t % NN;
-        const int tb = which == 0 ? a.old_tab : which == 1 ? a.oldf_tab : which == 2 ? a.an_tab
-                     : which == 3 ? a.anf_tab : which == 4 ? a.d_tab : a.df_tab;
-        s_tab[t] = from_d2<C>(a.bank[(size_t)tb * NN + e]);
     }
     for (int idx = t; idx < NS * N * R; idx += kBlock) {
         const int s = idx / (N * R), k = idx % (N * R);
@@ -687,45 +713,36 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
         CS *__restrict__ aout = (CS *)a.a_out;
         const long long mc = a.m_count;
         for (int qm = t / R; qm < Q; qm += cR) {
-            // keep the table reads in the loop (hoisted, the six tables would
-            // need more registers than a thread has)
             asm volatile("" ::: "memory");
             const long long m = m0 + (long long)qm * R + r;
             C x[NN];
 #pragma unroll
             for (int k = 0; k < NN; ++k) x[k] = conv<C>(ain[(long long)NN * m + k]);
-            C cn1[N], cf1[RHO ? N : 1], totf[RHO ? N : 1];
+            C cn1[N], totf[RHO ? N : 1];
 #pragma unroll
             for (int op = 0; op < N; ++op) {
                 cn1[op] = cmul(s_plo[(1 * N + op) * R + r], s_tq[(1 * N + op) * Q + qm]);
-                if (RHO) {
-                    cf1[op] = cmul(s_plo[(3 * N + op) * R + r], s_tq[(3 * N + op) * Q + qm]);
-                    totf[op] = C{};
-                }
+                if (RHO) totf[op] = C{};
             }
             // Per new point o of step n: the step-n entries y(o, i') (and the
             // rho(t_n) term), then every step-(n+1) entry that reads them.
 #pragma unroll
             for (int o = 0; o < N; ++o) {
-                asm volatile("" ::: "memory");  // table reads of this o only
+                asm volatile("" ::: "memory");  // coefficient reads of this o only
+                const T *co = coef + 2 * kCoefPerO * o;
                 const C bn = cmul(s_plo[(0 * N + o) * R + r], s_tq[(0 * N + o) * Q + qm]);
                 C y[N];
 #pragma unroll
                 for (int ip = 0; ip < N; ++ip) {
                     C sum = {};
 #pragma unroll
-                    for (int i = 0; i < N; ++i) cmac(sum, T_old[o * N + i], x[i + N * ip]);
-                    y[ip] = cmul(cmul(T_an[o * N + ip], bn), sum);
+                    for (int i = 0; i < N; ++i) cmac(sum, coef_ld(co, kCoefOA + ip * N + i), x[i + N * ip]);
+                    y[ip] = cmul(bn, sum);
                 }
                 if (RHO) {
                     C tot = {};
 #pragma unroll
-                    for (int ip = 0; ip < N; ++ip) {
-                        C sum = {};
-#pragma unroll
-                        for (int i = 0; i < N; ++i) cmac(sum, T_oldf[o * N + i], x[i + N * ip]);
-                        cmac(tot, T_anf[o * N + ip], sum);
-                    }
+                    for (int k = 0; k < NN; ++k) cmac(tot, coef_ld(co, kCoefW + k), x[k]);
                     const C bnf = cmul(s_plo[(2 * N + o) * R + r], s_tq[(2 * N + o) * Q + qm]);
                     const double2 v = to_d2(cmul(bnf, tot));
                     accn[o].x += v.x;
@@ -736,20 +753,20 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
                     asm volatile("" ::: "memory");
                     C sum = {};
 #pragma unroll
-                    for (int ip = 0; ip < N; ++ip) cmac(sum, T_old[op * N + ip], y[ip]);
-                    aout[m + mc * (o + N * op)] = conv<CS>(cmul(cmul(T_d[op * N + o], cn1[op]), sum));
+                    for (int ip = 0; ip < N; ++ip) cmac(sum, coef_ld(co, kCoefDO + op * N + ip), y[ip]);
+                    aout[m + mc * (o + N * op)] = conv<CS>(cmul(cn1[op], sum));
                     if (RHO) {
-                        C sf = {};
 #pragma unroll
-                        for (int ip = 0; ip < N; ++ip) cmac(sf, T_oldf[op * N + ip], y[ip]);
-                        cmac(totf[op], T_df[op * N + o], sf);
+                        for (int ip = 0; ip < N; ++ip) cmac(totf[op], coef_ld(co, kCoefV + op * N + ip), y[ip]);
                     }
                 }
             }
             if (RHO) {
+                asm volatile("" ::: "memory");
 #pragma unroll
                 for (int op = 0; op < N; ++op) {
-                    const double2 v = to_d2(cmul(cf1[op], totf[op]));
+                    const C cf1 = cmul(s_plo[(3 * N + op) * R + r], s_tq[(3 * N + op) * Q + qm]);
+                    const double2 v = to_d2(cmul(cf1, totf[op]));
                     accn1[op].x += v.x;
                     accn1[op].y += v.y;
                 }
@@ -874,6 +891,12 @@ hipError_t launch_step2(int prec, bool with_rho, const Step2Args &a, hipStream_t
         return with_rho ? launch_step2_t<float, double, true>(a, st) : launch_step2_t<float, double, false>(a, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_step2_coef(const CoefArgs &a, hipStream_t st) {
+    if (a.prec == kPrecC64) hipLaunchKernelGGL(step2_coef_kernel<float>, dim3(1), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL(step2_coef_kernel<double>, dim3(1), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_g_quad(const QuadArgs &a, int n_t, double2 *g, hipStream_t st) {
