@@ -185,7 +185,7 @@ def main() -> int:
     ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64, help="0 skips the serving run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step_kernel_traffic_l15.json"))
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step2_kernel_traffic_spin_boson_l15.json"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
