@@ -233,7 +233,7 @@ std::string validate(const quapi_params *p) {
 // ------------------------------------------------------------------ layout
 struct Layout {
     size_t a_bytes;                  // one tensor buffer
-    size_t off_a0, off_a1, off_bank, off_g, off_eta, off_U, off_s, off_H, off_rho0;
+    size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
     size_t off_plan, off_plan2, off_coef, off_pairs, off_sink;
     size_t total;
@@ -265,6 +265,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_a0 = take(l.a_bytes);
     l.off_a1 = take(l.a_bytes);
     l.off_bank = take((size_t)l.n_tables * N * N * 16);
+    l.off_bankf = take(p.dtype == QUAPI_C64 ? (size_t)l.n_tables * N * N * 8 : 0);
     l.off_g = take((size_t)(2 * L + 3) * 16);
     l.off_eta = take((size_t)(4 * L + 2) * 16);
     l.off_U = take((size_t)M * M * 16);
@@ -327,6 +328,7 @@ struct quapi_ctx {
     double2 *partials[kSlots] = {};
     double2 *stage = nullptr, *plan = nullptr, *plan2 = nullptr, *pairs = nullptr;
     void *coef = nullptr;         // fused-step coefficients (compute precision)
+    float2 *bank_f = nullptr;     // the bank rounded to complex64 (FP32 arithmetic only)
     RhoSink *sink = nullptr;
     // captured full-window steps, [without / with rho]: graph1 two single steps
     // A[0] -> A[1] -> A[0]; graph2[.][p] one fused launch A[p] -> A[1-p]
@@ -439,6 +441,7 @@ StepPlan plan_step(const quapi_ctx *c, int n) {
         a.oldf_tab = n == L ? B.oldf_first() : B.oldf_main();
     }
     a.bank = c->bank;
+    a.bank_c = c->bank_f ? (const void *)c->bank_f : (const void *)c->bank;
     return sp;
 }
 
@@ -993,6 +996,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->A[0] = w + lay.off_a0;
     c->A[1] = w + lay.off_a1;
     c->bank = (double2 *)(w + lay.off_bank);
+    c->bank_f = c->prec == kPrecC64 ? (float2 *)(w + lay.off_bankf) : nullptr;
     c->g = (double2 *)(w + lay.off_g);
     c->eta = (double2 *)(w + lay.off_eta);
     c->U = (double2 *)(w + lay.off_U);
@@ -1070,6 +1074,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     ta.U = c->U;
     ta.eta = c->eta;
     ta.bank = c->bank;
+    ta.bank_f = c->bank_f;
     if (e == hipSuccess) e = launch_tables(ta, c->stream);
     if (e == hipSuccess)
         e = launch_init_tensor(N, c->prec, c->rho0_d, c->bank, BankLayout{L}.self_end(), c->A[0], c->stream);

@@ -48,6 +48,7 @@ struct StepArgs {
     const void *a_in;
     void *a_out;
     const double2 *bank;
+    const void *bank_c;         // the bank in the compute precision (N >= 9 reads it by scalar loads)
     // Full-window steps: factor products over the thread / sweep / block digits,
     // precomputed once per context (FP64, [N][R], [N][Q], [N][grid]).  NULL:
     // the kernel multiplies the bank tables of the digits itself (growth steps).
@@ -124,6 +125,7 @@ struct TablesArgs {
     double2 *U;                 // out: M x M
     double2 *eta;               // out: 4L+2 classes
     double2 *bank;              // out: BankLayout{L}.count() tables
+    float2 *bank_f;             // out (if not NULL): the same tables rounded to complex64
 };
 
 // Kernel launchers (quapi_kernels.hip).  They return the launch status.

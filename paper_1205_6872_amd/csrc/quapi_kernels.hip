@@ -299,6 +299,7 @@ __global__ void __launch_bounds__(kBlock) tables_kernel(const TablesArgs a) {
             v = cmul(v, L == 1 ? Kop : one);
         }
         a.bank[idx] = v;
+        if (a.bank_f) a.bank_f[idx] = make_float2((float)v.x, (float)v.y);
     }
 }
 
@@ -322,8 +323,8 @@ __host__ __device__ inline StepLds step_lds_layout(int N, int csize, bool rho, i
                                                    bool plo_reg) {
     StepLds l;
     unsigned off = 0;
-    l.old = lds_take(off, N * I * csize);
-    l.oldf = lds_take(off, rho ? N * I * csize : 0);
+    l.old = lds_take(off, plo_reg ? N * I * csize : 0);
+    l.oldf = lds_take(off, (plo_reg && rho) ? N * I * csize : 0);
     l.tq = lds_take(off, N * Q * csize);
     l.tqf = lds_take(off, rho ? N * Q * csize : 0);
     l.plo = lds_take(off, plo_reg ? 0 : N * R * csize);
@@ -332,6 +333,19 @@ __host__ __device__ inline StepLds step_lds_layout(int N, int csize, bool rho, i
     l.red = lds_take(off, rho ? (kBlock / 64) * N * 16 : 0);
     l.total = off;
     return l;
+}
+
+// Wave-uniform read of a coefficient through the constant address space, so
+// that it is fetched by a scalar load into scalar registers (the FMAs then
+// take it as their scalar operand) instead of being broadcast to all 64 lanes
+// from LDS.
+template <typename T>
+__device__ __forceinline__ typename Cx<T>::type coef_ld(const T *p, int k) {
+    const __attribute__((address_space(4))) T *q = (const __attribute__((address_space(4))) T *)p;
+    typename Cx<T>::type v;
+    v.x = q[2 * k];
+    v.y = q[2 * k + 1];
+    return v;
 }
 
 // Product over nd digits of v (base N, least significant first) of the bank
@@ -408,11 +422,15 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
         s_phi[t] = ph;
         s_phi[N + t] = phf;
     }
-    for (int idx = t; idx < N * I; idx += kBlock) {
+    for (int idx = t; OLD_REG && idx < N * I; idx += kBlock) {
         const int o = idx / I, i = idx % I;
         s_old[idx] = from_d2<C>(bank[(size_t)a.old_tab * (N * N) + o * N + i]);
         if (RHO) s_oldf[idx] = from_d2<C>(bank[(size_t)a.oldf_tab * (N * N) + o * N + i]);
     }
+    // N >= 9: the oldest-point tables are read per use by scalar loads from
+    // the bank in the compute precision (wave-uniform operands of the FMAs).
+    const T *old_c = (const T *)a.bank_c + 2 * (size_t)a.old_tab * (N * N);
+    const T *oldf_c = (const T *)a.bank_c + 2 * (size_t)a.oldf_tab * (N * N);
     if (!PLO_REG) {
         for (int idx = t; idx < N * R; idx += kBlock) {
             const int o = idx / R, v = idx % R;
@@ -485,16 +503,18 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
                 const long long m = m0 + (long long)qm * R + r;
 #pragma unroll
                 for (int o = 0; o < N; ++o) {
+                    if (!OLD_REG) asm volatile("" ::: "memory");   // table reads of this o only
                     C s = {};
 #pragma unroll
-                    for (int i = 0; i < I; ++i) cmac(s, OLD_REG ? old_r[o * I + i] : s_old[o * I + i], x[u][i]);
+                    for (int i = 0; i < I; ++i) cmac(s, OLD_REG ? old_r[o * I + i] : coef_ld(old_c, o * N + i), x[u][i]);
                     const C p = cmul(PLO_REG ? plo[o] : s_plo[o * R + r], s_tq[o * Q + qm]);
                     aout[m + mc * o] = conv<CS>(cmul(s, p));
                     if (RHO) {
+                        if (!OLD_REG) asm volatile("" ::: "memory");
                         C sf = {};
 #pragma unroll
                         for (int i = 0; i < I; ++i)
-                            cmac(sf, OLD_REG ? oldf_r[o * I + i] : s_oldf[o * I + i], x[u][i]);
+                            cmac(sf, OLD_REG ? oldf_r[o * I + i] : coef_ld(oldf_c, o * N + i), x[u][i]);
                         const double2 v = to_d2(cmul(sf, s_tqf[o * Q + qm]));
                         acc[o].x += v.x;
                         acc[o].y += v.y;
@@ -623,19 +643,6 @@ __host__ __device__ inline Step2Lds step2_lds_layout(int csize, bool rho, int R,
     l.red = lds_take(off, rho ? 2 * (kBlock / 64) * N * 16 : 0);
     l.total = off;
     return l;
-}
-
-// Wave-uniform read of a coefficient through the constant address space, so
-// that it is fetched by a scalar load into scalar registers (the FMAs then
-// take it as their scalar operand) instead of being broadcast to all 64 lanes
-// from LDS.
-template <typename T>
-__device__ __forceinline__ typename Cx<T>::type coef_ld(const T *p, int k) {
-    const __attribute__((address_space(4))) T *q = (const __attribute__((address_space(4))) T *)p;
-    typename Cx<T>::type v;
-    v.x = q[2 * k];
-    v.y = q[2 * k + 1];
-    return v;
 }
 
 // The fused-step coefficients (layout at kCoefOA ..), computed in FP64 and
