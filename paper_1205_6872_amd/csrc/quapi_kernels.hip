@@ -852,6 +852,178 @@ __global__ void __launch_bounds__(kBlock) plan_tables_kernel(const PlanArgs a) {
     }
 }
 
+// ------------------------------------ full-window step on MFMA (N = 16)
+// For N = 16 the contraction over the oldest point is a 16 x 16 complex matrix
+// (32 x 16 with the final-point table for rho) applied to every item's 16
+// inputs: a real GEMM with 64 rows (Re / Im of each output, interior and final
+// tables), K = 32 (the item's 32 real words in memory order) and one column per
+// item.  A wave runs it on 16 items at a time with 16x16x4 MFMAs (FP32 for the
+// complex64 tier, FP64 otherwise): the coefficients are per-lane A fragments
+// kept in registers for the whole block, the inputs are B fragments loaded
+// straight from HBM, and each lane's accumulators hold 4 outputs of one item.
+//
+// MFMA 16x16x4 lane layout (wave64): A[i][k] in lane i + 16k, B[k][j] in lane
+// j + 16k; D[i][j] in lane j + 16(i / 4), element i % 4 for f32, and in lane
+// j + 16(i % 4), element i / 4 for f64.  The K index of MFMA step s held by
+// lane group g = lane / 16 is word 8g + s of the item, so a lane loads 8
+// consecutive words (32 B at complex64, 64 B at complex128).
+// Rows of row block b (tables: blocks 0, 1 interior, 2, 3 final point) are
+// numbered so that lane group g receives, as D elements v = 0..3, the real and
+// imaginary parts of outputs o = 8(b % 2) + 2g + v / 2.  Lane j + 16g therefore
+// holds outputs o = 2g, 2g+1 (block 0), 8+2g, 9+2g (block 1) of item j, and the
+// same four with the final-point table in blocks 2, 3.
+struct Step16Lds {
+    unsigned tq, tqf, red, total;
+};
+__host__ __device__ inline Step16Lds step16_lds_layout(int csize, bool rho, int Q) {
+    Step16Lds l;
+    unsigned off = 0;
+    l.tq = lds_take(off, 16 * Q * csize);
+    l.tqf = lds_take(off, rho ? 16 * Q * csize : 0);
+    l.red = lds_take(off, rho ? (kBlock / 64) * 16 * 16 : 0);
+    l.total = off;
+    return l;
+}
+
+template <typename T> struct Mfma16;
+template <> struct Mfma16<float> {
+    static constexpr bool kElemMajor = false;       // D row i: group i / 4, element i % 4
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 run(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma16<double> {
+    static constexpr bool kElemMajor = true;        // D row i: group i % 4, element i / 4
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 run(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename S, typename T, bool RHO>
+__global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
+    constexpr int N = 16, NB = RHO ? 4 : 2;
+    using C = typename Cx<T>::type;
+    using CS = typename Cx<S>::type;
+    using V4 = typename Mfma16<T>::v4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Q = a.Q;                                  // R = 16: one item per lane column
+    const Step16Lds lay = step16_lds_layout((int)sizeof(C), RHO, Q);
+    C *s_tq = (C *)(smem + lay.tq);                      // [N][Q] mid x high products
+    C *s_tqf = (C *)(smem + lay.tqf);
+    double2 *s_red = (double2 *)(smem + lay.red);        // [waves][N]
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    const long long blk = blockIdx.x;
+
+    for (int idx = t; idx < N * Q; idx += kBlock) {
+        const int o = idx / Q;
+        s_tq[idx] = from_d2<C>(cmul(a.t_hi[(size_t)o * a.grid + blk], a.t_mid[idx]));
+        if (RHO) s_tqf[idx] = from_d2<C>(cmul(a.t_hif[(size_t)o * a.grid + blk], a.t_midf[idx]));
+    }
+    // A fragments: row 16b + j, word 8g + s
+    T afr[NB][8];
+    {
+        const C *bc = (const C *)a.bank_c;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            // A row j of block b lands in D lane group gd as element vd
+            const int gd = Mfma16<T>::kElemMajor ? (j & 3) : (j >> 2);
+            const int vd = Mfma16<T>::kElemMajor ? (j >> 2) : (j & 3);
+            const int tb = b >= 2 ? a.oldf_tab : a.old_tab;
+            const int o = 8 * (b & 1) + 2 * gd + (vd >> 1), im_row = vd & 1;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int w = 8 * g + s, i = w / 2, im_word = w & 1;
+                const C c = bc[(size_t)tb * (N * N) + o * N + i];
+                // Re z = cr xr - ci xi ; Im z = ci xr + cr xi
+                afr[b][s] = im_row ? (im_word ? c.x : c.y) : (im_word ? -c.y : c.x);
+            }
+        }
+    }
+    // per-lane digit-0 products (item j) of its four outputs
+    int oo[4] = {2 * g, 2 * g + 1, 8 + 2 * g, 9 + 2 * g};
+    C plo[4];
+    double2 plof[4], acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        plo[q] = from_d2<C>(a.t_lo[oo[q] * 16 + j]);
+        plof[q] = RHO ? a.t_lof[oo[q] * 16 + j] : make_double2(1.0, 0.0);
+        acc[q] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+
+    const long long m0 = blk * 16LL * Q;
+    const long long mc = a.m_count;
+    const S *__restrict__ ain = (const S *)a.a_in;
+    CS *__restrict__ aout = (CS *)a.a_out;
+    for (int qm = wave; qm < Q; qm += kBlock / 64) {
+        const long long m = m0 + 16LL * qm + j;
+        T xw[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) xw[s] = (T)ain[32 * m + 8 * g + s];
+        V4 d[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) d[b] = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) d[b] = Mfma16<T>::run(afr[b][s], xw[s], d[b]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = q / 2, e = 2 * (q % 2);
+            C z;
+            z.x = d[b][e];
+            z.y = d[b][e + 1];
+            const C p = cmul(plo[q], s_tq[oo[q] * Q + qm]);
+            aout[m + mc * oo[q]] = conv<CS>(cmul(p, z));
+            if (RHO) {
+                C zf;
+                zf.x = d[2 + b][e];
+                zf.y = d[2 + b][e + 1];
+                const double2 v = to_d2(cmul(s_tqf[oo[q] * Q + qm], zf));
+                acc[q].x += v.x;
+                acc[q].y += v.y;
+            }
+        }
+    }
+    if (RHO) {
+        // sum over the 16 items of the lane group, then over the waves
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double2 v = cmul(acc[q], plof[q]);
+            for (int off = 8; off > 0; off >>= 1) {
+                v.x += __shfl_xor(v.x, off, 64);
+                v.y += __shfl_xor(v.y, off, 64);
+            }
+            if (j == 0) s_red[wave * N + oo[q]] = v;
+        }
+        __syncthreads();
+        if (t < N) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int w = 0; w < kBlock / 64; ++w) {
+                s.x += s_red[w * N + t].x;
+                s.y += s_red[w * N + t].y;
+            }
+            a.partials[blk * N + t] = s;
+        }
+    }
+}
+
+template <typename S, typename T, bool RHO>
+hipError_t launch_step16_t(const StepArgs &a, int grid, hipStream_t st) {
+    using C = typename Cx<T>::type;
+    const Step16Lds lay = step16_lds_layout((int)sizeof(C), RHO, a.Q);
+    hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO>), dim3(grid), dim3(kBlock), lay.total, st, a);
+    return hipGetLastError();
+}
+
+// The MFMA form runs the full-window steps of N = 16 whose thread digit split
+// gives 16 items per wave column (R = 16).
+__host__ __device__ inline bool use_step16(int N, bool grow, int R) { return N == 16 && !grow && R == 16; }
+
 template <int N, typename S, typename T, bool RHO, bool GROW>
 hipError_t launch_step_t(const StepArgs &a, int grid, hipStream_t st) {
     using C = typename Cx<T>::type;
@@ -881,6 +1053,7 @@ hipError_t launch_step_dt(int N, bool rho, bool grow, const StepArgs &a, int gri
 }  // namespace
 
 size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q) {
+    if (use_step16(N, grow, R)) return step16_lds_layout(prec == kPrecC64 ? 8 : 16, with_rho, Q).total;
     return step_lds_layout(N, prec == kPrecC64 ? 8 : 16, with_rho, grow ? 1 : N, R, Q, N <= 4).total;
 }
 
@@ -926,6 +1099,20 @@ hipError_t launch_init_tensor(int N, int prec, const double2 *rho0, const double
 
 hipError_t launch_step(int N, int prec, bool with_rho, bool grow, const StepArgs &a, int grid,
                        hipStream_t st) {
+    if (use_step16(N, grow, a.R)) {
+        switch (prec) {
+        case kPrecC128:
+            return with_rho ? launch_step16_t<double, double, true>(a, grid, st)
+                            : launch_step16_t<double, double, false>(a, grid, st);
+        case kPrecC64:
+            return with_rho ? launch_step16_t<float, float, true>(a, grid, st)
+                            : launch_step16_t<float, float, false>(a, grid, st);
+        case kPrecC64F64:
+            return with_rho ? launch_step16_t<float, double, true>(a, grid, st)
+                            : launch_step16_t<float, double, false>(a, grid, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (prec) {
     case kPrecC128: return launch_step_dt<double, double>(N, with_rho, grow, a, grid, st);
     case kPrecC64: return launch_step_dt<float, float>(N, with_rho, grow, a, grid, st);

@@ -173,10 +173,13 @@ def _sampled_fused_check(w, dtype, tol):
     mr = N ** (L - 2)                       # items: digits of points n-L+2 .. n-1
     ms = np.unique(np.concatenate([[0, mr - 1], rng.integers(0, mr, 14)]))
     with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
-        ctx.propagate(L + 1, sel=[L + 1])   # through the first full-window steps
-        n = L + 2                           # the fused pair is (n, n + 1)
+        ctx.propagate(L, sel=[L])           # growth and the first full-window step n = L
+        n = L + 1                           # pairs start at n = L+1, L+3, ...: (n, n + 1) is one
         a_in = {int(m): ctx.read_tensor(N * N * int(m), N * N) for m in ms}
+        ctx.set_timing(True)
         rho = ctx.propagate(2)
+        t = ctx.get_timing()
+        assert (t["step_launches"], t["step_steps"]) == (1, 2), t     # one fused launch ran both
         assert np.abs(np.trace(rho, axis1=1, axis2=2) - 1).max() <= (1e-12 if dtype == "c128" else 1e-6)
         worst = 0.0
         for m in ms:
@@ -210,6 +213,34 @@ def test_headline_size_sampled_entries_c64():
 def test_headline_size_sampled_entries_c64f64():
     # only the complex64 rounding of the stored values remains
     _sampled_entry_check(W.spin_boson_l15("c64f64"), "c64f64", 2e-7)
+
+
+def _fits(w, dtype):
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    need = Q.footprint(Q.params_from(w, dtype=dtype))
+    print(f"case {w.name} L={w.L} {dtype}: footprint {need / 2**30:.1f} GiB, free {free / 2**30:.1f} GiB", flush=True)
+    return need <= free
+
+
+def test_maximum_size_m2_l16_fused_pair_c128():
+    # 4^16 = 4.3e9 entries, 2 x 68.7 GB: the largest complex128 M = 2 window that fits in HBM;
+    # tensor offsets pass 2^32 entries
+    w = W.spin_boson_l15("c128").with_(L=16, name="spin_boson_l16")
+    if not _fits(w, "c128"):
+        pytest.skip("footprint exceeds free device memory")
+    _sampled_fused_check(w, "c128", 1e-12)
+
+
+def test_maximum_size_m4_l8_single_steps_c64():
+    # 16^8 = 4.3e9 entries, complex64 (2 x 34.4 GB); N = 16 runs single steps
+    rng = np.random.default_rng(23)
+    w = W.spin_boson_l7().with_(name="four_level_l8", M=4, s=np.linspace(-1, 1, 4),
+                                H=W.random_hermitian(rng, 4), rho0=np.diag([1.0, 0, 0, 0]).astype(complex),
+                                L=8, xi=0.3, dtype="c64")
+    if not _fits(w, "c64"):
+        pytest.skip("footprint exceeds free device memory")
+    _sampled_entry_check(w, "c64", 2e-5)
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c64f64"])
