@@ -1,0 +1,77 @@
+"""Per-shape step timing through the C ABI (library timing events on its stream).
+
+    python3 -m paper_1205_6872_amd.stepbench [--cases M:L,...] [--dtypes c128,c64,c64f64] [--steps K]
+
+For each case (M levels, memory length L) and storage/arithmetic mode it runs
+the growth steps, then K full-window steps with rho at every step and K
+without, and prints one JSON line per case: the mean full-window launch time
+with and without rho, steps per launch (2 where two steps are fused), and the
+algorithmic HBM rate 2 * N^L * sizeof(complex) per step.  The system is a
+seeded random Hermitian H with evenly spaced coupling eigenvalues and an
+Ohmic bath (xi = 0.3, omega_c = 7.5, kT = 0.2, dt = 0.25).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+
+from . import quapi as Q
+from . import workloads as W
+
+
+def case_workload(M: int, L: int, dtype: str, seed: int = 1) -> W.Workload:
+    rng = np.random.default_rng(seed)
+    rho0 = np.zeros((M, M), dtype=np.complex128)
+    rho0[0, 0] = 1.0
+    return W.Workload(name=f"random_m{M}_l{L}", M=M, s=np.linspace(-1.0, 1.0, M),
+                      H=W.random_hermitian(rng, M), rho0=rho0, kT=0.2, dt=0.25, L=L,
+                      n_steps=0, xi=0.3, omega_c=7.5, dtype=dtype)
+
+
+def time_case(M: int, L: int, dtype: str, steps: int) -> dict:
+    w = case_workload(M, L, dtype)
+    N = M * M
+    with Q.create(Q.params_from(w)) as ctx:
+        ctx.propagate(L)                                  # growth and the first full-window step
+        ctx.set_timing(True)
+        ctx.get_timing()
+        ctx.propagate(steps)                              # rho at every step
+        t_rho = ctx.get_timing()
+        first = ctx.step_count() + 1
+        ctx.propagate(steps, sel=[first + steps - 1])     # rho only at the last step
+        t_no = ctx.get_timing()
+    cs = 16 if dtype == "c128" else 8
+    step_bytes = 2 * N ** L * cs
+
+    def per(t):
+        launches = max(t["step_launches"], 1)
+        spl = t["step_steps"] / launches
+        ms = t["step_ms"] / launches
+        return ms, spl, step_bytes * spl / (ms * 1e-3) / 1e9
+
+    ms_r, spl_r, gbs_r = per(t_rho)
+    ms_n, spl_n, gbs_n = per(t_no)
+    return {"M": M, "L": L, "dtype": dtype, "entries": N ** L, "steps": steps,
+            "rho_launch_ms": round(ms_r, 4), "rho_steps_per_launch": round(spl_r, 3), "rho_gbs": round(gbs_r, 1),
+            "norho_launch_ms": round(ms_n, 4), "norho_steps_per_launch": round(spl_n, 3),
+            "norho_gbs": round(gbs_n, 1)}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--cases", default="4:7,3:8,2:12")
+    ap.add_argument("--dtypes", default="c128,c64,c64f64")
+    ap.add_argument("--steps", type=int, default=10)
+    args = ap.parse_args(argv)
+    for c in args.cases.split(","):
+        M, L = (int(v) for v in c.split(":"))
+        for d in args.dtypes.split(","):
+            print(json.dumps(time_case(M, L, d, args.steps)), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
