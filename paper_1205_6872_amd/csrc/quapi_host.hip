@@ -1075,6 +1075,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     ta.eta = c->eta;
     ta.bank = c->bank;
     ta.bank_f = c->bank_f;
+    ta.k_trace_exact = c->prec == kPrecC64;            // FP32 arithmetic: keep the trace exact per step
     if (e == hipSuccess) e = launch_tables(ta, c->stream);
     if (e == hipSuccess)
         e = launch_init_tensor(N, c->prec, c->rho0_d, c->bank, BankLayout{L}.self_end(), c->A[0], c->stream);

@@ -126,6 +126,7 @@ struct TablesArgs {
     double2 *eta;               // out: 4L+2 classes
     double2 *bank;              // out: BankLayout{L}.count() tables
     float2 *bank_f;             // out (if not NULL): the same tables rounded to complex64
+    int k_trace_exact;          // K rows (a, a) chosen on the FP32 grid with exact column sums
 };
 
 // Kernel launchers (quapi_kernels.hip).  They return the launch status.

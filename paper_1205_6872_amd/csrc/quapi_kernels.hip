@@ -228,10 +228,54 @@ __device__ void expm_minus_i_h_dt(const double2 *H, int M, double dt, double2 *U
     for (int i = 0; i < MM; ++i) U[i] = T[i];
 }
 
+// Trace-exact FP32 representatives of the propagator's diagonal rows.  The
+// trace of rho is kept by the propagation because every influence factor of a
+// diagonal point o = (a, a) is 1 and, by unitarity of U, the K entries of the
+// diagonal rows sum to delta_cd over a for every column p = (c, d).  Rounding
+// each entry to FP32 on its own breaks that sum by a fixed amount that then
+// acts at every step (a linear trace drift).  Here, for each column and each
+// of the real and imaginary parts, the entries other than the largest one are
+// rounded to the FP32 spacing of the largest, and the largest is set to the
+// target minus their sum; all of them are then exact FP32 values whose sum is
+// exactly the target (up to the largest leaving its binade).  Change per entry:
+// at most half an FP32 spacing of the column's largest entry.
+__device__ void trace_exact_column(const double2 *U, int M, int c, int d, double2 *out) {
+    double2 v[kMaxM];
+    for (int q = 0; q < M; ++q) {
+        const double2 u2 = U[q * M + d];
+        v[q] = cmul(U[q * M + c], make_double2(u2.x, -u2.y));
+    }
+    for (int part = 0; part < 2; ++part) {
+        const double target = (part == 0 && c == d) ? 1.0 : 0.0;
+        int big = 0;
+        for (int q = 1; q < M; ++q)
+            if (fabs(part ? v[q].y : v[q].x) > fabs(part ? v[big].y : v[big].x)) big = q;
+        const double vb = fabs(part ? v[big].y : v[big].x);
+        double w[kMaxM];
+        if (vb == 0.0) {
+            for (int q = 0; q < M; ++q) w[q] = 0.0;
+        } else {
+            const double grid = ldexp(1.0, ilogb(vb) - 23);   // FP32 spacing in the binade of vb
+            double rest = 0.0;
+            for (int q = 0; q < M; ++q) {
+                if (q == big) continue;
+                w[q] = rint((part ? v[q].y : v[q].x) / grid) * grid;
+                rest += w[q];
+            }
+            w[big] = target - rest;
+        }
+        for (int q = 0; q < M; ++q) {
+            if (part) out[q].y = w[q];
+            else out[q].x = w[q];
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) tables_kernel(const TablesArgs a) {
     __shared__ double2 sU[kMaxM * kMaxM];
     __shared__ double2 sEta[4 * kMaxL + 2];
     __shared__ double sS[kMaxM];
+    __shared__ double2 sKd[kMaxM * kMaxM * kMaxM];    // [a][p]: K[(a, a)][p], trace-exact
     const int M = a.M, N = M * M, NN = N * N, L = a.L;
     const int t = threadIdx.x;
     if (t == 0) expm_minus_i_h_dt(a.H, M, a.dt, sU);
@@ -263,6 +307,12 @@ __global__ void __launch_bounds__(kBlock) tables_kernel(const TablesArgs a) {
     }
     __syncthreads();
     if (t < M * M) a.U[t] = sU[t];
+    if (a.k_trace_exact && t < N) {
+        double2 col[kMaxM];
+        trace_exact_column(sU, M, t / M, t % M, col);
+        for (int q = 0; q < M; ++q) sKd[q * N + t] = col[q];
+    }
+    __syncthreads();
     const BankLayout B{L};
     const double2 e_self_int = sEta[0], e_self_end = sEta[1];
     auto lag = [&](int D) { return sEta[1 + D]; };
@@ -274,6 +324,7 @@ __global__ void __launch_bounds__(kBlock) tables_kernel(const TablesArgs a) {
         const int tb = idx / NN, o = (idx / N) % N, p = idx % N;
         const int oa = o / M, ob = o % M, pc = p / M, pd = p % M;
         const double2 Kop = [&] {
+            if (a.k_trace_exact && oa == ob) return sKd[oa * N + p];
             const double2 u1 = sU[oa * M + pc], u2 = sU[ob * M + pd];
             return cmul(u1, make_double2(u2.x, -u2.y));   // U[a][c] conj(U[b][d])
         }();
