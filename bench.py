@@ -145,16 +145,20 @@ def copy_ceiling(nbytes: int = 2 ** 34):
             "kernel_ms": round(ms, 4), "kernel": "torch copy_ of 16 GiB float64"}
 
 
-def serve_trace(n_requests: int):
+def serve_trace(n_requests: int, policy: str = "sjf", chunk_ms=8.0, chunk_steps: int = 32):
     """Serve the first n_requests of the seeded 512-request trace in real time."""
     from paper_1205_6872_amd import workloads as W
     from paper_1205_6872_amd.serve import Server, summarize
     reqs = W.serving_requests()[:n_requests]
-    log(f"bench: serving {len(reqs)} requests ({reqs[-1].meta['arrival_s']:.1f} s of arrivals)")
-    res = Server(max_active=8, chunk_steps=32, progress=True).run(reqs, realtime=True)
+    log(f"bench: serving {len(reqs)} requests ({reqs[-1].meta['arrival_s']:.1f} s of arrivals), "
+        f"policy {policy}")
+    res = Server(max_active=8, chunk_steps=chunk_steps, chunk_ms=chunk_ms, policy=policy,
+                 progress=True).run(reqs, realtime=True)
     s = summarize(res)
     s.update({"trace": "seeded Poisson, 20 requests/s, seed 2026", "sample": f"first {len(reqs)} of 512",
-              "max_active": 8, "rho_every_step": True,
+              "max_active": 8, "policy": policy,
+              "chunk": f"{chunk_ms} ms of estimated device time" if chunk_ms else f"{chunk_steps} steps",
+              "rho_every_step": True,
               "by_dtype": {d: sum(1 for r in res if r.dtype == d) for d in sorted({r.dtype for r in res})}})
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
 
@@ -259,6 +263,7 @@ def main() -> int:
         out["copy_ceiling"] = copy_ceiling()
     if args.serve_requests > 0:
         out["serving"] = serve_trace(args.serve_requests)
+        out["serving_fifo"] = serve_trace(args.serve_requests, policy="fifo", chunk_ms=None)
     if not args.no_cpu_baseline:
         log("bench: cpu_baseline (oracle on the host)")
         cb = cpu_baseline(w.with_(dtype="c128"))

@@ -3,17 +3,25 @@
 Requests (different M, L, bath, kT, step counts and precisions) arrive over
 time.  The server:
 
-* admits them in arrival order whenever a slot is free and the request's
-  device footprint (the library's ``footprint``) fits in the remaining HBM
-  budget -- the paper's "did not fit on the GPU" becomes "wait for memory";
+* admits a waiting request whenever a slot is free and the request's device
+  footprint (the library's ``footprint``) fits in the remaining HBM budget --
+  the paper's "did not fit on the GPU" becomes "wait for memory".  Policy
+  ``"fifo"`` admits in arrival order; ``"sjf"`` admits the waiting request
+  with the least estimated device work first (non-preemptive);
 * keeps every admitted request's tensor resident in its own workspace (a
   torch uint8 tensor) and runs it on its own HIP stream, so the work of
   different requests overlaps on the device;
 * enqueues each request's steps in chunks through ``propagate_async``,
   round-robin over the active requests, at most two chunks in flight per
-  request, so a long request never blocks a short one behind it;
+  request.  A chunk is sized to about ``chunk_ms`` of estimated device time,
+  so the streams that share a hardware queue interleave finely and a long
+  request's steps do not hold a short one's for long;
 * records arrival, admission and completion times and reports p50/p99
   latency (arrival -> rho on the host) and aggregate throughput.
+
+The work estimate is the HBM traffic of the steps at a nominal rate:
+2 N^min(n+1, L) sizeof(complex) bytes per step n at 4 TB/s, and at least
+10 microseconds per step (launch-bound small tensors).
 
 Every request returns rho(t_k) for k = 0..n_steps ('allPoints', Sec. IV of
 the paper).  The kernels are deterministic and each request has its own
@@ -31,12 +39,28 @@ import numpy as np
 
 from . import quapi as Q
 
-__all__ = ["Server", "RequestResult", "work_entries", "summarize"]
+__all__ = ["Server", "RequestResult", "work_entries", "est_step_s", "est_work_s", "summarize"]
 
 
 def work_entries(N: int, L: int, n_steps: int) -> int:
     """Tensor entries written over a run: step n writes N^min(n+1, L) entries."""
     return int(sum(N ** min(n + 1, L) for n in range(1, n_steps + 1)))
+
+
+_NOMINAL_BYTES_PER_S = 4.0e12
+_MIN_STEP_S = 1.0e-5
+
+
+def est_step_s(w) -> float:
+    """Estimated device time of one full-window step of request w."""
+    cs = 16 if w.dtype == "c128" else 8
+    return max(2.0 * w.N ** w.L * cs / _NOMINAL_BYTES_PER_S, _MIN_STEP_S)
+
+
+def est_work_s(w) -> float:
+    """Estimated device time of the whole request."""
+    cs = 16 if w.dtype == "c128" else 8
+    return max(2.0 * work_entries(w.N, w.L, w.n_steps) * cs / _NOMINAL_BYTES_PER_S, _MIN_STEP_S * w.n_steps)
 
 
 @dataclass
@@ -76,12 +100,19 @@ class Server:
     """Admission by footprint, one stream and context per active request."""
 
     def __init__(self, max_active: int = 8, hbm_budget: Optional[int] = None, chunk_steps: int = 32,
-                 device: str = "cuda:0", progress: bool = False):
+                 device: str = "cuda:0", progress: bool = False, policy: str = "fifo",
+                 chunk_ms: Optional[float] = None):
+        """chunk_steps: steps per chunk; with chunk_ms set, the chunk is instead
+        sized to about chunk_ms of estimated device time (2 to 256 steps)."""
         import torch
+        if policy not in ("fifo", "sjf"):
+            raise ValueError(f"unknown policy {policy!r}")
         self.torch = torch
         self.device = device
         self.max_active = max_active
         self.chunk = max(2, chunk_steps)
+        self.chunk_ms = chunk_ms
+        self.policy = policy
         self.progress = progress
         self.streams = [torch.cuda.Stream(device) for _ in range(max_active)]
         if hbm_budget is None:
@@ -120,16 +151,25 @@ class Server:
             t = now()
             while pending and (not realtime or requests[pending[0]].meta.get("arrival_s", 0.0) <= t):
                 waiting.append(pending.popleft())
-            # admission in arrival order, by slot and HBM footprint
+            # admission by slot and HBM footprint: the head of the queue (fifo), or
+            # the waiting request with the least estimated work that fits (sjf)
             while waiting and free_slots:
-                i = waiting[0]
-                if i not in fps:
-                    fps[i] = Q.footprint(Q.params_from(requests[i]))
-                if fps[i] > self.budget:
-                    raise Q.QuapiError(Q.ERR_NOMEM, f"request {i} needs {fps[i]} bytes, more than the budget")
-                if used + fps[i] > self.budget:
-                    break
-                waiting.popleft()
+                for i in waiting:
+                    if i not in fps:
+                        fps[i] = Q.footprint(Q.params_from(requests[i]))
+                        if fps[i] > self.budget:
+                            raise Q.QuapiError(Q.ERR_NOMEM,
+                                               f"request {i} needs {fps[i]} bytes, more than the budget")
+                if self.policy == "fifo":
+                    i = waiting[0]
+                    if used + fps[i] > self.budget:
+                        break
+                else:
+                    fit = [j for j in waiting if used + fps[j] <= self.budget]
+                    if not fit:
+                        break
+                    i = min(fit, key=lambda j: (est_work_s(requests[j]), j))
+                waiting.remove(i)
                 slot = free_slots.pop()
                 a = self._admit(requests[i], i, slot, now())
                 used += a.fp
@@ -140,7 +180,10 @@ class Server:
                 while a.events and a.events[0].query():
                     a.events.popleft()
                 if a.enqueued < a.w.n_steps and len(a.events) < 2:
-                    end = min(a.enqueued + self.chunk, a.w.n_steps)
+                    chunk = self.chunk
+                    if self.chunk_ms is not None:
+                        chunk = int(min(256, max(2, self.chunk_ms * 1e-3 / est_step_s(a.w))))
+                    end = min(a.enqueued + chunk, a.w.n_steps)
                     # never end a chunk inside a fused step pair (L+1, L+2), ...:
                     # the run then has the same bits as one call of all steps
                     if end < a.w.n_steps and end > a.w.L and (end - a.w.L) % 2 == 1:

@@ -56,3 +56,15 @@ def test_request_larger_than_budget_is_refused():
     with pytest.raises(Q.QuapiError) as ei:
         Server(max_active=2, hbm_budget=1000).run(reqs, realtime=False)
     assert ei.value.status == Q.ERR_NOMEM
+
+
+def test_sjf_admits_the_shorter_request_first_with_unchanged_results():
+    from paper_1205_6872_amd.serve import Server, est_work_s
+    reqs = _small_trace(6)
+    order = sorted(range(len(reqs)), key=lambda i: est_work_s(reqs[i]))
+    res = Server(max_active=1, chunk_ms=2.0, policy="sjf").run(reqs, realtime=False)
+    admitted = [r.index for r in sorted(res, key=lambda r: r.admit_s)]
+    # one slot: after the first admission (all arrive at once), shortest first
+    assert admitted == order, (admitted, order)
+    for w, r in zip(reqs, res):
+        assert np.array_equal(r.rho, _alone(w))
