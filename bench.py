@@ -33,7 +33,14 @@ on the library's stream (`steps_per_launch` says how many steps a launch covers)
 `cpu_baseline` times the oracle (plain C, OpenMP) on a bounded sample of the
 same workload on the host.
 
+`paper_table1` re-runs the paper's Table 1 experiment (its Sec. III model system
+with the tabulated super-Ohmic J, memory length dk = 2..15, 989 main-phase
+steps, rho at every point) and reports the main-phase wall time per dk.
+`serving` / `serving_fifo` serve the first requests of the seeded trace with
+shortest-work-first and arrival-order admission.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tiers c128,c64,c64f64]
+                       [--serve-requests R] [--no-table1] [--no-copy-ceiling]
                        [--no-cpu-baseline] [--traffic-json FILE]
 """
 from __future__ import annotations
@@ -189,6 +196,7 @@ def main() -> int:
     ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64, help="0 skips the serving run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-table1", action="store_true", help="skip the paper's Table 1 sweep")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step2_kernel_traffic_spin_boson_l15.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -264,6 +272,11 @@ def main() -> int:
     if args.serve_requests > 0:
         out["serving"] = serve_trace(args.serve_requests)
         out["serving_fifo"] = serve_trace(args.serve_requests, policy="fifo", chunk_ms=None)
+    if not args.no_table1:
+        from paper_1205_6872_amd.stepbench import paper_table1
+        log("bench: the paper's Table 1 sweep (its model system, dk = 2..15, 989 main steps, rho at every point)")
+        out["paper_table1"] = {"workload": "paper_quantum_dot (Sec. III model, tabulated J), dt = 0.25 ps, complex128",
+                               "rows": paper_table1()}
     if not args.no_cpu_baseline:
         log("bench: cpu_baseline (oracle on the host)")
         cb = cpu_baseline(w.with_(dtype="c128"))

@@ -1,6 +1,7 @@
 """Per-shape step timing through the C ABI (library timing events on its stream).
 
     python3 -m paper_1205_6872_amd.stepbench [--cases M:L,...] [--dtypes c128,c64,c64f64] [--steps K]
+    python3 -m paper_1205_6872_amd.stepbench --paper-table1
 
 For each case (M levels, memory length L) and storage/arithmetic mode it runs
 the growth steps, then K full-window steps with rho at every step and K
@@ -60,12 +61,44 @@ def time_case(M: int, L: int, dtype: str, steps: int) -> dict:
             "norho_gbs": round(gbs_n, 1)}
 
 
+def paper_table1(dks=range(2, 16), main_steps: int = 989, dt: float = 0.25, dtype: str = "c128") -> list:
+    """The paper's Table 1 experiment on this GPU: its model system (Sec. III,
+    tabulated super-Ohmic J) at memory lengths dk, timing the main propagation
+    (the main_steps iterations after the first dk steps) with rho returned to
+    the host at every point.  The paper does not print dt; it is a parameter."""
+    import time
+    rows = []
+    for dk in dks:
+        w = W.paper_quantum_dot(L=dk, n_steps=dk + main_steps, dt=dt).with_(dtype=dtype)
+        t0 = time.perf_counter()
+        ctx = Q.create(Q.params_from(w))
+        t1 = time.perf_counter()
+        try:
+            ctx.propagate(dk)                                  # steps 1..dk (growth and the first full window)
+            t2 = time.perf_counter()
+            rho = ctx.propagate(main_steps)                    # 'allPoints' main phase, blocking
+            t3 = time.perf_counter()
+        finally:
+            ctx.destroy()
+        tr = np.abs(np.trace(rho, axis1=1, axis2=2) - 1).max()
+        rows.append({"dk": dk, "entries": 4 ** dk, "create_s": round(t1 - t0, 5), "first_s": round(t2 - t1, 5),
+                     "main_s": round(t3 - t2, 5), "main_ms_per_step": round((t3 - t2) * 1e3 / main_steps, 4),
+                     "trace_err": float(tr)})
+    return rows
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--cases", default="4:7,3:8,2:12")
     ap.add_argument("--dtypes", default="c128,c64,c64f64")
     ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--paper-table1", action="store_true",
+                    help="the paper's Table 1 sweep (its model system, dk = 2..15, 989 main steps)")
     args = ap.parse_args(argv)
+    if args.paper_table1:
+        for row in paper_table1():
+            print(json.dumps(row), flush=True)
+        return 0
     for c in args.cases.split(","):
         M, L = (int(v) for v in c.split(":"))
         for d in args.dtypes.split(","):
