@@ -113,19 +113,28 @@ def kernel_name(tier: str, steps_per_launch: float) -> str:
     return f"step_kernel<4, {st}, rho, full-window>"
 
 
-def measured_traffic(path: str, tier: str):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+FUSED_KERNEL_SOURCES = ("quapi_step2.hip", "quapi_device.h", "quapi_internal.h")
+
+
+def fused_kernel_source_hash() -> str:
+    """sha256 over the sources the fused step kernel is compiled from."""
     import hashlib
+    h = hashlib.sha256()
+    for name in FUSED_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1205_6872_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(path: str, tier: str):
+    """HBM bytes per fused-kernel launch from the committed rocprofv3 counter
+    summary, or None when the kernel's sources changed since it was taken."""
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             tj = json.load(f)
-        src = os.path.join(ROOT, "paper_1205_6872_amd", "csrc", "quapi_kernels.hip")
-        with open(src, "rb") as f:
-            cur = hashlib.sha256(f.read()).hexdigest()
-        if tj.get("kernel_source_sha256") != cur:
+        if tj.get("kernel_source_sha256") != fused_kernel_source_hash():
             return None
         return tj.get(tier, {}).get("hbm_bytes_per_launch")
     except (OSError, ValueError):

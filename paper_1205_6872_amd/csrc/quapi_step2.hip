@@ -1,0 +1,228 @@
+// Two full-window propagation steps per pass over the tensor (M = 2, N = 4):
+// the fused step kernel, its coefficient kernel and their launchers.
+//
+// Method: Dattani 2012, Sec. II (exact path-sum equation and discretized
+// influence functional); the tensor-propagator step of the Introduction,
+// applied twice with the intermediate tensor kept in registers.
+#include <hip/hip_runtime.h>
+
+#include "quapi_device.h"
+#include "quapi_internal.h"
+
+namespace quapi {
+namespace {
+
+// ------------------------------------------------- fused two-step (N = 4)
+struct Step2Lds {
+    unsigned tq, plo, phi, red, total;
+};
+__host__ __device__ inline Step2Lds step2_lds_layout(int csize, bool rho, int R, int Q) {
+    constexpr int N = 4;
+    const int ns = rho ? 4 : 2;
+    Step2Lds l;
+    unsigned off = 0;
+    l.tq = lds_take(off, ns * N * Q * csize);
+    l.plo = lds_take(off, ns * N * R * csize);
+    l.phi = lds_take(off, ns * N * 16);
+    l.red = lds_take(off, rho ? 2 * (kBlock / 64) * N * 16 : 0);
+    l.total = off;
+    return l;
+}
+
+// The fused-step coefficients (layout at kCoefOA ..), computed in FP64 and
+// rounded once to the compute precision.
+template <typename T>
+__global__ void step2_coef_kernel(const CoefArgs a) {
+    constexpr int N = 4, NN = 16;
+    using C = typename Cx<T>::type;
+    const int k = threadIdx.x;
+    if (k >= kCoefCount) return;
+    const double2 *old = a.bank + (size_t)a.old_tab * NN, *oldf = a.bank + (size_t)a.oldf_tab * NN;
+    const double2 *an = a.bank + (size_t)a.an_tab * NN, *anf = a.bank + (size_t)a.anf_tab * NN;
+    const double2 *d = a.bank + (size_t)a.d_tab * NN, *df = a.bank + (size_t)a.df_tab * NN;
+    const int o = k / kCoefPerO, part = k % kCoefPerO / NN, e = k % NN, hi = e / N, lo = e % N;
+    double2 v;
+    if (part * NN == kCoefOA) v = cmul(an[o * N + hi], old[o * N + lo]);             // i' = hi, i = lo
+    else if (part * NN == kCoefW) v = cmul(anf[o * N + hi], oldf[o * N + lo]);       // i' = hi, i = lo
+    else if (part * NN == kCoefDO) v = cmul(d[hi * N + o], old[hi * N + lo]);        // o' = hi, i' = lo
+    else v = cmul(df[hi * N + o], oldf[hi * N + lo]);                               // o' = hi, i' = lo
+    ((C *)a.out)[k] = conv<C>(v);
+}
+
+// Steps n and n+1 (both full-window, n > L) in one pass over the tensor.
+// Each item m (points n-L+2 .. n-1) reads the N^2 contiguous entries of the
+// oldest two points (i = point n-L, i' = point n-L+1) and writes the N^2
+// entries of the two new points (o = point n, o' = point n+1):
+//   y(o, i')   = A_n(o, i') Bn(o, m) sum_i Old(o, i) x(i, i')          (A_n entry)
+//   out(o, o') = D(o', o) Cn1(o', m) sum_i' Old(o', i') y(o, i')        (A_{n+1} entry)
+// A_n(o, i') is the step-n factor of point n-L+1 and D(o', o) the step-(n+1)
+// factor of point n (K folded in); Bn, Cn1 are the products over the digits of m.
+// With RHO, rho(t_n) comes from x with the final-point classes of step n, and
+// rho(t_{n+1}) from y with those of step n+1; both are reduced per block.
+// The coefficients that do not depend on m are read per use through scalar
+// loads; the m-dependent digit products come from LDS.
+template <typename S, typename T, bool RHO>
+__global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
+    constexpr int N = 4, NN = 16;
+    constexpr int NS = RHO ? 4 : 2;
+    using C = typename Cx<T>::type;
+    using CS = typename Cx<S>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int R = a.R, Q = a.Q;
+    const Step2Lds lay = step2_lds_layout((int)sizeof(C), RHO, R, Q);
+    C *s_tq = (C *)(smem + lay.tq);            // [NS][N][Q]
+    C *s_plo = (C *)(smem + lay.plo);          // [NS][N][R]
+    double2 *s_phi = (double2 *)(smem + lay.phi);
+    double2 *s_red = (double2 *)(smem + lay.red);
+    const T *coef = (const T *)a.coef;
+
+    const int t = threadIdx.x;
+    const int cR = kBlock / R, active = cR * R;
+    const long long blk = blockIdx.x;
+    if (t < NS * N) {
+        const int s = t / N, o = t % N;
+        s_phi[t] = a.t_hi[s][(size_t)o * a.grid + blk];
+    }
+    for (int idx = t; idx < NS * N * R; idx += kBlock) {
+        const int s = idx / (N * R), k = idx % (N * R);
+        s_plo[idx] = from_d2<C>(a.t_lo[s][k]);
+    }
+    __syncthreads();
+    for (int idx = t; idx < NS * N * Q; idx += kBlock) {
+        const int s = idx / (N * Q), k = idx % (N * Q), o = k / Q;
+        s_tq[idx] = from_d2<C>(cmul(s_phi[s * N + o], a.t_mid[s][k]));
+    }
+    __syncthreads();
+
+    double2 accn[RHO ? N : 1], accn1[RHO ? N : 1];
+#pragma unroll
+    for (int o = 0; o < (RHO ? N : 1); ++o) accn[o] = accn1[o] = make_double2(0.0, 0.0);
+    const int r = t % R;
+    if (t < active) {
+        const long long m0 = blk * (long long)R * Q;
+        const CS *__restrict__ ain = (const CS *)a.a_in;
+        CS *__restrict__ aout = (CS *)a.a_out;
+        const long long mc = a.m_count;
+        for (int qm = t / R; qm < Q; qm += cR) {
+            asm volatile("" ::: "memory");
+            const long long m = m0 + (long long)qm * R + r;
+            C x[NN];
+#pragma unroll
+            for (int k = 0; k < NN; ++k) x[k] = conv<C>(ain[(long long)NN * m + k]);
+            C cn1[N], totf[RHO ? N : 1];
+#pragma unroll
+            for (int op = 0; op < N; ++op) {
+                cn1[op] = cmul(s_plo[(1 * N + op) * R + r], s_tq[(1 * N + op) * Q + qm]);
+                if (RHO) totf[op] = C{};
+            }
+            // Per new point o of step n: the step-n entries y(o, i') (and the
+            // rho(t_n) term), then every step-(n+1) entry that reads them.
+#pragma unroll
+            for (int o = 0; o < N; ++o) {
+                asm volatile("" ::: "memory");  // coefficient reads of this o only
+                const T *co = coef + 2 * kCoefPerO * o;
+                const C bn = cmul(s_plo[(0 * N + o) * R + r], s_tq[(0 * N + o) * Q + qm]);
+                C y[N];
+#pragma unroll
+                for (int ip = 0; ip < N; ++ip) {
+                    C sum = {};
+#pragma unroll
+                    for (int i = 0; i < N; ++i) cmac(sum, coef_ld(co, kCoefOA + ip * N + i), x[i + N * ip]);
+                    y[ip] = cmul(bn, sum);
+                }
+                if (RHO) {
+                    C tot = {};
+#pragma unroll
+                    for (int k = 0; k < NN; ++k) cmac(tot, coef_ld(co, kCoefW + k), x[k]);
+                    const C bnf = cmul(s_plo[(2 * N + o) * R + r], s_tq[(2 * N + o) * Q + qm]);
+                    const double2 v = to_d2(cmul(bnf, tot));
+                    accn[o].x += v.x;
+                    accn[o].y += v.y;
+                }
+#pragma unroll
+                for (int op = 0; op < N; ++op) {
+                    asm volatile("" ::: "memory");
+                    C sum = {};
+#pragma unroll
+                    for (int ip = 0; ip < N; ++ip) cmac(sum, coef_ld(co, kCoefDO + op * N + ip), y[ip]);
+                    aout[m + mc * (o + N * op)] = conv<CS>(cmul(cn1[op], sum));
+                    if (RHO) {
+#pragma unroll
+                        for (int ip = 0; ip < N; ++ip) cmac(totf[op], coef_ld(co, kCoefV + op * N + ip), y[ip]);
+                    }
+                }
+            }
+            if (RHO) {
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int op = 0; op < N; ++op) {
+                    const C cf1 = cmul(s_plo[(3 * N + op) * R + r], s_tq[(3 * N + op) * Q + qm]);
+                    const double2 v = to_d2(cmul(cf1, totf[op]));
+                    accn1[op].x += v.x;
+                    accn1[op].y += v.y;
+                }
+            }
+        }
+    }
+    if (RHO) {
+        const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+        for (int o = 0; o < N; ++o) {
+            double2 v = accn[o], w = accn1[o];
+            for (int off = 32; off > 0; off >>= 1) {
+                v.x += __shfl_xor(v.x, off, 64);
+                v.y += __shfl_xor(v.y, off, 64);
+                w.x += __shfl_xor(w.x, off, 64);
+                w.y += __shfl_xor(w.y, off, 64);
+            }
+            if (lane == 0) {
+                s_red[wave * N + o] = v;
+                s_red[(kBlock / 64 + wave) * N + o] = w;
+            }
+        }
+        __syncthreads();
+        if (t < 2 * N) {
+            const int which = t / N, o = t % N;
+            double2 s = make_double2(0.0, 0.0);
+            for (int w = 0; w < kBlock / 64; ++w) {
+                s.x += s_red[(which * (kBlock / 64) + w) * N + o].x;
+                s.y += s_red[(which * (kBlock / 64) + w) * N + o].y;
+            }
+            a.partials[which][blk * N + o] = s;
+        }
+    }
+}
+
+template <typename S, typename T, bool RHO>
+hipError_t launch_step2_t(const Step2Args &a, hipStream_t st) {
+    using C = typename Cx<T>::type;
+    const Step2Lds lay = step2_lds_layout((int)sizeof(C), RHO, a.R, a.Q);
+    hipLaunchKernelGGL((step2_kernel<S, T, RHO>), dim3(a.grid), dim3(kBlock), lay.total, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t step2_lds_bytes(int prec, bool with_rho, int R, int Q) {
+    return step2_lds_layout(prec == kPrecC64 ? 8 : 16, with_rho, R, Q).total;
+}
+
+hipError_t launch_step2(int prec, bool with_rho, const Step2Args &a, hipStream_t st) {
+    switch (prec) {
+    case kPrecC128:
+        return with_rho ? launch_step2_t<double, double, true>(a, st) : launch_step2_t<double, double, false>(a, st);
+    case kPrecC64:
+        return with_rho ? launch_step2_t<float, float, true>(a, st) : launch_step2_t<float, float, false>(a, st);
+    case kPrecC64F64:
+        return with_rho ? launch_step2_t<float, double, true>(a, st) : launch_step2_t<float, double, false>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step2_coef(const CoefArgs &a, hipStream_t st) {
+    if (a.prec == kPrecC64) hipLaunchKernelGGL(step2_coef_kernel<float>, dim3(1), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL(step2_coef_kernel<double>, dim3(1), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace quapi
