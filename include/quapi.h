@@ -60,7 +60,10 @@ typedef enum {
  * rounded once to the arithmetic type. */
 typedef enum {
     QUAPI_C128 = 0,          /* stored in complex128, FP64 products */
-    QUAPI_C64 = 1,           /* stored in complex64, FP32 products with FP32 accumulation */
+    QUAPI_C64 = 1,           /* stored in complex64, FP32 products with FP32 accumulation; the
+                                K entries of the diagonal rows (a, a) are rounded to FP32 values
+                                whose column sums are exactly delta_cd, so the rounding of K
+                                does not change the trace of rho from step to step */
     QUAPI_C64_F64 = 2        /* stored in complex64; each loaded value is widened and every
                                 product and sum is FP64, rounded to complex64 on store */
 } quapi_dtype;
