@@ -160,6 +160,14 @@ def paper_pmc_bytes(M: int, dk_max: int) -> int:
     return int(lib().quapi_paper_pmc_bytes(int(M), int(dk_max)))
 
 
+def _sel_array(sel) -> tuple:
+    """int32 copy of a selection and its length; an empty selection still gets
+    a valid (one-element) buffer, so the library never sees NULL ('all steps')."""
+    arr = np.ascontiguousarray(np.asarray(sel, dtype=np.int32).reshape(-1))
+    n = len(arr)
+    return (arr if n else np.zeros(1, dtype=np.int32)), n
+
+
 class Context:
     """A quapi_ctx.  Use ``create`` to make one."""
 
@@ -185,8 +193,8 @@ class Context:
         if sel is None:
             n_out, sel_arr, psel, n_sel = n_steps, None, None, 0
         else:
-            sel_arr = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
-            n_out = n_sel = len(sel_arr)
+            sel_arr, n_sel = _sel_array(sel)
+            n_out = n_sel
             psel = sel_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
         out = np.zeros(2 * self.N * max(n_out, 1), dtype=np.float64)
         _check(lib().quapi_propagate(h, int(n_steps), psel, n_sel, _ptr(out)), h)
@@ -198,8 +206,7 @@ class Context:
         if sel is None:
             psel, n_sel = None, 0
         else:
-            sel_arr = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
-            n_sel = len(sel_arr)
+            sel_arr, n_sel = _sel_array(sel)
             psel = sel_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
         _check(lib().quapi_propagate_async(h, int(n_steps), psel, n_sel, ctypes.c_void_p(rho_out_dev)), h)
 
