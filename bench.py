@@ -41,7 +41,7 @@ shortest-work-first and arrival-order admission.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tiers c128,c64,c64f64]
                        [--serve-requests R] [--no-table1] [--no-copy-ceiling]
-                       [--no-cpu-baseline] [--traffic-json FILE]
+                       [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -108,33 +108,41 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
 
 def kernel_name(tier: str, steps_per_launch: float) -> str:
     st = {"c128": "double, double", "c64": "float, float", "c64f64": "float, double"}[tier]
+    if steps_per_launch > 2.5:
+        return f"step3_kernel<{st}, rho> (three steps fused per launch)"
     if steps_per_launch > 1.5:
         return f"step2_kernel<{st}, rho> (two steps fused per launch)"
     return f"step_kernel<4, {st}, rho, full-window>"
 
 
-FUSED_KERNEL_SOURCES = ("quapi_step2.hip", "quapi_device.h", "quapi_internal.h")
+# The dominant kernel of each tier at M = 2, L = 15 and the sources it is built from.
+TIER_KERNEL = {"c128": "step3", "c64": "step2", "c64f64": "step2"}
+KERNEL_SOURCES = {"step2": ("quapi_step2.hip", "quapi_device.h", "quapi_internal.h"),
+                  "step3": ("quapi_step3.hip", "quapi_device.h", "quapi_internal.h")}
 
 
-def fused_kernel_source_hash() -> str:
-    """sha256 over the sources the fused step kernel is compiled from."""
+def kernel_source_hash(kernel: str) -> str:
+    """sha256 over the sources the fused kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
-    for name in FUSED_KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1205_6872_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(path: str, tier: str):
-    """HBM bytes per fused-kernel launch from the committed rocprofv3 counter
-    summary, or None when the kernel's sources changed since it was taken."""
+def measured_traffic(tier: str):
+    """HBM bytes per launch of the tier's dominant kernel from the committed
+    rocprofv3 counter summary, or None when the kernel's sources changed since
+    the counters were taken."""
+    kernel = TIER_KERNEL[tier]
+    path = os.path.join(ROOT, "profiles", f"{kernel}_kernel_traffic_spin_boson_l15.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             tj = json.load(f)
-        if tj.get("kernel_source_sha256") != fused_kernel_source_hash():
+        if tj.get("kernel_source_sha256") != kernel_source_hash(kernel):
             return None
         return tj.get(tier, {}).get("hbm_bytes_per_launch")
     except (OSError, ValueError):
@@ -206,7 +214,6 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=64, help="0 skips the serving run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-table1", action="store_true", help="skip the paper's Table 1 sweep")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "step2_kernel_traffic_spin_boson_l15.json"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
@@ -233,7 +240,7 @@ def main() -> int:
             f"{r['kernel_ms']:.3f} ms = {r['achieved_gbs']:.0f} GB/s")
     main_t = "c128" if "c128" in res else tiers[0]
     r = res[main_t]
-    traffic = measured_traffic(args.traffic_json, main_t)
+    traffic = measured_traffic(main_t)
     out = {
         "metric": "QUAPI step Gelem/s + HBM GB/s (FP64 vs FP32) at M=2 dk=15",
         "value": round(r["gelem_s"], 3),
@@ -270,7 +277,7 @@ def main() -> int:
             "value": round(a["gelem_s"], 3), "unit": "Gelem/s", "ms_per_step": round(a["ms_per_step"], 4),
             "roofline": {"bound": "hbm", "achieved": round(a["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(a["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic(args.traffic_json, t),
+                         "traffic": measured_traffic(t),
                          "kernel": kernel_name(t, a["steps_per_launch"]),
                          "kernel_ms": round(a["kernel_ms"], 4), "bytes_per_launch": a["bytes_per_launch"],
                          "steps_per_launch": round(a["steps_per_launch"], 3)},

@@ -135,10 +135,12 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
  *   rho_out  host buffer of n_out * M*M complex (n_out = n_sel, or n_steps when
  *            sel is NULL), written in selection order; caller-owned.
  * Blocking: returns when the results are on the host.
- * Results are deterministic.  For M = 2 (L >= 2) full-window steps run as fused
- * pairs (L+1, L+2), (L+3, L+4), ...; a sequence of calls gives bit-identical
- * results to one call when every call ends at step c <= L or with c - L even
- * (otherwise the split step runs unfused and rounds differently, within 1e-15). */
+ * Results are deterministic.  For M = 2 full-window steps run in fused groups of
+ * F = quapi_fused_steps() steps fixed by the global step number: (L+1 .. L+F),
+ * (L+F+1 .. L+2F), ... (by default F = 3 at complex128 from L = 14, F = 2
+ * otherwise with L >= 2); a sequence of calls gives bit-identical results to one call when
+ * every call ends at step c <= L or with c - L a multiple of F (otherwise the
+ * steps of a split group run one by one and round differently, within 1e-15). */
 quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
                              double *rho_out);
 
@@ -172,12 +174,26 @@ quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count,
 /* Number of entries in the current tensor (N^min(c+1, L)). */
 quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries);
 
+/* Full-window steps that one launch advances for this context (3, 2 or 1),
+ * the group size of the determinism rule of quapi_propagate.
+ * Errors: QUAPI_ERR_INVALID for NULL arguments. */
+quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps);
+
+/* Choose the full-window steps per launch: 1, 2 (N = 4, L >= 2), 3 (N = 4,
+ * L >= 3), or 0 for the default (3 at complex128 from L = 14, else 2 where
+ * available, else 1).  Every choice gives the same results to within rounding
+ * (the fused kernels apply the same factors in another order); use it to pin
+ * the kernel, e.g. in tests.  It takes effect from the next call.
+ * Errors: QUAPI_ERR_INVALID for an unavailable width; QUAPI_ERR_STATE while
+ * another call runs on the context. */
+quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps);
+
 /* Kernel timing with HIP events on the context's stream. */
 typedef struct {
     double setup_ms;          /* device time of the setup kernels in quapi_create */
     double step_ms;           /* summed duration of full-window step kernels (n >= L) */
     long long step_launches;  /* number of those launches */
-    long long step_steps;     /* full-window steps they covered (a fused launch covers two) */
+    long long step_steps;     /* full-window steps they covered (a fused launch covers two or three) */
     double grow_ms;           /* summed duration of growth-step kernels (n < L) */
     long long grow_launches;
     double finalize_ms;       /* summed duration of the kernels that sum rho over blocks */

@@ -10,7 +10,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB_DIR = PKG / "_lib"
 LIB = LIB_DIR / "libquapi.so"
-SOURCES = [CSRC / "quapi_kernels.hip", CSRC / "quapi_step2.hip", CSRC / "quapi_host.hip"]
+SOURCES = [CSRC / "quapi_kernels.hip", CSRC / "quapi_step2.hip", CSRC / "quapi_step3.hip", CSRC / "quapi_host.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -95,10 +95,25 @@ DigitSplit split_digits2(int n_digits) {
 // registers) and L >= 2 (two points to sum out).
 bool fused_ok(int N, int L) { return N == 4 && L >= 2; }
 
+// The three-step kernel runs for N = 4, L >= 3 (three points to sum out).
+bool triple_ok(int N, int L) { return N == 4 && L >= 3; }
+
+// Full-window steps per launch chosen by default: three at complex128 from
+// L = 14 (4^11 items and more; the step is HBM bound there, and a third step
+// in registers saves a third of the traffic), two otherwise.  A three-step
+// item runs one wave per SIMD through three dependent stages, so with fewer
+// items than that the two-step kernel finishes first; at complex64 storage the
+// two-step kernel is already bound by its arithmetic.
+int fusion_width(int N, int L, int prec) {
+    if (triple_ok(N, L) && L >= 14 && prec == kPrecC128) return 3;
+    return fused_ok(N, L) ? 2 : 1;
+}
+
 int max_grid(int N, int L) {
     int g = 1;
     for (int nd = 0; nd <= L - 1; ++nd) g = std::max(g, split_digits(N, nd).grid);
     if (fused_ok(N, L)) g = std::max(g, split_digits2(L - 2).grid);
+    if (N == 4 && L >= 3) g = std::max(g, split_digits2(L - 3).grid);
     return g;
 }
 
@@ -235,11 +250,12 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
-    size_t off_plan, off_plan2, off_coef, off_pairs, off_sink;
+    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_pairs, off_sink;
     size_t total;
     int n_panels, n_tables, partial_blocks;
     DigitSplit main_split;   // digit split of the full-window steps
     DigitSplit split2;       // digit split of the fused two-step kernel
+    DigitSplit split3;       // digit split of the three-step kernel
 };
 
 constexpr int kSlots = 4;    // rho partial buffers: a fused launch takes two
@@ -255,6 +271,8 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.partial_blocks = max_grid(N, L);
     l.main_split = split_digits(N, L - 1);
     l.split2 = fused_ok(N, L) ? split_digits2(L - 2) : DigitSplit{0, 0, 1, 1, 1};
+    const bool triple = triple_ok(N, L);
+    l.split3 = triple ? split_digits2(L - 3) : DigitSplit{0, 0, 1, 1, 1};
     l.a_bytes = entries * cs;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -291,6 +309,10 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     const DigitSplit &s2 = l.split2;
     l.off_plan2 = take(fused_ok(N, L) ? (size_t)4 * N * (s2.R + s2.Q + s2.grid) * 16 : 0);
     l.off_coef = take(fused_ok(N, L) ? (size_t)kCoefCount * 16 : 0);
+    // six table sets (interior / final, steps n, n+1, n+2) of the three-step split
+    const DigitSplit &s3 = l.split3;
+    l.off_plan3 = take(triple ? (size_t)6 * N * (s3.R + s3.Q + s3.grid) * 16 : 0);
+    l.off_coef3 = take(triple ? (size_t)kC3Count * 16 : 0);
     l.total = off;
     return l;
 }
@@ -332,10 +354,14 @@ struct quapi_ctx {
     RhoSink *sink = nullptr;
     // captured full-window steps, [without / with rho]: graph1 two single steps
     // A[0] -> A[1] -> A[0]; graph2[.][p] one fused launch A[p] -> A[1-p]
-    hipGraphExec_t graph1[2] = {}, graph2[2][2] = {};
+    hipGraphExec_t graph1[2] = {}, graph2[2][2] = {}, graph3[2][2] = {};
     bool graph_failed = false;
     bool plan_ready = false;      // full-window factor tables computed
     bool plan2_ready = false;     // fused-step factor tables computed
+    bool plan3_ready = false;     // three-step factor tables computed
+    int fuse = 1;                 // full-window steps per launch (fusion_width)
+    double2 *plan3 = nullptr;
+    void *coef3 = nullptr;
     std::vector<double> rho0_h;
     // host copies of uploaded inputs (kept alive until the uploads complete)
     std::vector<double> s_h, H_h, pa_h, ph_h, tw_h, tJ_h, glx_h, glw_h;
@@ -700,20 +726,150 @@ quapi_status enqueue_step2(quapi_ctx *c, int n, bool sel_n, bool sel_n1) {
     return QUAPI_OK;
 }
 
+// Arguments of a launch of steps n, n+1, n+2 (n > L); the six factor-table
+// sets and the coefficients are computed on first use.
+quapi_status prepare_step3(quapi_ctx *c, bool rho, Step3Args *out) {
+    const int N = c->N, L = c->L;
+    const BankLayout B{L};
+    const DigitSplit &sp = c->lay.split3;
+    const int nd = L - 3;
+    Step3Args a{};
+    a.m_count = ipow_ll(N, nd);
+    a.R = sp.R;
+    a.Q = sp.Q;
+    a.grid = sp.grid;
+    const size_t cap = c->lay.a_bytes / c->csize;
+    const size_t lds = step3_lds_bytes(c->prec, rho, a.R, a.Q);
+    if ((long long)a.grid * a.R * a.Q != a.m_count || (size_t)a.m_count * N * N * N > cap ||
+        a.grid > c->lay.partial_blocks || lds > (size_t)kLdsLimit || a.R > kBlock)
+        return fail(c, QUAPI_ERR_DEVICE, "internal three-step launch check failed");
+    const size_t per = (size_t)N * (sp.R + sp.Q + sp.grid);
+    for (int k = 0; k < 6; ++k) {
+        double2 *base = c->plan3 + per * k;
+        a.t_lo[k] = base;
+        a.t_mid[k] = base + (size_t)N * sp.R;
+        a.t_hi[k] = base + (size_t)N * (sp.R + sp.Q);
+    }
+    if (!c->plan3_ready) {
+        // digit j of m is point n-L+3+j: lag L-3-j+s from step n+s
+        for (int step = 0; step < 3; ++step) {
+            PlanArgs pa{};
+            pa.bank = c->bank;
+            pa.N = N;
+            pa.d_lo = sp.d_lo;
+            pa.d_mid = sp.d_mid;
+            pa.n_digits = nd;
+            pa.R = sp.R;
+            pa.Q = sp.Q;
+            pa.grid = sp.grid;
+            for (int j = 0; j < nd; ++j) {
+                const int lag = L - 3 - j + step;
+                pa.tab[j] = (int16_t)(lag == 1 ? B.k_lag1() : B.lag(lag));
+                pa.tabf[j] = (int16_t)(lag == 1 ? B.k_fin1() : B.fin(lag));
+            }
+            pa.t_lo = (double2 *)a.t_lo[step];
+            pa.t_lof = (double2 *)a.t_lo[step + 3];
+            pa.t_mid = (double2 *)a.t_mid[step];
+            pa.t_midf = (double2 *)a.t_mid[step + 3];
+            pa.t_hi = (double2 *)a.t_hi[step];
+            pa.t_hif = (double2 *)a.t_hi[step + 3];
+            hipError_t e = launch_plan_tables(pa, c->stream);
+            if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "plan kernel launch: %s", hipGetErrorString(e));
+        }
+        Coef3Args ca{};
+        ca.bank = c->bank;
+        ca.old_tab = B.old_main();
+        ca.oldf_tab = B.oldf_main();
+        ca.an_tab = B.lag(L - 1);                               // point n-L+1 seen from n
+        ca.anf_tab = B.fin(L - 1);
+        ca.f_tab = L - 2 == 1 ? B.k_lag1() : B.lag(L - 2);      // point n-L+2 seen from n
+        ca.ff_tab = L - 2 == 1 ? B.k_fin1() : B.fin(L - 2);
+        ca.g_tab = B.k_lag1();                                  // point n seen from n+1
+        ca.gf_tab = B.k_fin1();
+        ca.h_tab = B.lag(L - 1);                                // point n-L+2 seen from n+1
+        ca.hf_tab = B.fin(L - 1);
+        ca.p_tab = B.k_lag1();                                  // point n+1 seen from n+2
+        ca.pf_tab = B.k_fin1();
+        ca.q_tab = B.lag(2);                                    // point n seen from n+2
+        ca.qf_tab = B.fin(2);
+        ca.prec = c->prec;
+        ca.out = c->coef3;
+        hipError_t e = launch_step3_coef(ca, c->stream);
+        if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "coefficient kernel launch: %s", hipGetErrorString(e));
+        c->plan3_ready = true;
+    }
+    a.coef = c->coef3;
+    *out = a;
+    return QUAPI_OK;
+}
+
+// Enqueue the steps n, n+1, n+2 (n > L) as one launch; rho of the selected
+// ones goes to the sink in step order.
+quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
+    const bool rho = selk[0] || selk[1] || selk[2];
+    Step3Args a;
+    quapi_status st = prepare_step3(c, rho, &a);
+    if (st != QUAPI_OK) return st;
+    a.a_in = c->A[c->cur];
+    a.a_out = c->A[1 - c->cur];
+    int slots[3] = {-1, -1, -1};
+    if (rho) {
+        for (int k = 0; k < 3; ++k) {
+            slots[k] = take_slot(c);
+            st = wait_slot(c, slots[k]);
+            if (st != QUAPI_OK) return st;
+            a.partials[k] = c->partials[slots[k]];
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        e0 = take_event(c);
+        e1 = take_event(c);
+        if (e0) (void)hipEventRecord(e0, c->stream);
+    }
+    hipError_t e = launch_step3(c->prec, rho, a, c->stream);
+    if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "three-step launch: %s", hipGetErrorString(e));
+    if (c->timing && e0 && e1) {
+        (void)hipEventRecord(e1, c->stream);
+        c->recs.push_back({0, e0, e1, 3});
+    }
+    if (rho) {
+        int fin[3], nf = 0;
+        for (int k = 0; k < 3; ++k)
+            if (selk[k]) fin[nf++] = slots[k];
+        st = finalize_side(c, fin, nf, a.grid);
+        if (st != QUAPI_OK) return st;
+    }
+    c->cur = 1 - c->cur;
+    c->step = n + 2;
+    return QUAPI_OK;
+}
+
 // Capture full-window steps into an executable graph whose node arguments
 // never change (the step tables are the same for all n > L, and rho goes
 // through the sink); finalizes run on the same stream.
-//   fused == false: two single steps A[0] -> A[1] -> A[0]
-//   fused == true:  one fused launch A[par] -> A[1 - par]
-quapi_status build_graph(quapi_ctx *c, bool rho, bool fused, int par, hipGraphExec_t *out) {
+//   width 1: two single steps A[0] -> A[1] -> A[0]
+//   width 2: one two-step launch A[par] -> A[1 - par]
+//   width 3: one three-step launch A[par] -> A[1 - par]
+quapi_status build_graph(quapi_ctx *c, bool rho, int width, int par, hipGraphExec_t *out) {
     StepPlan sp{};
     Step2Args a2{};
-    quapi_status st = fused ? prepare_step2(c, rho, &a2) : prepare_step(c, c->L + 1, rho, &sp);
+    Step3Args a3{};
+    quapi_status st = width == 3 ? prepare_step3(c, rho, &a3)
+                      : width == 2 ? prepare_step2(c, rho, &a2)
+                                   : prepare_step(c, c->L + 1, rho, &sp);
     if (st != QUAPI_OK) return st;
     hipGraph_t g = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    if (fused) {
+    if (width == 3) {
+        a3.a_in = c->A[par];
+        a3.a_out = c->A[1 - par];
+        for (int k = 0; k < 3; ++k) a3.partials[k] = c->partials[k];
+        e = launch_step3(c->prec, rho, a3, c->stream);
+        for (int k = 0; k < 3 && rho && e == hipSuccess; ++k)
+            e = launch_rho_finalize(c->N, c->partials[k], a3.grid, c->pairs, c->sink, c->stream);
+    } else if (width == 2) {
         a2.a_in = c->A[par];
         a2.a_out = c->A[1 - par];
         a2.partials[0] = c->partials[0];
@@ -809,15 +965,52 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
     // finalized rho values land at sink->base + k*N in step order
     HIP_TRY(c, launch_set_sink(c->sink, dev_out ? dev_out + (size_t)written * N : c->stage, c->stream));
     const size_t entries = (size_t)ipow_ll(N, L);
-    const bool fused = fused_ok(N, L);
+    const bool fused = c->fuse == 2;
     const bool graphs = !c->timing && !c->graph_failed && entries <= kGraphMaxEntries;
     const int first = c->step + 1, last = c->step + n_steps;
     for (int n = first; n <= last; ++n) {
         const bool s0 = is_sel(n, si);
+        // Three full-window steps n, n+1, n+2 at groups fixed by the global
+        // step number -- (L+1, L+2, L+3), (L+4, ..), ... -- as for pairs below.
+        if (c->fuse == 3 && n > L && n + 2 <= last && (n - L - 1) % 3 == 0) {
+            bool selk[3];
+            int nsel = 0;
+            for (int k = 0; k < 3; ++k) {
+                selk[k] = is_sel(n + k, si + nsel);
+                nsel += selk[k] ? 1 : 0;
+            }
+            if (!dev_out && staged + nsel > kRhoStage) {
+                st = flush();
+                if (st != QUAPI_OK) return st;
+            }
+            bool done = false;
+            if (graphs && selk[0] == selk[1] && selk[1] == selk[2]) {
+                hipGraphExec_t &gx = c->graph3[s0 ? 1 : 0][c->cur];
+                if (!gx && build_graph(c, s0, 3, c->cur, &gx) != QUAPI_OK) {
+                    c->graph_failed = true;   // stay on direct launches
+                } else {
+                    st = join_side(c);        // the graph reuses partial buffers 0, 1 and 2
+                    if (st != QUAPI_OK) return st;
+                    HIP_TRY(c, hipGraphLaunch(gx, c->stream));
+                    c->cur = 1 - c->cur;
+                    c->step = n + 2;
+                    done = true;
+                }
+            }
+            if (!done) {
+                st = enqueue_step3(c, n, selk);
+                if (st != QUAPI_OK) return st;
+            }
+            si += sel ? nsel : 0;
+            written += nsel;
+            if (!dev_out) staged += nsel;
+            n += 2;
+            continue;
+        }
         // Two full-window steps n, n+1.  Pairs are fixed by the global step
         // number -- (L+1, L+2), (L+3, L+4), ... -- so a run gives the same bits
         // however it is split into calls, as long as no call ends inside a pair.
-        if (n > L && n < last && (n - L - 1) % 2 == 0) {
+        if (c->fuse != 3 && n > L && n < last && (n - L - 1) % 2 == 0) {
             const bool s1 = is_sel(n + 1, si + (s0 ? 1 : 0));
             const int nsel = (s0 ? 1 : 0) + (s1 ? 1 : 0);
             if (!dev_out && staged + nsel > kRhoStage) {
@@ -827,7 +1020,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
             bool done = false;
             if (graphs && s0 == s1 && (fused || c->cur == 0)) {
                 hipGraphExec_t &gx = fused ? c->graph2[s0 ? 1 : 0][c->cur] : c->graph1[s0 ? 1 : 0];
-                if (!gx && build_graph(c, s0, fused, c->cur, &gx) != QUAPI_OK) {
+                if (!gx && build_graph(c, s0, fused ? 2 : 1, c->cur, &gx) != QUAPI_OK) {
                     c->graph_failed = true;   // stay on direct launches
                 } else {
                     st = join_side(c);        // the graph reuses partial buffers 0 and 1
@@ -885,6 +1078,9 @@ void release(quapi_ctx *c) {
     for (auto &g : c->graph1)
         if (g) (void)hipGraphExecDestroy(g);
     for (auto &row : c->graph2)
+        for (auto &g : row)
+            if (g) (void)hipGraphExecDestroy(g);
+    for (auto &row : c->graph3)
         for (auto &g : row)
             if (g) (void)hipGraphExecDestroy(g);
     for (auto &r : c->recs) {
@@ -1004,6 +1200,9 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     for (int k = 0; k < kSlots; ++k)
         c->partials[k] = (double2 *)(w + lay.off_partials) + (size_t)k * lay.partial_blocks * N;
     c->plan2 = (double2 *)(w + lay.off_plan2);
+    c->plan3 = (double2 *)(w + lay.off_plan3);
+    c->coef3 = w + lay.off_coef3;
+    c->fuse = fusion_width(N, p->dk_max, c->prec);
     c->coef = w + lay.off_coef;
     c->stage = (double2 *)(w + lay.off_stage);
     c->pairs = (double2 *)(w + lay.off_pairs);
@@ -1119,6 +1318,25 @@ quapi_status quapi_propagate_async(quapi_ctx *ctx, int n_steps, const int *sel, 
 quapi_status quapi_step_count(const quapi_ctx *ctx, int *step) {
     if (!ctx || !step) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
     *step = ctx->step;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps) {
+    if (!ctx || !steps) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    *steps = ctx->fuse;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
+    if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
+    const int N = ctx->N, L = ctx->L;
+    if (steps == 0) steps = fusion_width(N, L, ctx->prec);
+    const bool ok = steps == 1 || (steps == 2 && fused_ok(N, L)) || (steps == 3 && triple_ok(N, L));
+    if (!ok)
+        return fail(ctx, QUAPI_ERR_INVALID, "%d fused steps unavailable at N = %d, L = %d (1 always; 2: N = 4, L >= 2; "
+                    "3: N = 4, L >= 3)", steps, N, L);
+    if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
+    ctx->fuse = steps;
     return QUAPI_OK;
 }
 

@@ -97,6 +97,39 @@ struct CoefArgs {
     void *out;
 };
 
+// Three consecutive full-window steps n, n+1, n+2 (n > L, N = 4, L >= 3) in
+// one pass: A_out[m + m_count*(o + N*o' + N^2*o'')] from the N^3 contiguous
+// inputs A_in[i + N*i' + N^2*i'' + N^3*m], m the digits of points
+// n-L+3 .. n-1 (m_count = N^(L-3)); the step-n and step-(n+1) tensors stay in
+// registers.
+struct Step3Args {
+    const void *a_in;
+    void *a_out;
+    // factor products over the digits of m, per table set: 0, 1, 2 interior
+    // steps n, n+1, n+2; 3, 4, 5 final point of those steps ([N][R], [N][Q], [N][grid])
+    const double2 *t_lo[6], *t_mid[6], *t_hi[6];
+    double2 *partials[3];       // block partials of rho(t_n), rho(t_{n+1}), rho(t_{n+2})
+    long long m_count;
+    int R, Q, grid;
+    const void *coef;           // kC3Count complex entries in the compute precision
+};
+
+// Coefficients of the three-step kernel (compute precision):
+//   old[o][i], oldf[o][i]       oldest point seen from the new point (every step)
+//   AF[o][i''][i']  an(o, i') F(o, i'')     step n: points n-L+1 (lag L-1), n-L+2 (lag L-2)
+//   GH[o'][i''][o]  G(o', o) H(o', i'')     step n+1: point n (lag 1, K), n-L+2 (lag L-1)
+//   PQ[o''][o'][o]  P(o'', o') Q(o'', o)    step n+2: point n+1 (lag 1, K), n (lag 2)
+// and the final-point versions (suffix f) for rho.
+constexpr int kC3Old = 0, kC3Oldf = 16, kC3AF = 32, kC3AFf = 96, kC3GH = 160, kC3GHf = 224, kC3PQ = 288,
+              kC3PQf = 352, kC3Count = 416;
+struct Coef3Args {
+    const double2 *bank;
+    int old_tab, oldf_tab, an_tab, anf_tab, f_tab, ff_tab, g_tab, gf_tab, h_tab, hf_tab, p_tab, pf_tab,
+        q_tab, qf_tab;
+    int prec;
+    void *out;
+};
+
 // Factor products of the full-window digit split (see StepArgs::t_lo ...).
 struct PlanArgs {
     const double2 *bank;
@@ -154,6 +187,9 @@ hipError_t launch_plan_tables(const PlanArgs &a, hipStream_t st);
 size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q);
 hipError_t launch_step2(int prec, bool with_rho, const Step2Args &a, hipStream_t st);
 hipError_t launch_step2_coef(const CoefArgs &a, hipStream_t st);
+hipError_t launch_step3(int prec, bool with_rho, const Step3Args &a, hipStream_t st);
+hipError_t launch_step3_coef(const Coef3Args &a, hipStream_t st);
+size_t step3_lds_bytes(int prec, bool with_rho, int R, int Q);
 size_t step2_lds_bytes(int prec, bool with_rho, int R, int Q);
 
 }  // namespace quapi

@@ -1,0 +1,348 @@
+// Three full-window propagation steps per pass over the tensor (M = 2, N = 4):
+// the three-step kernel, its coefficient kernel and their launchers.
+//
+// Method: Dattani 2012, Sec. II (exact path-sum equation and discretized
+// influence functional); the tensor-propagator step of the Introduction,
+// applied three times with the two intermediate tensors kept in registers.
+// Each pass reads and writes the tensor once, so a step moves a third of the
+// bytes of a single step.
+#include <hip/hip_runtime.h>
+
+#include "quapi_device.h"
+#include "quapi_internal.h"
+
+namespace quapi {
+namespace {
+
+struct Step3Lds {
+    unsigned tq, plo, phi, red, total;
+};
+__host__ __device__ inline Step3Lds step3_lds_layout(int csize, bool rho, int R, int Q) {
+    constexpr int N = 4;
+    const int ns = rho ? 6 : 3;
+    Step3Lds l;
+    unsigned off = 0;
+    l.tq = lds_take(off, ns * N * Q * csize);
+    l.plo = lds_take(off, ns * N * R * csize);
+    l.phi = lds_take(off, ns * N * 16);
+    l.red = lds_take(off, rho ? 3 * (kBlock / 64) * N * 16 : 0);
+    l.total = off;
+    return l;
+}
+
+// The coefficient pointer passed through an opaque register move: loads
+// through it are issued again after each call instead of being kept live in
+// scalar registers across the whole item (the constant address space lets the
+// compiler reuse them otherwise, and there are too many to keep).
+template <typename T>
+__device__ __forceinline__ const T *fresh(const T *p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// The coefficients (layout at kC3Old ..), computed in FP64 and rounded once to
+// the compute precision.
+template <typename T>
+__global__ void step3_coef_kernel(const Coef3Args a) {
+    constexpr int N = 4, NN = 16;
+    using C = typename Cx<T>::type;
+    const int k = threadIdx.x;
+    if (k >= kC3Count) return;
+    auto tab = [&](int t, int row, int col) { return a.bank[(size_t)t * NN + row * N + col]; };
+    double2 v;
+    if (k < kC3Oldf) {
+        v = tab(a.old_tab, k / N, k % N);
+    } else if (k < kC3AF) {
+        v = tab(a.oldf_tab, (k - kC3Oldf) / N, (k - kC3Oldf) % N);
+    } else {
+        const bool fin = ((k - kC3AF) / 64) % 2 == 1;
+        const int part = (k - kC3AF) / 128, e = (k - kC3AF) % 64;
+        const int x = e / NN, y = (e / N) % N, z = e % N;    // [x][y][z]
+        if (part == 0) {        // AF[o][i''][i'] = an(o, i') F(o, i'')
+            v = cmul(tab(fin ? a.anf_tab : a.an_tab, x, z), tab(fin ? a.ff_tab : a.f_tab, x, y));
+        } else if (part == 1) { // GH[o'][i''][o] = G(o', o) H(o', i'')
+            v = cmul(tab(fin ? a.gf_tab : a.g_tab, x, z), tab(fin ? a.hf_tab : a.h_tab, x, y));
+        } else {                // PQ[o''][o'][o] = P(o'', o') Q(o'', o)
+            v = cmul(tab(fin ? a.pf_tab : a.p_tab, x, y), tab(fin ? a.qf_tab : a.q_tab, x, z));
+        }
+    }
+    ((C *)a.out)[k] = conv<C>(v);
+}
+
+// Steps n, n+1, n+2 (all full-window, n > L) in one pass.  Each item m (points
+// n-L+3 .. n-1) reads the N^3 contiguous entries of the oldest three points
+// (i = n-L, i' = n-L+1, i'' = n-L+2) into w[i + N i' + N^2 i''] and writes the
+// N^3 entries of the three new points (o = n, o' = n+1, o'' = n+2):
+//   y(o, i', i'')  = B(o, m) AF(o, i'', i') sum_i old(o, i) x(i, i', i'')        (step n)
+//   z(o, o', i'')  = C(o', m) GH(o', i'', o) sum_i' old(o', i') y(o, i', i'')    (step n+1)
+//   out(o, o', o'') = D(o'', m) PQ(o'', o', o) sum_i'' old(o'', i'') z(o, o', i'') (step n+2)
+// B, C, D are the products over the digits of m.  Each stage overwrites the
+// four slots it reads, so w holds x, then y (slot o + N i' + N^2 i''), then z
+// (slot o + N o' + N^2 i'').  With RHO, rho at each of the three steps comes
+// from the values that stage reads, with the final-point classes.
+template <typename S, typename T, bool RHO>
+__global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
+    constexpr int N = 4, NNN = 64;
+    constexpr int NS = RHO ? 6 : 3;
+    using C = typename Cx<T>::type;
+    using CS = typename Cx<S>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int R = a.R, Q = a.Q;
+    const Step3Lds lay = step3_lds_layout((int)sizeof(C), RHO, R, Q);
+    C *s_tq = (C *)(smem + lay.tq);            // [NS][N][Q]
+    C *s_plo = (C *)(smem + lay.plo);          // [NS][N][R]
+    double2 *s_phi = (double2 *)(smem + lay.phi);
+    double2 *s_red = (double2 *)(smem + lay.red);
+    const T *coef = (const T *)a.coef;
+
+    const int t = threadIdx.x;
+    const int cR = kBlock / R, active = cR * R;
+    const long long blk = blockIdx.x;
+    if (t < NS * N) {
+        const int s = t / N, o = t % N;
+        s_phi[t] = a.t_hi[s][(size_t)o * a.grid + blk];
+    }
+    for (int idx = t; idx < NS * N * R; idx += kBlock) {
+        const int s = idx / (N * R), k = idx % (N * R);
+        s_plo[idx] = from_d2<C>(a.t_lo[s][k]);
+    }
+    __syncthreads();
+    for (int idx = t; idx < NS * N * Q; idx += kBlock) {
+        const int s = idx / (N * Q), k = idx % (N * Q), o = k / Q;
+        s_tq[idx] = from_d2<C>(cmul(s_phi[s * N + o], a.t_mid[s][k]));
+    }
+    __syncthreads();
+
+    double2 acc[RHO ? 3 : 1][RHO ? N : 1];
+#pragma unroll
+    for (int s = 0; s < (RHO ? 3 : 1); ++s)
+#pragma unroll
+        for (int o = 0; o < (RHO ? N : 1); ++o) acc[s][o] = make_double2(0.0, 0.0);
+    const int r = t % R;
+    auto factor = [&](int set, int o, int qm) {
+        return cmul(s_plo[(set * N + o) * R + r], s_tq[(set * N + o) * Q + qm]);
+    };
+    if (t < active) {
+        const long long m0 = blk * (long long)R * Q;
+        const CS *__restrict__ ain = (const CS *)a.a_in;
+        CS *__restrict__ aout = (CS *)a.a_out;
+        const long long mc = a.m_count;
+        for (int qm = t / R; qm < Q; qm += cR) {
+            asm volatile("" ::: "memory");
+            const long long m = m0 + (long long)qm * R + r;
+            C w[NNN];
+#pragma unroll
+            for (int k = 0; k < NNN; ++k) w[k] = conv<C>(ain[(long long)NNN * m + k]);
+
+            // Each stage runs two passes over its 16 groups of four slots: first
+            // the rho terms (the final-point table old_f resident in scalar
+            // registers), then the step itself (table old resident), which
+            // overwrites the slots.  Per group only the four group coefficients
+            // are fetched again.
+            // ---- step n: groups g = i' + N i'', slots 4g .. 4g+3
+            {
+                if (RHO) {
+                    const T *co = fresh(coef);
+                    C tf[N] = {};
+#pragma unroll
+                    for (int g = 0; g < N * N; ++g) {
+                        const T *cg = fresh(coef);
+#pragma unroll
+                        for (int o = 0; o < N; ++o) {
+                            C sf = {};
+#pragma unroll
+                            for (int i = 0; i < N; ++i) cmac(sf, coef_ld(co, kC3Oldf + o * N + i), w[N * g + i]);
+                            cmac(tf[o], coef_ld(cg, kC3AFf + o * 16 + g), sf);
+                        }
+                    }
+#pragma unroll
+                    for (int o = 0; o < N; ++o) {
+                        const double2 v = to_d2(cmul(factor(3, o, qm), tf[o]));
+                        acc[0][o].x += v.x;
+                        acc[0][o].y += v.y;
+                    }
+                }
+                asm volatile("" ::: "memory");
+                const T *co = fresh(coef);
+                C bn[N];
+#pragma unroll
+                for (int o = 0; o < N; ++o) bn[o] = factor(0, o, qm);
+#pragma unroll
+                for (int g = 0; g < N * N; ++g) {
+                    const T *cg = fresh(coef);
+                    C xs[N];
+#pragma unroll
+                    for (int i = 0; i < N; ++i) xs[i] = w[N * g + i];
+#pragma unroll
+                    for (int o = 0; o < N; ++o) {
+                        C s = {};
+#pragma unroll
+                        for (int i = 0; i < N; ++i) cmac(s, coef_ld(co, kC3Old + o * N + i), xs[i]);
+                        w[N * g + o] = cmul(bn[o], cmul(coef_ld(cg, kC3AF + o * 16 + g), s));
+                    }
+                }
+            }
+            // ---- step n+1: groups (o, i''), slots o + N i' + N^2 i'' over i'
+            {
+                asm volatile("" ::: "memory");
+                if (RHO) {
+                    const T *co = fresh(coef);
+                    C tf[N] = {};
+#pragma unroll
+                    for (int ipp = 0; ipp < N; ++ipp) {
+#pragma unroll
+                        for (int o = 0; o < N; ++o) {
+                            const T *cg = fresh(coef);
+#pragma unroll
+                            for (int op = 0; op < N; ++op) {
+                                C sf = {};
+#pragma unroll
+                                for (int ip = 0; ip < N; ++ip)
+                                    cmac(sf, coef_ld(co, kC3Oldf + op * N + ip), w[o + N * ip + N * N * ipp]);
+                                cmac(tf[op], coef_ld(cg, kC3GHf + op * 16 + ipp * N + o), sf);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int op = 0; op < N; ++op) {
+                        const double2 v = to_d2(cmul(factor(4, op, qm), tf[op]));
+                        acc[1][op].x += v.x;
+                        acc[1][op].y += v.y;
+                    }
+                }
+                asm volatile("" ::: "memory");
+                const T *co = fresh(coef);
+                C cn[N];
+#pragma unroll
+                for (int op = 0; op < N; ++op) cn[op] = factor(1, op, qm);
+#pragma unroll
+                for (int ipp = 0; ipp < N; ++ipp) {
+#pragma unroll
+                    for (int o = 0; o < N; ++o) {
+                        const T *cg = fresh(coef);
+                        C ys[N];
+#pragma unroll
+                        for (int ip = 0; ip < N; ++ip) ys[ip] = w[o + N * ip + N * N * ipp];
+#pragma unroll
+                        for (int op = 0; op < N; ++op) {
+                            C s = {};
+#pragma unroll
+                            for (int ip = 0; ip < N; ++ip) cmac(s, coef_ld(co, kC3Old + op * N + ip), ys[ip]);
+                            w[o + N * op + N * N * ipp] =
+                                cmul(cn[op], cmul(coef_ld(cg, kC3GH + op * 16 + ipp * N + o), s));
+                        }
+                    }
+                }
+            }
+            // ---- step n+2: groups (o, o'), slots o + N o' + N^2 i'' over i''; store
+            {
+                asm volatile("" ::: "memory");
+                if (RHO) {
+                    const T *co = fresh(coef);
+                    C tf[N] = {};
+#pragma unroll
+                    for (int op = 0; op < N; ++op) {
+#pragma unroll
+                        for (int o = 0; o < N; ++o) {
+                            const T *cg = fresh(coef);
+#pragma unroll
+                            for (int opp = 0; opp < N; ++opp) {
+                                C sf = {};
+#pragma unroll
+                                for (int ipp = 0; ipp < N; ++ipp)
+                                    cmac(sf, coef_ld(co, kC3Oldf + opp * N + ipp), w[o + N * op + N * N * ipp]);
+                                cmac(tf[opp], coef_ld(cg, kC3PQf + opp * 16 + op * N + o), sf);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int opp = 0; opp < N; ++opp) {
+                        const double2 v = to_d2(cmul(factor(5, opp, qm), tf[opp]));
+                        acc[2][opp].x += v.x;
+                        acc[2][opp].y += v.y;
+                    }
+                }
+                asm volatile("" ::: "memory");
+                const T *co = fresh(coef);
+                C dn[N];
+#pragma unroll
+                for (int opp = 0; opp < N; ++opp) dn[opp] = factor(2, opp, qm);
+#pragma unroll
+                for (int op = 0; op < N; ++op) {
+#pragma unroll
+                    for (int o = 0; o < N; ++o) {
+                        const T *cg = fresh(coef);
+#pragma unroll
+                        for (int opp = 0; opp < N; ++opp) {
+                            C s = {};
+#pragma unroll
+                            for (int ipp = 0; ipp < N; ++ipp)
+                                cmac(s, coef_ld(co, kC3Old + opp * N + ipp), w[o + N * op + N * N * ipp]);
+                            aout[m + mc * (o + N * op + N * N * opp)] =
+                                conv<CS>(cmul(dn[opp], cmul(coef_ld(cg, kC3PQ + opp * 16 + op * N + o), s)));
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (RHO) {
+        const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+#pragma unroll
+            for (int o = 0; o < N; ++o) {
+                double2 v = acc[s][o];
+                for (int off = 32; off > 0; off >>= 1) {
+                    v.x += __shfl_xor(v.x, off, 64);
+                    v.y += __shfl_xor(v.y, off, 64);
+                }
+                if (lane == 0) s_red[(s * (kBlock / 64) + wave) * N + o] = v;
+            }
+        }
+        __syncthreads();
+        if (t < 3 * N) {
+            const int s = t / N, o = t % N;
+            double2 sum = make_double2(0.0, 0.0);
+            for (int w = 0; w < kBlock / 64; ++w) {
+                sum.x += s_red[(s * (kBlock / 64) + w) * N + o].x;
+                sum.y += s_red[(s * (kBlock / 64) + w) * N + o].y;
+            }
+            a.partials[s][blk * N + o] = sum;
+        }
+    }
+}
+
+template <typename S, typename T, bool RHO>
+hipError_t launch_step3_t(const Step3Args &a, hipStream_t st) {
+    using C = typename Cx<T>::type;
+    const Step3Lds lay = step3_lds_layout((int)sizeof(C), RHO, a.R, a.Q);
+    hipLaunchKernelGGL((step3_kernel<S, T, RHO>), dim3(a.grid), dim3(kBlock), lay.total, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t step3_lds_bytes(int prec, bool with_rho, int R, int Q) {
+    return step3_lds_layout(prec == kPrecC64 ? 8 : 16, with_rho, R, Q).total;
+}
+
+hipError_t launch_step3(int prec, bool with_rho, const Step3Args &a, hipStream_t st) {
+    switch (prec) {
+    case kPrecC128:
+        return with_rho ? launch_step3_t<double, double, true>(a, st) : launch_step3_t<double, double, false>(a, st);
+    case kPrecC64:
+        return with_rho ? launch_step3_t<float, float, true>(a, st) : launch_step3_t<float, float, false>(a, st);
+    case kPrecC64F64:
+        return with_rho ? launch_step3_t<float, double, true>(a, st) : launch_step3_t<float, double, false>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step3_coef(const Coef3Args &a, hipStream_t st) {
+    if (a.prec == kPrecC64) hipLaunchKernelGGL(step3_coef_kernel<float>, dim3(1), dim3(512), 0, st, a);
+    else hipLaunchKernelGGL(step3_coef_kernel<double>, dim3(1), dim3(512), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace quapi

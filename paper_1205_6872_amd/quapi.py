@@ -29,7 +29,8 @@ SETUP_G, SETUP_ETA, SETUP_U, SETUP_K = 0, 1, 2, 3
 
 EXPORTED_SYMBOLS = (
     "quapi_footprint", "quapi_paper_pmc_bytes", "quapi_create", "quapi_propagate",
-    "quapi_propagate_async", "quapi_step_count", "quapi_get_setup", "quapi_read_tensor",
+    "quapi_propagate_async", "quapi_step_count", "quapi_fused_steps", "quapi_set_fused_steps",
+    "quapi_get_setup", "quapi_read_tensor",
     "quapi_tensor_size", "quapi_set_timing", "quapi_get_timing", "quapi_destroy",
     "quapi_last_error",
 )
@@ -74,6 +75,8 @@ def load_library() -> ctypes.CDLL:
     lib.quapi_propagate.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, _DP]
     lib.quapi_propagate_async.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, vp]
     lib.quapi_step_count.argtypes = [vp, ip]
+    lib.quapi_fused_steps.argtypes = [vp, ip]
+    lib.quapi_set_fused_steps.argtypes = [vp, ctypes.c_int]
     lib.quapi_get_setup.argtypes = [vp, ctypes.c_int, _DP, sz]
     lib.quapi_read_tensor.argtypes = [vp, sz, sz, _DP]
     lib.quapi_tensor_size.argtypes = [vp, ctypes.POINTER(sz)]
@@ -209,6 +212,18 @@ class Context:
             sel_arr, n_sel = _sel_array(sel)
             psel = sel_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
         _check(lib().quapi_propagate_async(h, int(n_steps), psel, n_sel, ctypes.c_void_p(rho_out_dev)), h)
+
+    def fused_steps(self) -> int:
+        """Full-window steps per launch (3, 2 or 1): calls that end on a multiple
+        of it past L give the same bits as one call."""
+        v = ctypes.c_int(0)
+        _check(lib().quapi_fused_steps(self._live(), ctypes.byref(v)))
+        return int(v.value)
+
+    def set_fused_steps(self, steps: int) -> None:
+        """Pin the full-window steps per launch (1, 2, 3; 0 = default)."""
+        h = self._live()
+        _check(lib().quapi_set_fused_steps(h, int(steps)), h)
 
     def step_count(self) -> int:
         v = ctypes.c_int(0)

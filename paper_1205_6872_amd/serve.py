@@ -92,6 +92,7 @@ class _Active:
     slot: int
     fp: int
     admit_s: float
+    fuse: int = 1
     enqueued: int = 0
     events: deque = field(default_factory=deque)
 
@@ -128,7 +129,7 @@ class Server:
         rho_dev = torch.empty((w.n_steps + 1, w.N, 2), dtype=torch.float64, device=self.device)
         ctx.propagate_async(0, [0], rho_dev.data_ptr())          # rho(t_0)
         return _Active(w=w, index=index, ctx=ctx, stream=stream, rho_dev=rho_dev, slot=slot,
-                       fp=Q.footprint(p), admit_s=now)
+                       fp=Q.footprint(p), admit_s=now, fuse=ctx.fused_steps())
 
     def run(self, requests, realtime: bool = True) -> list[RequestResult]:
         """Serve the requests (each with meta['arrival_s']); returns results in index order."""
@@ -184,10 +185,12 @@ class Server:
                     if self.chunk_ms is not None:
                         chunk = int(min(256, max(2, self.chunk_ms * 1e-3 / est_step_s(a.w))))
                     end = min(a.enqueued + chunk, a.w.n_steps)
-                    # never end a chunk inside a fused step pair (L+1, L+2), ...:
+                    # never end a chunk inside a fused step group (L+1 .. L+F), ...:
                     # the run then has the same bits as one call of all steps
-                    if end < a.w.n_steps and end > a.w.L and (end - a.w.L) % 2 == 1:
-                        end -= 1
+                    if end < a.w.n_steps and end > a.w.L and (end - a.w.L) % a.fuse:
+                        end -= (end - a.w.L) % a.fuse
+                        if end <= a.enqueued:
+                            end = min(a.enqueued + a.fuse, a.w.n_steps)
                     k = end - a.enqueued
                     off = (a.enqueued + 1) * a.w.N * 16
                     a.ctx.propagate_async(k, None, a.rho_dev.data_ptr() + off)

@@ -166,43 +166,89 @@ def _sampled_entry_check(w, dtype, tol):
             assert abs(np.trace(rho[0]) - 1) <= tr_tol
 
 
-def _sampled_fused_check(w, dtype, tol):
-    """Two full-window steps done by one fused launch, at the workload's size,
-    checked on sampled entries by applying the one-step entry formula twice."""
+def _sampled_fused_check(w, dtype, tol, F=None):
+    """One fused launch of F = 2 or 3 full-window steps at the workload's size
+    (default: the library's choice), checked on sampled entries by applying the
+    one-step entry formula F times."""
     rng = np.random.default_rng(19)
     L, N = w.L, w.N
     inp = orun.inputs_from(w)
     _, ec, _, K = orun.setup(inp)
-    mr = N ** (L - 2)                       # items: digits of points n-L+2 .. n-1
-    ms = np.unique(np.concatenate([[0, mr - 1], rng.integers(0, mr, 14)]))
     with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
+        if F is None:
+            F = ctx.fused_steps()
+            assert F == (3 if dtype == "c128" and L >= 14 else 2), F
+        else:
+            ctx.set_fused_steps(F)
+        mr = N ** (L - F)                   # items: digits of points n-L+F .. n-1
+        ms = np.unique(np.concatenate([[0, mr - 1], rng.integers(0, mr, 14)]))
         ctx.propagate(L, sel=[L])           # growth and the first full-window step n = L
-        n = L + 1                           # pairs start at n = L+1, L+3, ...: (n, n + 1) is one
-        a_in = {int(m): ctx.read_tensor(N * N * int(m), N * N) for m in ms}
+        n = L + 1                           # groups start at n = L+1, L+1+F, ...
+        a_in = {int(m): ctx.read_tensor(N ** F * int(m), N ** F) for m in ms}
         ctx.set_timing(True)
-        rho = ctx.propagate(2)
+        rho = ctx.propagate(F)
         t = ctx.get_timing()
-        assert (t["step_launches"], t["step_steps"]) == (1, 2), t     # one fused launch ran both
+        assert (t["step_launches"], t["step_steps"]) == (1, F), t     # one fused launch ran them all
         assert np.abs(np.trace(rho, axis1=1, axis2=2) - 1).max() <= (1e-12 if dtype == "c128" else 1e-6)
         worst = 0.0
         for m in ms:
-            x = a_in[int(m)]
+            m = int(m)
+            x = a_in[m]
             got, want = [], []
-            for o in range(N):
-                # A_n entries (i', m, o) for i' = 0..N-1
-                y = np.array([oentry.step_entry(w.s, K, ec, L, n, ip + N * int(m), o, x[N * ip:N * ip + N])
-                              for ip in range(N)])
-                for op in range(N):
-                    want.append(oentry.step_entry(w.s, K, ec, L, n + 1, int(m) + mr * o, op, y))
-                    got.append(ctx.read_tensor(int(m) + mr * (o + N * op), 1)[0])
+            step = lambda k, mid, o, v: oentry.step_entry(w.s, K, ec, L, n + k, mid, o, v)
+            if F == 2:
+                for o in range(N):
+                    # A_n entries (i', m, o) for i' = 0..N-1
+                    y = np.array([step(0, ip + N * m, o, x[N * ip:N * ip + N]) for ip in range(N)])
+                    for op in range(N):
+                        want.append(step(1, m + mr * o, op, y))
+                        got.append(ctx.read_tensor(m + mr * (o + N * op), 1)[0])
+            else:
+                # x index i + N i' + N^2 i''; y[o][i'][i''], z[o][o'][i'']
+                y = np.array([[[step(0, ip + N * ipp + N * N * m, o, x[N * ip + N * N * ipp:][:N])
+                                for ipp in range(N)] for ip in range(N)] for o in range(N)])
+                z = np.array([[[step(1, ipp + N * m + N ** (L - 2) * o, op, y[o, :, ipp])
+                                for ipp in range(N)] for op in range(N)] for o in range(N)])
+                for o in range(N):
+                    for op in range(N):
+                        for opp in range(N):
+                            want.append(step(2, m + mr * o + mr * N * op, opp, z[o, op, :]))
+                            got.append(ctx.read_tensor(m + mr * (o + N * op + N * N * opp), 1)[0])
             got, want = np.array(got), np.array(want)
             worst = max(worst, np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))
         assert worst <= tol, worst
 
 
-@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 3e-5), ("c64f64", 3e-7)])
-def test_headline_size_fused_pair_sampled_entries(dtype, tol):
-    _sampled_fused_check(W.spin_boson_l15(dtype), dtype, tol)
+@pytest.mark.parametrize("dtype,tol,F", [("c128", 1e-12, None), ("c128", 1e-12, 2), ("c64", 3e-5, None),
+                                         ("c64", 3e-5, 3), ("c64f64", 3e-7, None), ("c64f64", 3e-7, 3)])
+def test_headline_size_fused_group_sampled_entries(dtype, tol, F):
+    _sampled_fused_check(W.spin_boson_l15(dtype), dtype, tol, F)
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", None), ("c64", 1e-5), ("c64f64", 1e-6)])
+@pytest.mark.parametrize("F", [1, 2, 3])
+def test_every_group_width_against_oracle(F, dtype, tol):
+    # the default picks 2 at this size; each width runs the whole propagation
+    w = W.spin_boson_l7()
+    with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
+        assert ctx.fused_steps() == 2
+        ctx.set_fused_steps(F)
+        assert ctx.fused_steps() == F
+        if F > 1:
+            ctx.set_timing(True)
+        g = ctx.propagate(100)
+        if F > 1:
+            t = ctx.get_timing()
+            assert t["step_steps"] >= F * (t["step_launches"] - 2), t     # groups ran as groups
+    o = oracle_rho(w, 100)[1:]
+    if tol is None:
+        err = rel_err_per_step(g, o)
+        assert err.max() <= TOL_C128, (err.argmax(), err.max())
+    else:
+        assert np.abs(g - o).max() <= tol
+    with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
+        with pytest.raises(Q.QuapiError):
+            ctx.set_fused_steps(4)
 
 
 def test_headline_size_sampled_entries_c128():
@@ -226,7 +272,7 @@ def _fits(w, dtype):
     return need <= free
 
 
-def test_maximum_size_m2_l16_fused_pair_c128():
+def test_maximum_size_m2_l16_fused_group_c128():
     # 4^16 = 4.3e9 entries, 2 x 68.7 GB: the largest complex128 M = 2 window that fits in HBM;
     # tensor offsets pass 2^32 entries
     w = W.spin_boson_l15("c128").with_(L=16, name="spin_boson_l16")
