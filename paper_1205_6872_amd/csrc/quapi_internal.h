@@ -114,11 +114,12 @@ struct Step3Args {
     const void *coef;           // kC3Count complex entries in the compute precision
 };
 
-// Coefficients of the three-step kernel (compute precision):
+// Coefficients of the three-step kernel (compute precision), the four of one
+// group of a stage contiguous (indexed by the stage's new point last):
 //   old[o][i], oldf[o][i]       oldest point seen from the new point (every step)
-//   AF[o][i''][i']  an(o, i') F(o, i'')     step n: points n-L+1 (lag L-1), n-L+2 (lag L-2)
-//   GH[o'][i''][o]  G(o', o) H(o', i'')     step n+1: point n (lag 1, K), n-L+2 (lag L-1)
-//   PQ[o''][o'][o]  P(o'', o') Q(o'', o)    step n+2: point n+1 (lag 1, K), n (lag 2)
+//   AF[i''][i'][o]  an(o, i') F(o, i'')     step n: points n-L+1 (lag L-1), n-L+2 (lag L-2)
+//   GH[i''][o][o']  G(o', o) H(o', i'')     step n+1: point n (lag 1, K), n-L+2 (lag L-1)
+//   PQ[o'][o][o'']  P(o'', o') Q(o'', o)    step n+2: point n+1 (lag 1, K), n (lag 2)
 // and the final-point versions (suffix f) for rho.
 constexpr int kC3Old = 0, kC3Oldf = 16, kC3AF = 32, kC3AFf = 96, kC3GH = 160, kC3GHf = 224, kC3PQ = 288,
               kC3PQf = 352, kC3Count = 416;

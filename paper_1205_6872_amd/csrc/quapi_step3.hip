@@ -57,13 +57,14 @@ __global__ void step3_coef_kernel(const Coef3Args a) {
     } else {
         const bool fin = ((k - kC3AF) / 64) % 2 == 1;
         const int part = (k - kC3AF) / 128, e = (k - kC3AF) % 64;
-        const int x = e / NN, y = (e / N) % N, z = e % N;    // [x][y][z]
-        if (part == 0) {        // AF[o][i''][i'] = an(o, i') F(o, i'')
-            v = cmul(tab(fin ? a.anf_tab : a.an_tab, x, z), tab(fin ? a.ff_tab : a.f_tab, x, y));
-        } else if (part == 1) { // GH[o'][i''][o] = G(o', o) H(o', i'')
-            v = cmul(tab(fin ? a.gf_tab : a.g_tab, x, z), tab(fin ? a.hf_tab : a.h_tab, x, y));
-        } else {                // PQ[o''][o'][o] = P(o'', o') Q(o'', o)
-            v = cmul(tab(fin ? a.pf_tab : a.p_tab, x, y), tab(fin ? a.qf_tab : a.q_tab, x, z));
+        // [x][y][z]: (x, y) is the group, z the new point of the stage
+        const int x = e / NN, y = (e / N) % N, z = e % N;
+        if (part == 0) {        // AF[i''][i'][o] = an(o, i') F(o, i'')
+            v = cmul(tab(fin ? a.anf_tab : a.an_tab, z, y), tab(fin ? a.ff_tab : a.f_tab, z, x));
+        } else if (part == 1) { // GH[i''][o][o'] = G(o', o) H(o', i'')
+            v = cmul(tab(fin ? a.gf_tab : a.g_tab, z, y), tab(fin ? a.hf_tab : a.h_tab, z, x));
+        } else {                // PQ[o'][o][o''] = P(o'', o') Q(o'', o)
+            v = cmul(tab(fin ? a.pf_tab : a.p_tab, z, x), tab(fin ? a.qf_tab : a.q_tab, z, y));
         }
     }
     ((C *)a.out)[k] = conv<C>(v);
@@ -73,9 +74,9 @@ __global__ void step3_coef_kernel(const Coef3Args a) {
 // n-L+3 .. n-1) reads the N^3 contiguous entries of the oldest three points
 // (i = n-L, i' = n-L+1, i'' = n-L+2) into w[i + N i' + N^2 i''] and writes the
 // N^3 entries of the three new points (o = n, o' = n+1, o'' = n+2):
-//   y(o, i', i'')  = B(o, m) AF(o, i'', i') sum_i old(o, i) x(i, i', i'')        (step n)
-//   z(o, o', i'')  = C(o', m) GH(o', i'', o) sum_i' old(o', i') y(o, i', i'')    (step n+1)
-//   out(o, o', o'') = D(o'', m) PQ(o'', o', o) sum_i'' old(o'', i'') z(o, o', i'') (step n+2)
+//   y(o, i', i'')  = B(o, m) AF(i'', i', o) sum_i old(o, i) x(i, i', i'')        (step n)
+//   z(o, o', i'')  = C(o', m) GH(i'', o, o') sum_i' old(o', i') y(o, i', i'')    (step n+1)
+//   out(o, o', o'') = D(o'', m) PQ(o', o, o'') sum_i'' old(o'', i'') z(o, o', i'') (step n+2)
 // B, C, D are the products over the digits of m.  Each stage overwrites the
 // four slots it reads, so w holds x, then y (slot o + N i' + N^2 i''), then z
 // (slot o + N o' + N^2 i'').  With RHO, rho at each of the three steps comes
@@ -152,7 +153,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                             C sf = {};
 #pragma unroll
                             for (int i = 0; i < N; ++i) cmac(sf, coef_ld(co, kC3Oldf + o * N + i), w[N * g + i]);
-                            cmac(tf[o], coef_ld(cg, kC3AFf + o * 16 + g), sf);
+                            cmac(tf[o], coef_ld(cg, kC3AFf + g * N + o), sf);
                         }
                     }
 #pragma unroll
@@ -178,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                         C s = {};
 #pragma unroll
                         for (int i = 0; i < N; ++i) cmac(s, coef_ld(co, kC3Old + o * N + i), xs[i]);
-                        w[N * g + o] = cmul(bn[o], cmul(coef_ld(cg, kC3AF + o * 16 + g), s));
+                        w[N * g + o] = cmul(bn[o], cmul(coef_ld(cg, kC3AF + g * N + o), s));
                     }
                 }
             }
@@ -199,7 +200,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
 #pragma unroll
                                 for (int ip = 0; ip < N; ++ip)
                                     cmac(sf, coef_ld(co, kC3Oldf + op * N + ip), w[o + N * ip + N * N * ipp]);
-                                cmac(tf[op], coef_ld(cg, kC3GHf + op * 16 + ipp * N + o), sf);
+                                cmac(tf[op], coef_ld(cg, kC3GHf + (ipp * N + o) * N + op), sf);
                             }
                         }
                     }
@@ -229,7 +230,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
 #pragma unroll
                             for (int ip = 0; ip < N; ++ip) cmac(s, coef_ld(co, kC3Old + op * N + ip), ys[ip]);
                             w[o + N * op + N * N * ipp] =
-                                cmul(cn[op], cmul(coef_ld(cg, kC3GH + op * 16 + ipp * N + o), s));
+                                cmul(cn[op], cmul(coef_ld(cg, kC3GH + (ipp * N + o) * N + op), s));
                         }
                     }
                 }
@@ -251,7 +252,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
 #pragma unroll
                                 for (int ipp = 0; ipp < N; ++ipp)
                                     cmac(sf, coef_ld(co, kC3Oldf + opp * N + ipp), w[o + N * op + N * N * ipp]);
-                                cmac(tf[opp], coef_ld(cg, kC3PQf + opp * 16 + op * N + o), sf);
+                                cmac(tf[opp], coef_ld(cg, kC3PQf + (op * N + o) * N + opp), sf);
                             }
                         }
                     }
@@ -279,7 +280,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                             for (int ipp = 0; ipp < N; ++ipp)
                                 cmac(s, coef_ld(co, kC3Old + opp * N + ipp), w[o + N * op + N * N * ipp]);
                             aout[m + mc * (o + N * op + N * N * opp)] =
-                                conv<CS>(cmul(dn[opp], cmul(coef_ld(cg, kC3PQ + opp * 16 + op * N + o), s)));
+                                conv<CS>(cmul(dn[opp], cmul(coef_ld(cg, kC3PQ + (op * N + o) * N + opp), s)));
                         }
                     }
                 }

@@ -32,10 +32,13 @@ def case_workload(M: int, L: int, dtype: str, seed: int = 1) -> W.Workload:
                       n_steps=0, xi=0.3, omega_c=7.5, dtype=dtype)
 
 
-def time_case(M: int, L: int, dtype: str, steps: int) -> dict:
+def time_case(M: int, L: int, dtype: str, steps: int, fused_steps: int = 0) -> dict:
     w = case_workload(M, L, dtype)
     N = M * M
     with Q.create(Q.params_from(w)) as ctx:
+        ctx.set_fused_steps(fused_steps)
+        F = ctx.fused_steps()
+        steps -= steps % F                                # whole groups
         ctx.propagate(L)                                  # growth and the first full-window step
         ctx.set_timing(True)
         ctx.get_timing()
@@ -55,7 +58,7 @@ def time_case(M: int, L: int, dtype: str, steps: int) -> dict:
 
     ms_r, spl_r, gbs_r = per(t_rho)
     ms_n, spl_n, gbs_n = per(t_no)
-    return {"M": M, "L": L, "dtype": dtype, "entries": N ** L, "steps": steps,
+    return {"M": M, "L": L, "dtype": dtype, "entries": N ** L, "steps": steps, "fused_steps": F,
             "rho_launch_ms": round(ms_r, 4), "rho_steps_per_launch": round(spl_r, 3), "rho_gbs": round(gbs_r, 1),
             "norho_launch_ms": round(ms_n, 4), "norho_steps_per_launch": round(spl_n, 3),
             "norho_gbs": round(gbs_n, 1)}
@@ -91,7 +94,8 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--cases", default="4:7,3:8,2:12")
     ap.add_argument("--dtypes", default="c128,c64,c64f64")
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--fused-steps", default="0", help="comma list of widths to pin (0 = default)")
     ap.add_argument("--paper-table1", action="store_true",
                     help="the paper's Table 1 sweep (its model system, dk = 2..15, 989 main steps)")
     args = ap.parse_args(argv)
@@ -102,7 +106,8 @@ def main(argv=None) -> int:
     for c in args.cases.split(","):
         M, L = (int(v) for v in c.split(":"))
         for d in args.dtypes.split(","):
-            print(json.dumps(time_case(M, L, d, args.steps)), flush=True)
+            for f in args.fused_steps.split(","):
+                print(json.dumps(time_case(M, L, d, args.steps, int(f))), flush=True)
     return 0
 
 
