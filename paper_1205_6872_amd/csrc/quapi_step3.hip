@@ -39,6 +39,12 @@ __device__ __forceinline__ const T *fresh(const T *p) {
     asm volatile("" : "+s"(p));
     return p;
 }
+// The same for a plane stride, so the 64 output-plane offsets are formed per
+// group instead of all being kept (and spilled) for the whole item.
+__device__ __forceinline__ long long fresh_stride(long long v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
 
 // The coefficients (layout at kC3Old ..), computed in FP64 and rounded once to
 // the compute precision.
@@ -273,13 +279,15 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
 #pragma unroll
                     for (int o = 0; o < N; ++o) {
                         const T *cg = fresh(coef);
+                        const long long st = fresh_stride(mc);
+                        CS *const po = aout + m + st * (o + N * op);
 #pragma unroll
                         for (int opp = 0; opp < N; ++opp) {
                             C s = {};
 #pragma unroll
                             for (int ipp = 0; ipp < N; ++ipp)
                                 cmac(s, coef_ld(co, kC3Old + opp * N + ipp), w[o + N * op + N * N * ipp]);
-                            aout[m + mc * (o + N * op + N * N * opp)] =
+                            po[st * N * N * opp] =
                                 conv<CS>(cmul(dn[opp], cmul(coef_ld(cg, kC3PQ + (op * N + o) * N + opp), s)));
                         }
                     }
