@@ -16,7 +16,7 @@ its own model system is Sec. III):
 * ``spin_boson_l7``    M=2, L=7,  100 steps (small; the oracle finishes in seconds)
 * ``spin_boson_l12``   M=2, L=12, 500 steps
 * ``three_site_l8``    M=3, L=8,  300 steps, tight-binding chain
-* ``spin_boson_l15``   M=2, L=15, 1000 steps (the headline propagation size)
+* ``spin_boson_l15``   M=2, L=15, 1000 steps (4^15 = 1.07e9 tensor entries)
 * ``paper_quantum_dot`` the paper's Sec. III model system (super-Ohmic J with
   a Gaussian cutoff, passed as a table), M=2
 * ``serving_requests`` a seeded Poisson trace of mixed requests

@@ -10,7 +10,7 @@ Small cases run the whole propagation through both sides.  At the full
 workload sizes the oracle cannot run every step, so the test compares the
 first steps completely, checks the trace and Hermiticity invariants at every
 step, and checks full-window steps entry by entry on sampled outputs
-(oracle.entry) at the headline size.
+(oracle.entry) at L = 15 (4^15 entries).
 """
 import numpy as np
 import pytest
@@ -221,7 +221,7 @@ def _sampled_fused_check(w, dtype, tol, F=None):
 
 @pytest.mark.parametrize("dtype,tol,F", [("c128", 1e-12, None), ("c128", 1e-12, 2), ("c64", 3e-5, None),
                                          ("c64", 3e-5, 3), ("c64f64", 3e-7, None), ("c64f64", 3e-7, 3)])
-def test_headline_size_fused_group_sampled_entries(dtype, tol, F):
+def test_l15_fused_group_sampled_entries(dtype, tol, F):
     _sampled_fused_check(W.spin_boson_l15(dtype), dtype, tol, F)
 
 
@@ -251,15 +251,15 @@ def test_every_group_width_against_oracle(F, dtype, tol):
             ctx.set_fused_steps(4)
 
 
-def test_headline_size_sampled_entries_c128():
+def test_l15_single_steps_sampled_entries_c128():
     _sampled_entry_check(W.spin_boson_l15("c128"), "c128", 1e-12)
 
 
-def test_headline_size_sampled_entries_c64():
+def test_l15_single_steps_sampled_entries_c64():
     _sampled_entry_check(W.spin_boson_l15("c64"), "c64", 2e-5)
 
 
-def test_headline_size_sampled_entries_c64f64():
+def test_l15_single_steps_sampled_entries_c64f64():
     # only the complex64 rounding of the stored values remains
     _sampled_entry_check(W.spin_boson_l15("c64f64"), "c64f64", 2e-7)
 
@@ -333,7 +333,7 @@ def test_m3_m4_against_oracle_every_tier(name, w, n, dtype, tol):
 # from the FP32 sums appears only between steps 200 and 260); with FP64
 # arithmetic only the storage rounding of 1e9 entries remains.
 @pytest.mark.parametrize("dtype,max_drho,max_drift", [("c64", 1e-5, 1e-6), ("c64f64", 1e-5, 1e-6)])
-def test_c64_tiers_against_c128_headline_workload(dtype, max_drho, max_drift):
+def test_c64_tiers_against_c128_at_l15(dtype, max_drho, max_drift):
     w = W.spin_boson_l15(dtype)
     n = 150
     r64 = gpu_rho(w, n, dtype=dtype)
