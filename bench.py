@@ -30,6 +30,8 @@ HBM.  `roofline` prices the step kernel against the HBM peak: algorithmic
 bytes per launch = 2 * N^L * sizeof(complex) (one read, one write of the
 tensor), divided by the kernel's average duration per launch from HIP events
 on the library's stream (`steps_per_launch` says how many steps a launch covers).
+`step_equivalent_gbs` divides the same bytes by the measured time per step:
+the rate an unfused step would need to match it.
 `cpu_baseline` times the oracle (plain C, OpenMP) on a bounded sample of the
 same workload on the host.
 
@@ -261,7 +263,9 @@ def main() -> int:
                      "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kernel_name(main_t, r["steps_per_launch"]),
                      "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_launch": r["bytes_per_launch"],
-                     "steps_per_launch": round(r["steps_per_launch"], 3)},
+                     "steps_per_launch": round(r["steps_per_launch"], 3),
+                     # bytes a single (unfused) step reads and writes, per measured step time
+                     "step_equivalent_gbs": round(r["bytes_per_launch"] / (r["ms_per_step"] * 1e-3) / 1e9, 1)},
         "setup_ms": round(r["setup_ms"], 3),
         "growth_ms": round(r["grow_ms"], 3),
         "finalize_ms": round(r["finalize_ms"], 4),
@@ -280,7 +284,8 @@ def main() -> int:
                          "traffic": measured_traffic(t),
                          "kernel": kernel_name(t, a["steps_per_launch"]),
                          "kernel_ms": round(a["kernel_ms"], 4), "bytes_per_launch": a["bytes_per_launch"],
-                         "steps_per_launch": round(a["steps_per_launch"], 3)},
+                         "steps_per_launch": round(a["steps_per_launch"], 3),
+                         "step_equivalent_gbs": round(a["bytes_per_launch"] / (a["ms_per_step"] * 1e-3) / 1e9, 1)},
             "max_abs_drho_vs_f64": d, "trace_drift_vs_f64": drift, "steps_compared": len(a["rho"]),
         }
     if not args.no_copy_ceiling:
