@@ -3,14 +3,16 @@
 Sec. II, exact path-sum equation with the discretized influence functional:
 
     rho(t_n)[o_n] = sum over o_0 .. o_{n-1} of
-        rho0[o_0] * prod_{k<n} K[o_{k+1}, o_k]
+        rho0[o_0] * prod_{k<n} K_{k+1}[o_{k+1}, o_k]
         * exp( - sum_{k=0..n} sum_{k'=max(0,k-L)..k}
                  (s_k^+ - s_k^-)(eta_kk' s_k'^+ - conj(eta_kk') s_k'^-) ),
 
 every path enumerated explicitly (N^{n+1} of them, N = M^2), with each
 eta_kk' computed from the time intervals of its two points
 (``eta.eta_pair``), not from the class formulas.  rho(t_0) = rho0: the path
-has one point and a zero-length interval.
+has one point and a zero-length interval.  K_{k+1} is the propagator over
+(t_k, t_{k+1}]: K is one N x N matrix for a constant H, or a stack
+(n_K, N, N) of per-interval propagators (interval k uses K[min(k, n_K - 1)]).
 """
 from __future__ import annotations
 
@@ -19,6 +21,14 @@ import numpy as np
 from .eta import eta_pair
 
 __all__ = ["brute_rho", "brute_tensor"]
+
+
+def _interval_K(K: np.ndarray, k: int) -> np.ndarray:
+    """Propagator over (t_k, t_{k+1}]."""
+    K = np.asarray(K)
+    if K.ndim == 2:
+        return K
+    return K[min(k, len(K) - 1)]
 
 
 def brute_rho(s, K: np.ndarray, rho0: np.ndarray, G, dt: float, L: int, n: int) -> np.ndarray:
@@ -43,7 +53,7 @@ def brute_rho(s, K: np.ndarray, rho0: np.ndarray, G, dt: float, L: int, n: int) 
             expo += (sp[:, k] - sm[:, k]) * (e * sp[:, kp] - np.conj(e) * sm[:, kp])
     w = rho0[grids[:, 0]] * np.exp(-expo)
     for k in range(n):
-        w = w * K[grids[:, k + 1], grids[:, k]]
+        w = w * _interval_K(K, k)[grids[:, k + 1], grids[:, k]]
     rho = np.zeros(N, dtype=np.complex128)
     for o in range(N):
         rho[o] = w[grids[:, n] == o].sum()
@@ -77,7 +87,7 @@ def brute_tensor(s, K: np.ndarray, rho0: np.ndarray, G, dt: float, L: int, n: in
             expo += (sp[:, k] - sm[:, k]) * (e * sp[:, kp] - np.conj(e) * sm[:, kp])
     w = rho0[grids[:, 0]] * np.exp(-expo)
     for k in range(n):
-        w = w * K[grids[:, k + 1], grids[:, k]]
+        w = w * _interval_K(K, k)[grids[:, k + 1], grids[:, k]]
     flat = np.zeros(len(grids), dtype=np.int64)
     for j in range(L):
         flat += grids[:, n - L + 1 + j] * N ** j

@@ -24,7 +24,13 @@ __all__ = ["step_entry"]
 
 def step_entry(s, K: np.ndarray, eta: EtaClasses, L: int, n: int, m: int, o: int,
                a_in: np.ndarray) -> complex:
-    """A_n[m + N^{L-1} o] from the N input values a_in[i] = A_{n-1}[i + N m] (n >= L)."""
+    """A_n[m + N^{L-1} o] from the N input values a_in[i] = A_{n-1}[i + N m] (n >= L).
+
+    K is the propagator of step n, or a stack of per-interval propagators from
+    which step n takes K[min(n, len(K)) - 1]."""
+    K = np.asarray(K)
+    if K.ndim == 3:
+        K = K[min(n, len(K)) - 1]
     s = np.asarray(s, dtype=np.float64)
     M = len(s)
     N = M * M

@@ -30,6 +30,7 @@ class OracleInputs:
     omega_c: float = 1.0
     omega_tab: Optional[np.ndarray] = None
     J_tab: Optional[np.ndarray] = None
+    H_t: Optional[np.ndarray] = None          # (n_H, M, M): H over (t_k, t_{k+1}], k < n_H; then H_t[-1]
 
 
 def inputs_from(obj) -> OracleInputs:
@@ -37,7 +38,8 @@ def inputs_from(obj) -> OracleInputs:
     return OracleInputs(s=np.asarray(obj.s, float), H=np.asarray(obj.H, complex),
                         rho0=np.asarray(obj.rho0, complex), kT=float(obj.kT), dt=float(obj.dt),
                         L=int(obj.L), bath_kind=obj.bath_kind, xi=float(obj.xi),
-                        omega_c=float(obj.omega_c), omega_tab=obj.omega_tab, J_tab=obj.J_tab)
+                        omega_c=float(obj.omega_c), omega_tab=obj.omega_tab, J_tab=obj.J_tab,
+                        H_t=None if getattr(obj, "H_t", None) is None else np.asarray(obj.H_t, complex))
 
 
 def G_function(inp: OracleInputs):
@@ -58,11 +60,16 @@ def lineshape_grid(inp: OracleInputs) -> np.ndarray:
 
 
 def setup(inp: OracleInputs):
-    """(g grid, eta classes, U, K)."""
+    """(g grid, eta classes, U, K).  With a driven H(t), U and K are stacks with
+    one matrix per interval (t_k, t_{k+1}], k = 0..n_H-1."""
     g = lineshape_grid(inp)
     ec = eta_mod.eta_classes(g, inp.L)
-    U = system.propagator_U(inp.H, inp.dt)
-    K = system.liouville_K(U)
+    if inp.H_t is None:
+        U = system.propagator_U(inp.H, inp.dt)
+        K = system.liouville_K(U)
+    else:
+        U = np.array([system.propagator_U(h, inp.dt) for h in inp.H_t])
+        K = np.array([system.liouville_K(u) for u in U])
     return g, ec, U, K
 
 

@@ -40,7 +40,7 @@ def _load():
         build_oracle(force=False)
         lib = ctypes.CDLL(str(ORACLE_LIB))
         dp = ctypes.POINTER(ctypes.c_double)
-        lib.oracle_propagate.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int,
+        lib.oracle_propagate.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
                                          dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
         lib.oracle_propagate.restype = ctypes.c_int
         _lib = lib
@@ -58,18 +58,22 @@ def _ptr(a: np.ndarray):
 
 def tensor_rho(s, K: np.ndarray, rho0: np.ndarray, eta: EtaClasses, L: int, n_steps: int,
                threads: int = 0, return_step_seconds: bool = False):
-    """rho(t_k), k = 0..n_steps, as an array (n_steps+1, M, M), by the tensor recursion."""
+    """rho(t_k), k = 0..n_steps, as an array (n_steps+1, M, M), by the tensor recursion.
+
+    K is the N x N propagator, or a stack (n_K, N, N) with K[k] the propagator
+    over (t_k, t_{k+1}] (step n uses K[min(n, n_K) - 1])."""
     lib = _load()
     s = np.ascontiguousarray(np.asarray(s, dtype=np.float64))
     M = len(s)
     N = M * M
-    Kri = _ri(np.asarray(K).reshape(N, N))
+    Ks = np.asarray(K).reshape(-1, N, N)
+    Kri = _ri(Ks)
     r0 = _ri(np.asarray(rho0).reshape(N))
     arrs = [_ri([eta.self_interior]), _ri([eta.self_end]), _ri(eta.lag[:L + 1]),
             _ri(eta.init[:L + 1]), _ri(eta.fin[:L + 1]), _ri(eta.fin_init[:L + 1])]
     out = np.zeros(2 * N * (n_steps + 1), dtype=np.float64)
     secs = np.zeros(max(n_steps, 1), dtype=np.float64)
-    rc = lib.oracle_propagate(M, _ptr(s), _ptr(Kri), _ptr(r0), L, n_steps, *[_ptr(a) for a in arrs],
+    rc = lib.oracle_propagate(M, _ptr(s), _ptr(Kri), len(Ks), _ptr(r0), L, n_steps, *[_ptr(a) for a in arrs],
                               _ptr(out), _ptr(secs), int(threads))
     if rc != 0:
         raise RuntimeError(f"oracle_propagate failed with code {rc}")

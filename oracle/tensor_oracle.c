@@ -9,8 +9,13 @@
  * influence functional and the eta definitions; tensor-propagator scheme of
  * Makri and Makarov named in the Introduction):
  *
- *   rho(t_n)[o_n] = sum_{o_0..o_{n-1}} rho0[o_0] prod_{k<n} K[o_{k+1}, o_k]
+ *   rho(t_n)[o_n] = sum_{o_0..o_{n-1}} rho0[o_0] prod_{k<n} K_{k+1}[o_{k+1}, o_k]
  *                   prod_{k<=n} prod_{max(0,k-L) <= k' <= k} F_{eta(k,k';n)}(o_k, o_k')
+ *
+ * K_{k+1} is the bare propagator over (t_k, t_{k+1}]: the same matrix for
+ * every interval when H is constant, one matrix per interval for a driven H(t)
+ * (the Hamiltonian of the paper's model carries a time-dependent Rabi
+ * frequency, Sec. III); step n uses K_n.
  *
  * Because each influence factor couples points at most L apart, the partial
  * sum over all points older than n-L+1 can be carried as a tensor A over the
@@ -26,8 +31,9 @@
  *   fin[D]    final with interior, lag D    fin_init[n] final point n with point 0
  * Each array has L+1 complex entries (entry 0 unused), interleaved (re, im).
  *
- * Liouville index o = a*M + b for (s^+ = s[a], s^- = s[b]); K is N x N
- * row-major (K[o' * N + o]); rho0 and every output rho are N complex values.
+ * Liouville index o = a*M + b for (s^+ = s[a], s^- = s[b]); K holds n_K
+ * matrices of N x N, row-major (K[o' * N + o]), and step n uses matrix
+ * min(n, n_K) - 1; rho0 and every output rho are N complex values.
  *
  * Reductions: rho sums are accumulated with Neumaier compensation over fixed
  * chunks of output entries and the chunk partials are combined in order, so
@@ -87,13 +93,13 @@ static double now_s(void) {
  * step_seconds (optional, may be NULL): wall time of each step n = 1..n_steps
  * at index n-1.
  */
-int oracle_propagate(int M, const double *s, const double *K_ri, const double *rho0_ri,
+int oracle_propagate(int M, const double *s, const double *K_ri, int n_K, const double *rho0_ri,
                      int L, int n_steps,
                      const double *eta_self_int, const double *eta_self_end,
                      const double *eta_lag, const double *eta_init,
                      const double *eta_fin, const double *eta_fin_init,
                      double *rho_out, double *step_seconds, int n_threads) {
-    if (M < 1 || M > 8 || L < 1 || n_steps < 0) return 1;
+    if (M < 1 || M > 8 || L < 1 || n_steps < 0 || n_K < 1) return 1;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #else
@@ -102,7 +108,7 @@ int oracle_propagate(int M, const double *s, const double *K_ri, const double *r
     const int N = M * M;
     const size_t NN = (size_t)N * N;
 
-    cplx *K = malloc(sizeof(cplx) * NN);
+    cplx *K = malloc(sizeof(cplx) * NN * n_K);
     cplx *self_int = malloc(sizeof(cplx) * N), *self_end = malloc(sizeof(cplx) * N);
     cplx *T_lag = malloc(sizeof(cplx) * NN * (L + 1));
     cplx *T_init = malloc(sizeof(cplx) * NN * (L + 1));
@@ -118,7 +124,7 @@ int oracle_propagate(int M, const double *s, const double *K_ri, const double *r
         free(T_fin_init); free(A); free(B); free(part);
         return 2;
     }
-    for (size_t k = 0; k < NN; ++k) K[k] = ld(K_ri, k);
+    for (size_t k = 0; k < NN * n_K; ++k) K[k] = ld(K_ri, k);
     const cplx e_si = ld(eta_self_int, 0), e_se = ld(eta_self_end, 0);
     for (int o = 0; o < N; ++o) {
         self_int[o] = influence(s, M, o, o, e_si);
@@ -146,6 +152,7 @@ int oracle_propagate(int M, const double *s, const double *K_ri, const double *r
         const size_t in_count = ipow(N, ax);
         const size_t upper_count = in_count / N;   /* points p_lo+1 .. n-1 */
         const size_t out_count = sum_out ? in_count : in_count * N;
+        const cplx *Kn = K + NN * (size_t)(n < n_K ? n - 1 : n_K - 1);   /* propagator of step n */
         /* class tables of predecessor point k' for the new point n */
 #define T_INT(kp) ((kp) == 0 ? T_init + NN * n : T_lag + NN * (n - (kp)))
 #define T_FIN(kp) ((kp) == 0 ? T_fin_init + NN * n : T_fin + NN * (n - (kp)))
@@ -174,16 +181,16 @@ int oracle_propagate(int M, const double *s, const double *K_ri, const double *r
                     newest = d;
                 }
                 if (ax >= 2) {          /* bare propagator from o_{n-1} (an upper point) */
-                    P *= K[on * N + newest];
-                    Pf *= K[on * N + newest];
+                    P *= Kn[on * N + newest];
+                    Pf *= Kn[on * N + newest];
                 }
                 cplx acc = 0, accf = 0;
                 for (int i = 0; i < N; ++i) {
                     const cplx a = A[(size_t)i + (size_t)N * up];
                     cplx f = F0[on * N + i], ff = F0f[on * N + i];
                     if (ax == 1) {      /* o_{n-1} is the digit-0 point itself */
-                        f *= K[on * N + i];
-                        ff *= K[on * N + i];
+                        f *= Kn[on * N + i];
+                        ff *= Kn[on * N + i];
                     }
                     accf += ff * a;
                     if (sum_out) acc += f * a;

@@ -20,6 +20,8 @@ its own model system is Sec. III):
 * ``paper_quantum_dot`` the paper's Sec. III model system (super-Ohmic J with
   a Gaussian cutoff, passed as a table), M=2
 * ``serving_requests`` a seeded Poisson trace of mixed requests
+* ``paper_quantum_dot_pulse`` / ``pulse_area_sweep`` the Sec. III model driven
+  by a Gaussian pulse of a given area (the quantity experiments sweep, Sec. IV)
 """
 from __future__ import annotations
 
@@ -31,7 +33,7 @@ import numpy as np
 __all__ = [
     "Workload", "spin_boson", "spin_boson_l7", "spin_boson_l12", "three_site_l8",
     "spin_boson_l15", "paper_quantum_dot", "serving_requests", "random_hermitian",
-    "ALL_FIXED",
+    "gaussian_pulse", "paper_quantum_dot_pulse", "pulse_area_sweep", "ALL_FIXED",
 ]
 
 
@@ -54,6 +56,9 @@ class Workload:
     J_tab: Optional[np.ndarray] = None       # J at the nodes (>= 0)
     dtype: str = "c128"                # "c128" | "c64" | "c64f64"
     meta: dict = field(default_factory=dict)
+    # driven system: H_t[k] (M x M) is the Hamiltonian over (t_k, t_{k+1}] for
+    # k < len(H_t), the last one after that; None: H at every step
+    H_t: Optional[np.ndarray] = None
 
     @property
     def N(self) -> int:
@@ -136,6 +141,35 @@ def paper_quantum_dot(*, L: int = 7, n_steps: int = 100, dt: float = 0.25,
                     rho0=_pm_basis_rho0(2, 0), kT=kT, dt=dt, L=L, n_steps=n_steps,
                     bath_kind="table", omega_tab=w, J_tab=J,
                     meta=dict(A=A, omega_c=wc, T_K=25.0, Omega=W))
+
+
+def gaussian_pulse(area: float, t0: float, sigma: float, t: np.ndarray) -> np.ndarray:
+    """Rabi frequency of a Gaussian pulse with the given area (integral over t)."""
+    return area / (sigma * np.sqrt(2.0 * np.pi)) * np.exp(-0.5 * ((t - t0) / sigma) ** 2)
+
+
+def paper_quantum_dot_pulse(area: float, *, L: int = 7, n_steps: int = 100, dt: float = 0.25,
+                            t0: float = 6.0, sigma: float = 1.5, n_tab: int = 4000,
+                            omega_max: float = 13.2) -> Workload:
+    """The Sec. III model with Omega(t) a Gaussian pulse of the given area
+    (t0, sigma in ps): H_t[k] = (1/2) Omega(t_k + dt/2) sigma_x over (t_k, t_{k+1}].
+    The pulse shape is not given in the paper; it is a parameter of this workload."""
+    w = paper_quantum_dot(L=L, n_steps=n_steps, dt=dt, n_tab=n_tab, omega_max=omega_max)
+    om = gaussian_pulse(area, t0, sigma, dt * (np.arange(n_steps) + 0.5))
+    H_t = np.zeros((n_steps, 2, 2), dtype=np.complex128)
+    H_t[:, 0, 1] = H_t[:, 1, 0] = 0.5 * om
+    return w.with_(name=f"paper_quantum_dot_pulse_{area:.4g}", H=H_t[0].copy(), H_t=H_t,
+                   meta=dict(w.meta, area=area, t0=t0, sigma=sigma))
+
+
+def pulse_area_sweep(n: int = 32, max_area: float = 4.0 * np.pi, **kw) -> list:
+    """Requests that differ only in pulse area (0 .. max_area), all arriving at t = 0."""
+    out = []
+    for k, a in enumerate(np.linspace(0.0, max_area, n)):
+        w = paper_quantum_dot_pulse(float(a), **kw)
+        w.meta.update(arrival_s=0.0, index=k)
+        out.append(w)
+    return out
 
 
 def random_hermitian(rng: np.random.Generator, M: int) -> np.ndarray:

@@ -155,3 +155,66 @@ def test_thread_count_does_not_change_bits():
     r1 = tensor.tensor_rho(w.s, K, w.rho0, ec, w.L, 12, threads=1)
     r4 = tensor.tensor_rho(w.s, K, w.rho0, ec, w.L, 12, threads=4)
     assert np.array_equal(r1, r4)
+
+
+
+# ---- driven systems: one Hamiltonian per interval (t_k, t_{k+1}]
+
+def test_driven_no_bath_is_ordered_unitary_evolution():
+    rng = np.random.default_rng(31)
+    for M, L in ((2, 3), (3, 2)):
+        n = 14
+        H_t = np.array([W.random_hermitian(rng, M) for _ in range(9)])   # shorter than the run
+        rho0 = np.zeros((M, M), complex)
+        rho0[0, 0], rho0[M - 1, M - 1], rho0[0, M - 1], rho0[M - 1, 0] = 0.6, 0.4, 0.2j, -0.2j
+        w = W.three_site_l8().with_(M=M, s=np.linspace(-1, 1, M), H=H_t[0], H_t=H_t, rho0=rho0, xi=0.0, L=L)
+        rho = run.oracle_run(w, n)
+        r = rho0.copy()
+        for k in range(n + 1):
+            assert np.abs(rho[k] - r).max() <= 1e-14, (M, k)
+            U = system.propagator_U(H_t[min(k, len(H_t) - 1)], w.dt)
+            r = U @ r @ U.conj().T
+
+
+def test_driven_pulse_area_closed_form():
+    # without a bath, H(t) = Omega(t) sigma_x / 2 commutes with itself at all times,
+    # so rho_11 after the pulse is sin^2(A/2), A the discrete area sum_k Omega_k dt
+    for area in (0.0, 0.5 * np.pi, np.pi, 2.3, 2 * np.pi):
+        w = W.paper_quantum_dot_pulse(area, L=3, n_steps=60).with_(bath_kind="ohmic", xi=0.0,
+                                                                     omega_tab=None, J_tab=None)
+        rho = run.oracle_run(w, 60)
+        a_disc = 2.0 * np.real(w.H_t[:, 0, 1]).sum() * w.dt
+        assert abs(rho[-1, 1, 1].real - np.sin(a_disc / 2) ** 2) <= 1e-13, area
+        assert abs(a_disc - area) <= 1e-4 * max(area, 1)     # the pulse starts at t0 - 4 sigma = 0
+
+
+def test_driven_tensor_recursion_equals_brute_force():
+    rng = np.random.default_rng(37)
+    base = W.spin_boson_l7()
+    H_t = np.array([W.random_hermitian(rng, 2) for _ in range(3)])
+    inp = _inputs(base, H_t=H_t, xi=0.3)
+    Gf = run.G_function(inp)
+    for L in range(1, 5):
+        inp.L = L
+        _, ec, _, K = run.setup(inp)
+        assert K.shape == (3, 4, 4)
+        rho_t = tensor.tensor_rho(inp.s, K, inp.rho0, ec, L, 5)
+        for n in range(6):
+            rb = brute.brute_rho(inp.s, K, inp.rho0, Gf, inp.dt, L, n)
+            assert np.abs(rb - rho_t[n]).max() <= 1e-14, (L, n)
+
+
+def test_driven_step_entry_equals_brute_force_tensor():
+    rng = np.random.default_rng(41)
+    H_t = np.array([W.random_hermitian(rng, 2) for _ in range(6)])
+    inp = _inputs(W.spin_boson_l7(), H_t=H_t, L=2)
+    Gf = run.G_function(inp)
+    _, ec, _, K = run.setup(inp)
+    N = 4
+    for n in [3, 4, 5]:
+        a_prev = brute.brute_tensor(inp.s, K, inp.rho0, Gf, inp.dt, inp.L, n - 1)
+        a_now = brute.brute_tensor(inp.s, K, inp.rho0, Gf, inp.dt, inp.L, n)
+        for m in range(N ** (inp.L - 1)):
+            for o in range(N):
+                got = entry.step_entry(inp.s, K, ec, inp.L, n, m, o, a_prev[N * m:N * m + N])
+                assert abs(got - a_now[m + N ** (inp.L - 1) * o]) <= 1e-15
