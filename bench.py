@@ -6,11 +6,12 @@ default, rho(t_n) extracted at every step ('allPoints').  Inputs are
 synthetic (seeded parameters, no dataset).
 
 A timed "step" is one full-window propagation step.  For M = 2 the library
-fuses two consecutive steps into one kernel launch: it reads the tensor
-once, keeps the intermediate tensor in registers, writes the tensor two steps
-later once, and produces per-block partial sums of rho at both steps in the
-same pass; a small finalize kernel on a side stream sums them.  So one launch
-moves 2 * N^L * sizeof(complex) bytes and covers two steps.  The growth steps (n < L) and the device setup run first and
+fuses consecutive steps into one kernel launch (three at complex128 from
+L = 14, else two): it reads the tensor once, keeps the intermediate tensors
+in registers, writes the tensor of the group's last step once, and produces
+per-block partial sums of rho at every step of the group in the same pass; a
+small finalize kernel on a side stream sums them.  So one launch moves
+2 * N^L * sizeof(complex) bytes and covers two or three steps.  The growth steps (n < L) and the device setup run first and
 are reported separately.  Three precisions run on the same workload:
 complex128 (the reported `value`), the complex64 tier with FP32 arithmetic
 (`fp32_tier`), and complex64 storage with FP64 arithmetic
@@ -40,10 +41,15 @@ with the tabulated super-Ohmic J, memory length dk = 2..15, 989 main-phase
 steps, rho at every point) and reports the main-phase wall time per dk.
 `serving` / `serving_fifo` serve the first requests of the seeded trace with
 shortest-work-first and arrival-order admission.
+`pulse_sweep` serves the paper's use case of many runs that differ only in
+the pulse area: its Sec. III quantum dot driven by a Gaussian pulse (a
+Hamiltonian per time interval, so each request recomputes its propagator
+tables every step), 32 areas from 0 to 4 pi, rho at the last step only, and
+reports the makespan, latency and the final excited-state population per area.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tiers c128,c64,c64f64]
-                       [--serve-requests R] [--no-table1] [--no-copy-ceiling]
-                       [--no-cpu-baseline]
+                       [--serve-requests R] [--no-table1] [--no-pulse-sweep]
+                       [--no-copy-ceiling] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -189,6 +195,28 @@ def serve_trace(n_requests: int, policy: str = "sjf", chunk_ms=8.0, chunk_steps:
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
 
 
+def pulse_sweep(n: int = 32, L: int = 11, n_steps: int = 200, dtype: str = "c128"):
+    """The pulse-area sweep through the server: n driven requests, all at t = 0,
+    rho at the last step only ('justFinalPoint')."""
+    import numpy as np
+    from paper_1205_6872_amd import workloads as W
+    from paper_1205_6872_amd.serve import Server, summarize
+    reqs = [w.with_(dtype=dtype, meta=dict(w.meta, final_only=True))
+            for w in W.pulse_area_sweep(n=n, L=L, n_steps=n_steps)]
+    log(f"bench: pulse-area sweep, {n} driven requests, L = {L}, {n_steps} steps, rho at the last step")
+    res = Server(max_active=8, chunk_steps=64).run(reqs, realtime=False)
+    s = summarize(res)
+    w0 = reqs[0]
+    s.update({"workload": (f"paper_quantum_dot_pulse: Sec. III model (tabulated J), Gaussian pulse "
+                           f"t0 = {w0.meta['t0']} ps, sigma = {w0.meta['sigma']} ps, dt = {w0.dt} ps, "
+                           f"L = {L}, {n_steps} steps, {dtype}"),
+              "areas_over_pi": [round(w.meta["area"] / np.pi, 4) for w in reqs],
+              "excited_population": [round(float(r.rho[-1, 1, 1].real), 6) for r in res],
+              "max_trace_err": float(max(abs(np.trace(r.rho[-1]) - 1) for r in res)),
+              "max_active": 8, "rho_every_step": False})
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+
+
 def cpu_baseline(w, n_main: int = 2):
     """Oracle on the host: growth to L, then n_main full-window steps (timed)."""
     import numpy as np
@@ -216,6 +244,7 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=64, help="0 skips the serving run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-table1", action="store_true", help="skip the paper's Table 1 sweep")
+    ap.add_argument("--no-pulse-sweep", action="store_true", help="skip the pulse-area sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
@@ -298,6 +327,8 @@ def main() -> int:
         log("bench: the paper's Table 1 sweep (its model system, dk = 2..15, 989 main steps, rho at every point)")
         out["paper_table1"] = {"workload": "paper_quantum_dot (Sec. III model, tabulated J), dt = 0.25 ps, complex128",
                                "rows": paper_table1()}
+    if not args.no_pulse_sweep:
+        out["pulse_sweep"] = pulse_sweep()
     if not args.no_cpu_baseline:
         log("bench: cpu_baseline (oracle on the host)")
         cb = cpu_baseline(w.with_(dtype="c128"))

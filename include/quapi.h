@@ -95,6 +95,14 @@ typedef struct {
     double dt;                /* > 0 */
     int dk_max;               /* memory length L = Delta k_max, 1 <= L <= 30 */
     int dtype;                /* quapi_dtype */
+    /* Driven system (optional; the model's Rabi frequency may depend on time,
+     * Sec. III): n_H Hamiltonians, each M*M complex and Hermitian like H.  The
+     * bare propagator of step k (interval (t_{k-1}, t_k]) is exp(-i H_t[k-1] dt)
+     * for k <= n_H and uses H_t[n_H-1] after that.  NULL / n_H = 0: H for every
+     * step.  A driven context recomputes its propagator tables before every
+     * step and runs one step per launch. */
+    const double *H_t;
+    int n_H;                  /* 0 <= n_H <= 1,000,000 */
 } quapi_params;
 
 /* Device bytes that quapi_create needs for these parameters (the two
@@ -181,7 +189,7 @@ quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps);
 
 /* Choose the full-window steps per launch: 1, 2 (N = 4, L >= 2), 3 (N = 4,
  * L >= 3), or 0 for the default (3 at complex128 from L = 14, else 2 where
- * available, else 1).  Every choice gives the same results to within rounding
+ * available, else 1; always 1 for a driven context).  Every choice gives the same results to within rounding
  * (the fused kernels apply the same factors in another order); use it to pin
  * the kernel, e.g. in tests.  It takes effect from the next call.
  * Errors: QUAPI_ERR_INVALID for an unavailable width; QUAPI_ERR_STATE while

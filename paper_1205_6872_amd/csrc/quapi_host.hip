@@ -191,6 +191,24 @@ void plan_panels(const quapi_params &p, double t_max, std::vector<double> &pa,
 }
 
 // ------------------------------------------------------------- validation
+// Empty if H (M x M complex, interleaved) is finite and Hermitian to 1e-12 of
+// its largest entry, else what is wrong.
+std::string hermitian_error(const double *H, int M, const char *name) {
+    double hmax = 0.0;
+    for (int i = 0; i < 2 * M * M; ++i) {
+        if (!std::isfinite(H[i])) return std::string(name) + " has a non-finite entry";
+        hmax = std::max(hmax, std::fabs(H[i]));
+    }
+    for (int a = 0; a < M; ++a)
+        for (int b = 0; b < M; ++b) {
+            const double re = H[2 * (a * M + b)], im = H[2 * (a * M + b) + 1];
+            const double re2 = H[2 * (b * M + a)], im2 = H[2 * (b * M + a) + 1];
+            if (std::fabs(re - re2) > 1e-12 * hmax || std::fabs(im + im2) > 1e-12 * hmax)
+                return std::string(name) + " is not Hermitian";
+        }
+    return "";
+}
+
 std::string validate(const quapi_params *p) {
     char buf[256];
     if (!p) return "params is NULL";
@@ -202,19 +220,19 @@ std::string validate(const quapi_params *p) {
     const int M = p->M;
     for (int i = 0; i < M; ++i)
         if (!std::isfinite(p->s[i])) return "s has a non-finite entry";
-    double hmax = 0.0;
-    for (int i = 0; i < 2 * M * M; ++i) {
-        if (!std::isfinite(p->H[i])) return "H has a non-finite entry";
+    for (int i = 0; i < 2 * M * M; ++i)
         if (!std::isfinite(p->rho0[i])) return "rho0 has a non-finite entry";
-        hmax = std::max(hmax, std::fabs(p->H[i]));
-    }
-    for (int a = 0; a < M; ++a)
-        for (int b = 0; b < M; ++b) {
-            const double re = p->H[2 * (a * M + b)], im = p->H[2 * (a * M + b) + 1];
-            const double re2 = p->H[2 * (b * M + a)], im2 = p->H[2 * (b * M + a) + 1];
-            if (std::fabs(re - re2) > 1e-12 * hmax || std::fabs(im + im2) > 1e-12 * hmax)
-                return "H is not Hermitian";
+    std::string herr = hermitian_error(p->H, M, "H");
+    if (!herr.empty()) return herr;
+    if (p->n_H < 0 || p->n_H > 1000000) return "n_H must be in 0..1000000";
+    if (p->n_H > 0 && !p->H_t) return "H_t must be non-NULL when n_H > 0";
+    for (int k = 0; k < p->n_H; ++k) {
+        herr = hermitian_error(p->H_t + (size_t)2 * M * M * k, M, "an H_t matrix");
+        if (!herr.empty()) {
+            snprintf(buf, sizeof buf, "%s (index %d)", herr.c_str(), k);
+            return buf;
         }
+    }
     if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return "dt must be finite and > 0";
     if (p->dk_max < 1 || p->dk_max > kMaxL) {
         snprintf(buf, sizeof buf, "dk_max = %d outside 1..%d", p->dk_max, kMaxL);
@@ -248,7 +266,7 @@ std::string validate(const quapi_params *p) {
 // ------------------------------------------------------------------ layout
 struct Layout {
     size_t a_bytes;                  // one tensor buffer
-    size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_rho0;
+    size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_Ht, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
     size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_pairs, off_sink;
     size_t total;
@@ -289,6 +307,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_U = take((size_t)M * M * 16);
     l.off_s = take((size_t)M * 8);
     l.off_H = take((size_t)M * M * 16);
+    l.off_Ht = take((size_t)std::max(p.n_H, 0) * M * M * 16);
     l.off_rho0 = take((size_t)N * 16);
     l.off_pa = take((size_t)n_panels * 8);
     l.off_ph = take((size_t)n_panels * 8);
@@ -350,6 +369,10 @@ struct quapi_ctx {
     double2 *partials[kSlots] = {};
     double2 *stage = nullptr, *plan = nullptr, *plan2 = nullptr, *pairs = nullptr;
     void *coef = nullptr;         // fused-step coefficients (compute precision)
+    int n_H = 0;                  // driven: per-interval Hamiltonians on the device
+    const double2 *Ht_d = nullptr;
+    std::vector<double> Ht_h;
+    TablesArgs drive_ta{};        // the setup tables call, reused per step with k_only
     float2 *bank_f = nullptr;     // the bank rounded to complex64 (FP32 arithmetic only)
     RhoSink *sink = nullptr;
     // captured full-window steps, [without / with rho]: graph1 two single steps
@@ -966,7 +989,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
     HIP_TRY(c, launch_set_sink(c->sink, dev_out ? dev_out + (size_t)written * N : c->stage, c->stream));
     const size_t entries = (size_t)ipow_ll(N, L);
     const bool fused = c->fuse == 2;
-    const bool graphs = !c->timing && !c->graph_failed && entries <= kGraphMaxEntries;
+    const bool graphs = !c->timing && !c->graph_failed && entries <= kGraphMaxEntries && c->n_H == 0;
     const int first = c->step + 1, last = c->step + n_steps;
     for (int n = first; n <= last; ++n) {
         const bool s0 = is_sel(n, si);
@@ -1047,6 +1070,16 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
         if (!dev_out && s0 && staged + 1 > kRhoStage) {
             st = flush();
             if (st != QUAPI_OK) return st;
+        }
+        if (c->n_H > 0) {
+            // driven: the propagator tables of step n, and the plan tables
+            // built from them, before the step
+            TablesArgs ta = c->drive_ta;
+            ta.H = c->Ht_d + (size_t)std::min(n - 1, c->n_H - 1) * c->M * c->M;
+            ta.k_only = 1;
+            hipError_t e = launch_tables(ta, c->stream);
+            if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "tables launch: %s", hipGetErrorString(e));
+            c->plan_ready = false;
         }
         st = enqueue_step(c, n, s0);
         if (st != QUAPI_OK) return st;
@@ -1202,7 +1235,9 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->plan2 = (double2 *)(w + lay.off_plan2);
     c->plan3 = (double2 *)(w + lay.off_plan3);
     c->coef3 = w + lay.off_coef3;
-    c->fuse = fusion_width(N, p->dk_max, c->prec);
+    c->n_H = p->n_H;
+    c->Ht_d = (const double2 *)(w + lay.off_Ht);
+    c->fuse = c->n_H > 0 ? 1 : fusion_width(N, p->dk_max, c->prec);
     c->coef = w + lay.off_coef;
     c->stage = (double2 *)(w + lay.off_stage);
     c->pairs = (double2 *)(w + lay.off_pairs);
@@ -1211,6 +1246,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
 
     c->s_h.assign(p->s, p->s + M);
     c->H_h.assign(p->H, p->H + 2 * M * M);
+    if (p->n_H > 0) c->Ht_h.assign(p->H_t, p->H_t + (size_t)2 * M * M * p->n_H);
     c->rho0_h.assign(p->rho0, p->rho0 + 2 * N);
     c->pa_h = std::move(pa);
     c->ph_h = std::move(ph);
@@ -1230,6 +1266,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = up(lay.off_s, c->s_h.data(), (size_t)M * 8);
     if (e == hipSuccess) e = up(lay.off_H, c->H_h.data(), (size_t)M * M * 16);
+    if (e == hipSuccess && c->n_H > 0) e = up(lay.off_Ht, c->Ht_h.data(), c->Ht_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_rho0, c->rho0_h.data(), (size_t)N * 16);
     if (e == hipSuccess) e = up(lay.off_pa, c->pa_h.data(), c->pa_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_ph, c->ph_h.data(), c->ph_h.size() * 8);
@@ -1275,6 +1312,8 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     ta.bank = c->bank;
     ta.bank_f = c->bank_f;
     ta.k_trace_exact = c->prec == kPrecC64;            // FP32 arithmetic: keep the trace exact per step
+    c->drive_ta = ta;
+    if (c->n_H > 0) ta.H = c->Ht_d;                    // driven: step 1 uses the first matrix
     if (e == hipSuccess) e = launch_tables(ta, c->stream);
     if (e == hipSuccess)
         e = launch_init_tensor(N, c->prec, c->rho0_d, c->bank, BankLayout{L}.self_end(), c->A[0], c->stream);
@@ -1330,7 +1369,9 @@ quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps) {
 quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
     if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
     const int N = ctx->N, L = ctx->L;
-    if (steps == 0) steps = fusion_width(N, L, ctx->prec);
+    if (steps == 0) steps = ctx->n_H > 0 ? 1 : fusion_width(N, L, ctx->prec);
+    if (ctx->n_H > 0 && steps != 1)
+        return fail(ctx, QUAPI_ERR_INVALID, "a driven context runs one step per launch");
     const bool ok = steps == 1 || (steps == 2 && fused_ok(N, L)) || (steps == 3 && triple_ok(N, L));
     if (!ok)
         return fail(ctx, QUAPI_ERR_INVALID, "%d fused steps unavailable at N = %d, L = %d (1 always; 2: N = 4, L >= 2; "

@@ -161,6 +161,7 @@ struct TablesArgs {
     double2 *bank;              // out: BankLayout{L}.count() tables
     float2 *bank_f;             // out (if not NULL): the same tables rounded to complex64
     int k_trace_exact;          // K rows (a, a) chosen on the FP32 grid with exact column sums
+    int k_only;                 // rewrite only the tables that carry K (driven H: per step); eta, U untouched
 };
 
 // Kernel launchers (quapi_kernels.hip).  They return the launch status.

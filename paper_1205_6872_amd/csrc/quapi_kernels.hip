@@ -263,10 +263,10 @@ __global__ void __launch_bounds__(kBlock) tables_kernel(const TablesArgs a) {
             }
         }
         sEta[c] = v;
-        a.eta[c] = v;
+        if (!a.k_only) a.eta[c] = v;
     }
     __syncthreads();
-    if (t < M * M) a.U[t] = sU[t];
+    if (t < M * M && !a.k_only) a.U[t] = sU[t];
     if (a.k_trace_exact && t < N) {
         double2 col[kMaxM];
         trace_exact_column(sU, M, t / M, t % M, col);
@@ -280,8 +280,15 @@ __global__ void __launch_bounds__(kBlock) tables_kernel(const TablesArgs a) {
     auto fin = [&](int D) { return sEta[1 + 2 * L + D]; };
     auto fin_init = [&](int n) { return sEta[1 + 3 * L + n]; };
     const int n_tab = B.count();
+    // the tables that carry K: K itself, K folded into the lag-1 classes, and
+    // the oldest-point tables when L = 1 (their oldest point is the previous one)
+    auto carries_k = [&](int tb) {
+        return tb == B.K() || tb == B.k_lag1() || tb == B.k_init1() || tb == B.k_fin1() ||
+               tb == B.k_fin_init1() || (L == 1 && tb >= B.old_main() && tb <= B.oldf_first());
+    };
     for (int idx = t; idx < n_tab * NN; idx += kBlock) {
         const int tb = idx / NN, o = (idx / N) % N, p = idx % N;
+        if (a.k_only && !carries_k(tb)) continue;
         const int oa = o / M, ob = o % M, pc = p / M, pd = p % M;
         const double2 Kop = [&] {
             if (a.k_trace_exact && oa == ob) return sKd[oa * N + p];

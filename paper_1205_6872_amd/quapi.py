@@ -46,7 +46,7 @@ class Bath(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("s", _DP), ("H", _DP), ("rho0", _DP), ("bath", Bath),
                 ("kT", ctypes.c_double), ("dt", ctypes.c_double), ("dk_max", ctypes.c_int),
-                ("dtype", ctypes.c_int)]
+                ("dtype", ctypes.c_int), ("H_t", _DP), ("n_H", ctypes.c_int)]
 
 
 class Timing(ctypes.Structure):
@@ -124,7 +124,7 @@ class _ParamsHolder:
 
     def __init__(self, M: int, s, H, rho0, kT: float, dt: float, L: int, dtype: str = "c128",
                  bath_kind: str = "ohmic", xi: float = 0.0, omega_c: float = 1.0,
-                 omega_tab=None, J_tab=None):
+                 omega_tab=None, J_tab=None, H_t=None):
         self.s = _f64(s)
         self.H = np.ascontiguousarray(_c128_ri(H))
         self.rho0 = np.ascontiguousarray(_c128_ri(rho0))
@@ -133,14 +133,16 @@ class _ParamsHolder:
         kind = {"ohmic": BATH_OHMIC, "table": BATH_TABLE}[bath_kind]
         n_tab = int(len(self.omega)) if self.omega is not None else 0
         bath = Bath(kind, float(xi), float(omega_c), _ptr(self.omega), _ptr(self.J), n_tab)
+        self.H_t = None if H_t is None else np.ascontiguousarray(_c128_ri(np.asarray(H_t).reshape(-1, M, M)))
+        n_H = 0 if H_t is None else int(np.asarray(H_t).reshape(-1, M, M).shape[0])
         self.p = Params(int(M), _ptr(self.s), _ptr(self.H), _ptr(self.rho0), bath, float(kT), float(dt),
-                        int(L), DTYPES[dtype])
+                        int(L), DTYPES[dtype], _ptr(self.H_t), n_H)
 
     @classmethod
     def from_workload(cls, w, **over):
         kw = dict(M=w.M, s=w.s, H=w.H, rho0=w.rho0, kT=w.kT, dt=w.dt, L=w.L, dtype=w.dtype,
                   bath_kind=w.bath_kind, xi=w.xi, omega_c=w.omega_c, omega_tab=w.omega_tab,
-                  J_tab=w.J_tab)
+                  J_tab=w.J_tab, H_t=getattr(w, "H_t", None))
         kw.update(over)
         return cls(**kw)
 

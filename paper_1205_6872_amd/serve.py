@@ -23,8 +23,11 @@ The work estimate is the HBM traffic of the steps at a nominal rate:
 2 N^min(n+1, L) sizeof(complex) bytes per step n at 4 TB/s, and at least
 10 microseconds per step (launch-bound small tensors).
 
-Every request returns rho(t_k) for k = 0..n_steps ('allPoints', Sec. IV of
-the paper).  The kernels are deterministic and each request has its own
+A request returns rho(t_k) for k = 0..n_steps ('allPoints', Sec. IV of the
+paper), or with ``meta['final_only']`` just rho(t_0) and rho(t_n_steps)
+('justFinalPoint'), which skips the rho reduction of every other step.  A
+request with a Hamiltonian per interval (``H_t``, a driven system) runs one
+step per launch, like any driven context.  The kernels are deterministic and each request has its own
 context, so a request's result does not depend on what else is running.
 """
 from __future__ import annotations
@@ -93,6 +96,7 @@ class _Active:
     fp: int
     admit_s: float
     fuse: int = 1
+    final_only: bool = False
     enqueued: int = 0
     events: deque = field(default_factory=deque)
 
@@ -126,10 +130,12 @@ class Server:
         p = Q.params_from(w)
         stream = self.streams[slot]
         ctx = Q.create_in_torch(p, stream=stream, device=self.device)
-        rho_dev = torch.empty((w.n_steps + 1, w.N, 2), dtype=torch.float64, device=self.device)
+        final_only = bool(w.meta.get("final_only", False))
+        rows = 2 if final_only else w.n_steps + 1
+        rho_dev = torch.empty((rows, w.N, 2), dtype=torch.float64, device=self.device)
         ctx.propagate_async(0, [0], rho_dev.data_ptr())          # rho(t_0)
         return _Active(w=w, index=index, ctx=ctx, stream=stream, rho_dev=rho_dev, slot=slot,
-                       fp=Q.footprint(p), admit_s=now, fuse=ctx.fused_steps())
+                       fp=Q.footprint(p), admit_s=now, fuse=ctx.fused_steps(), final_only=final_only)
 
     def run(self, requests, realtime: bool = True) -> list[RequestResult]:
         """Serve the requests (each with meta['arrival_s']); returns results in index order."""
@@ -192,8 +198,12 @@ class Server:
                         if end <= a.enqueued:
                             end = min(a.enqueued + a.fuse, a.w.n_steps)
                     k = end - a.enqueued
-                    off = (a.enqueued + 1) * a.w.N * 16
-                    a.ctx.propagate_async(k, None, a.rho_dev.data_ptr() + off)
+                    if a.final_only:                             # rho only at the last step
+                        sel = [a.w.n_steps] if end == a.w.n_steps else []
+                        a.ctx.propagate_async(k, sel, a.rho_dev.data_ptr() + a.w.N * 16)
+                    else:
+                        off = (a.enqueued + 1) * a.w.N * 16
+                        a.ctx.propagate_async(k, None, a.rho_dev.data_ptr() + off)
                     a.enqueued += k
                     ev = torch.cuda.Event()
                     ev.record(a.stream)
@@ -214,7 +224,7 @@ class Server:
                     results.append(RequestResult(
                         index=a.index, name=w.name, M=w.M, L=w.L, dtype=w.dtype, n_steps=w.n_steps,
                         arrival_s=(w.meta.get("arrival_s", 0.0) if realtime else 0.0), admit_s=a.admit_s,
-                        finish_s=finish, rho=rho.view(np.complex128).reshape(w.n_steps + 1, w.M, w.M),
+                        finish_s=finish, rho=rho.view(np.complex128).reshape(-1, w.M, w.M),
                         entries=work_entries(w.N, w.L, w.n_steps)))
                     progressed = True
                     if self.progress and len(results) % 16 == 0:

@@ -84,6 +84,45 @@ def test_invalid_parameters_are_rejected(over, needle):
     assert needle in str(ei.value)
 
 
+def _pulse(n_H=5):
+    rng = np.random.default_rng(3)
+    return np.stack([W.random_hermitian(rng, 2) for _ in range(n_H)])
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda H: H.__setitem__((2, 0, 1), 1.0 + 0.5j), "an H_t matrix is not Hermitian (index 2)"),
+    (lambda H: H.__setitem__((4, 1, 1), np.nan), "an H_t matrix has a non-finite entry (index 4)"),
+    (lambda H: H.__setitem__((0, 0, 0), 1j), "an H_t matrix is not Hermitian (index 0)"),
+])
+def test_invalid_driven_hamiltonians_are_rejected(mutate, needle):
+    H_t = _pulse()
+    mutate(H_t)
+    with pytest.raises(Q.QuapiError) as ei:
+        Q.footprint(_p(H_t=H_t))
+    assert ei.value.status == Q.ERR_INVALID
+    assert needle in str(ei.value)
+
+
+def test_driven_count_and_pointer_are_checked():
+    ph = _p(H_t=_pulse())
+    ph.p.H_t = None                                   # n_H = 5 with no array
+    with pytest.raises(Q.QuapiError) as ei:
+        Q.footprint(ph)
+    assert "H_t must be non-NULL" in str(ei.value)
+    ph = _p()
+    ph.p.n_H = -1
+    with pytest.raises(Q.QuapiError) as ei:
+        Q.footprint(ph)
+    assert "n_H" in str(ei.value)
+
+
+def test_footprint_holds_the_driven_hamiltonians():
+    base = Q.footprint(_p())
+    n_H = 10000
+    fp = Q.footprint(_p(H_t=np.broadcast_to(np.eye(2, dtype=complex), (n_H, 2, 2))))
+    assert n_H * 4 * 16 <= fp - base <= n_H * 4 * 16 + 512
+
+
 def test_memory_cap_gives_nomem_before_touching_a_device(monkeypatch):
     monkeypatch.setenv("QUAPI_FAKE_HBM_BYTES", "100000")
     with pytest.raises(Q.QuapiError) as ei:

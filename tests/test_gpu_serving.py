@@ -68,3 +68,25 @@ def test_sjf_admits_the_shorter_request_first_with_unchanged_results():
     assert admitted == order, (admitted, order)
     for w, r in zip(reqs, res):
         assert np.array_equal(r.rho, _alone(w))
+
+
+def test_pulse_area_sweep_final_point_only():
+    """Driven requests (a Hamiltonian per interval) served with rho at the last
+    step only: each final rho equals the one a context computes alone, and at
+    complex64 precision too (mixed batch)."""
+    from paper_1205_6872_amd.serve import Server
+    reqs = W.pulse_area_sweep(n=6, L=5, n_steps=60)
+    for k, w in enumerate(reqs):
+        w.meta["final_only"] = True
+        if k % 2:
+            reqs[k] = w.with_(dtype="c64", meta=dict(w.meta))
+    res = Server(max_active=3, chunk_steps=16).run(reqs, realtime=False)
+    for w, r in zip(reqs, res):
+        assert r.rho.shape == (2, 2, 2)
+        with Q.create(Q.params_from(w)) as ctx:
+            alone = ctx.propagate(w.n_steps, sel=[0, w.n_steps])
+        assert np.array_equal(r.rho, alone), (w.name, np.abs(r.rho - alone).max())
+    # areas 0, 0.8 pi, 1.6 pi, ...: no pulse leaves the dot in its ground
+    # state; 0.8 pi lifts most of it (sin^2(0.4 pi) = 0.90 without phonons)
+    pe = [r.rho[-1, 1, 1].real for r in res]
+    assert abs(pe[0]) < 1e-12 and pe[1] > 0.5 and pe[2] < pe[1]
