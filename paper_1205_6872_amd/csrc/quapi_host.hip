@@ -92,20 +92,24 @@ DigitSplit split_digits2(int n_digits) {
 }
 
 // The fused two-step kernel applies to N = 4 (its N^2 inputs per item fit in
-// registers) and L >= 2 (two points to sum out).
-bool fused_ok(int N, int L) { return N == 4 && L >= 2; }
+// registers) and L >= 3: two points to sum out, and the factor of the second
+// oldest point seen from the first new one at lag L-1 >= 2, so that it carries
+// no K and its rows of the diagonal points are ones (the kernel uses that).
+bool fused_ok(int N, int L) { return N == 4 && L >= 3; }
 
-// The three-step kernel runs for N = 4, L >= 3 (three points to sum out).
-bool triple_ok(int N, int L) { return N == 4 && L >= 3; }
+// The three-step kernel runs for N = 4, L >= 4 (three points to sum out; the
+// step-n group factors at lags L-1 and L-2 >= 2, for the same reason).
+bool triple_ok(int N, int L) { return N == 4 && L >= 4; }
 
-// Full-window steps per launch chosen by default: three at complex128 from
-// L = 14 (4^11 items and more; the step is HBM bound there, and a third step
-// in registers saves a third of the traffic), two otherwise.  A three-step
-// item runs one wave per SIMD through three dependent stages, so with fewer
-// items than that the two-step kernel finishes first; at complex64 storage the
-// two-step kernel is already bound by its arithmetic.
+// Full-window steps per launch chosen by default: three at complex128 and at
+// complex64 with FP32 arithmetic from L = 13 (4^10 items and more; the step is
+// HBM bound there, and a third step in registers saves a third of the
+// traffic), two otherwise.  A three-step item runs one or two waves per SIMD
+// through three dependent stages, so with fewer items than that the two-step
+// kernel finishes first; with complex64 storage and FP64 arithmetic the
+// three-step kernel is bound by its arithmetic and the two-step one is not.
 int fusion_width(int N, int L, int prec) {
-    if (triple_ok(N, L) && L >= 14 && prec == kPrecC128) return 3;
+    if (triple_ok(N, L) && L >= 13 && (prec == kPrecC128 || prec == kPrecC64)) return 3;
     return fused_ok(N, L) ? 2 : 1;
 }
 
@@ -113,7 +117,7 @@ int max_grid(int N, int L) {
     int g = 1;
     for (int nd = 0; nd <= L - 1; ++nd) g = std::max(g, split_digits(N, nd).grid);
     if (fused_ok(N, L)) g = std::max(g, split_digits2(L - 2).grid);
-    if (N == 4 && L >= 3) g = std::max(g, split_digits2(L - 3).grid);
+    if (triple_ok(N, L)) g = std::max(g, split_digits2(L - 3).grid);
     return g;
 }
 
@@ -1374,8 +1378,8 @@ quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
         return fail(ctx, QUAPI_ERR_INVALID, "a driven context runs one step per launch");
     const bool ok = steps == 1 || (steps == 2 && fused_ok(N, L)) || (steps == 3 && triple_ok(N, L));
     if (!ok)
-        return fail(ctx, QUAPI_ERR_INVALID, "%d fused steps unavailable at N = %d, L = %d (1 always; 2: N = 4, L >= 2; "
-                    "3: N = 4, L >= 3)", steps, N, L);
+        return fail(ctx, QUAPI_ERR_INVALID, "%d fused steps unavailable at N = %d, L = %d (1 always; 2: N = 4, L >= 3; "
+                    "3: N = 4, L >= 4)", steps, N, L);
     if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
     ctx->fuse = steps;
     return QUAPI_OK;

@@ -97,7 +97,7 @@ struct CoefArgs {
     void *out;
 };
 
-// Three consecutive full-window steps n, n+1, n+2 (n > L, N = 4, L >= 3) in
+// Three consecutive full-window steps n, n+1, n+2 (n > L, N = 4, L >= 4) in
 // one pass: A_out[m + m_count*(o + N*o' + N^2*o'')] from the N^3 contiguous
 // inputs A_in[i + N*i' + N^2*i'' + N^3*m], m the digits of points
 // n-L+3 .. n-1 (m_count = N^(L-3)); the step-n and step-(n+1) tensors stay in

@@ -115,40 +115,79 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
                 cn1[op] = cmul(s_plo[(1 * N + op) * R + r], s_tq[(1 * N + op) * Q + qm]);
                 if (RHO) totf[op] = C{};
             }
-            // Per new point o of step n: the step-n entries y(o, i') (and the
-            // rho(t_n) term), then every step-(n+1) entry that reads them.
+            // Diagonal points o = (a, a) (o = 0 and 3) carry no influence: every
+            // factor exp(-(s_a - s_b)(...)) of a later point o is exactly one
+            // there.  So OA and W (old-point tables times the lag L-1 >= 2
+            // factor, no K) are ones in the rows o = 0, 3, and DO, V (K folded
+            // in) do not depend on i' in the rows o' = 0, 3: those rows reduce
+            // to plain sums over the summed point, shared by both diagonal rows.
+            C sx[N], totd = {};
 #pragma unroll
-            for (int o = 0; o < N; ++o) {
+            for (int ip = 0; ip < N; ++ip) {
+                sx[ip] = x[N * ip];
+#pragma unroll
+                for (int i = 1; i < N; ++i) sx[ip] = cadd(sx[ip], x[i + N * ip]);
+            }
+            if (RHO) {
+                totd = x[0];
+#pragma unroll
+                for (int k = 1; k < NN; ++k) totd = cadd(totd, x[k]);
+            }
+            // Per new point o of step n: the step-n entries y(o, i') (and the
+            // rho(t_n) term), then every step-(n+1) entry that reads them.  The
+            // diagonal points go first, so the shared sums are dead after them.
+#pragma unroll
+            for (int oo = 0; oo < N; ++oo) {
+                const int o = oo == 0 ? 0 : oo == 1 ? 3 : oo - 1;
                 asm volatile("" ::: "memory");  // coefficient reads of this o only
                 const T *co = coef + 2 * kCoefPerO * o;
+                const bool dg = o == 0 || o == 3;
                 const C bn = cmul(s_plo[(0 * N + o) * R + r], s_tq[(0 * N + o) * Q + qm]);
                 C y[N];
 #pragma unroll
                 for (int ip = 0; ip < N; ++ip) {
-                    C sum = {};
+                    C sum = sx[ip];
+                    if (!dg) {
+                        sum = C{};
 #pragma unroll
-                    for (int i = 0; i < N; ++i) cmac(sum, coef_ld(co, kCoefOA + ip * N + i), x[i + N * ip]);
+                        for (int i = 0; i < N; ++i) cmac(sum, coef_ld(co, kCoefOA + ip * N + i), x[i + N * ip]);
+                    }
                     y[ip] = cmul(bn, sum);
                 }
                 if (RHO) {
-                    C tot = {};
+                    C tot = totd;
+                    if (!dg) {
+                        tot = C{};
 #pragma unroll
-                    for (int k = 0; k < NN; ++k) cmac(tot, coef_ld(co, kCoefW + k), x[k]);
+                        for (int k = 0; k < NN; ++k) cmac(tot, coef_ld(co, kCoefW + k), x[k]);
+                    }
                     const C bnf = cmul(s_plo[(2 * N + o) * R + r], s_tq[(2 * N + o) * Q + qm]);
                     const double2 v = to_d2(cmul(bnf, tot));
                     accn[o].x += v.x;
                     accn[o].y += v.y;
                 }
+                C ysum = y[0];
+#pragma unroll
+                for (int ip = 1; ip < N; ++ip) ysum = cadd(ysum, y[ip]);
 #pragma unroll
                 for (int op = 0; op < N; ++op) {
                     asm volatile("" ::: "memory");
+                    const bool dgp = op == 0 || op == 3;
                     C sum = {};
+                    if (dgp) {
+                        sum = cmul(coef_ld(co, kCoefDO + op * N), ysum);
+                    } else {
 #pragma unroll
-                    for (int ip = 0; ip < N; ++ip) cmac(sum, coef_ld(co, kCoefDO + op * N + ip), y[ip]);
+                        for (int ip = 0; ip < N; ++ip) cmac(sum, coef_ld(co, kCoefDO + op * N + ip), y[ip]);
+                    }
                     aout[m + mc * (o + N * op)] = conv<CS>(cmul(cn1[op], sum));
                     if (RHO) {
+                        if (dgp) {
+                            cmac(totf[op], coef_ld(co, kCoefV + op * N), ysum);
+                        } else {
 #pragma unroll
-                        for (int ip = 0; ip < N; ++ip) cmac(totf[op], coef_ld(co, kCoefV + op * N + ip), y[ip]);
+                            for (int ip = 0; ip < N; ++ip) cmac(totf[op], coef_ld(co, kCoefV + op * N + ip), y[ip]);
+                        }
                     }
                 }
             }

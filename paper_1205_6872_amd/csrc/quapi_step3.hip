@@ -146,16 +146,27 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
             // registers), then the step itself (table old resident), which
             // overwrites the slots.  Per group only the four group coefficients
             // are fetched again.
+            //
+            // Diagonal points o = (a, a) (o = 0 and 3) carry no influence: every
+            // factor exp(-(s_a - s_b)(...)) of a later point o is exactly one
+            // there.  So the old / old_f rows of o = 0, 3 and the step-n group
+            // factors AF of o = 0, 3 (lags L-1 and L-2 >= 2, no K) are ones, and
+            // their sums over the summed point are one plain sum shared by both
+            // rows -- the same additions in the same order as the general form.
             // ---- step n: groups g = i' + N i'', slots 4g .. 4g+3
             {
                 if (RHO) {
                     const T *co = fresh(coef);
-                    C tf[N] = {};
+                    C tf[N] = {};           // tf[0]: both diagonal points
 #pragma unroll
                     for (int g = 0; g < N * N; ++g) {
                         const T *cg = fresh(coef);
+                        C sd = w[N * g];
 #pragma unroll
-                        for (int o = 0; o < N; ++o) {
+                        for (int i = 1; i < N; ++i) sd = cadd(sd, w[N * g + i]);
+                        tf[0] = cadd(tf[0], sd);
+#pragma unroll
+                        for (int o = 1; o <= 2; ++o) {
                             C sf = {};
 #pragma unroll
                             for (int i = 0; i < N; ++i) cmac(sf, coef_ld(co, kC3Oldf + o * N + i), w[N * g + i]);
@@ -164,7 +175,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                     }
 #pragma unroll
                     for (int o = 0; o < N; ++o) {
-                        const double2 v = to_d2(cmul(factor(3, o, qm), tf[o]));
+                        const double2 v = to_d2(cmul(factor(3, o, qm), tf[o == 3 ? 0 : o]));
                         acc[0][o].x += v.x;
                         acc[0][o].y += v.y;
                     }
@@ -180,13 +191,18 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                     C xs[N];
 #pragma unroll
                     for (int i = 0; i < N; ++i) xs[i] = w[N * g + i];
+                    C sd = xs[0];
 #pragma unroll
-                    for (int o = 0; o < N; ++o) {
+                    for (int i = 1; i < N; ++i) sd = cadd(sd, xs[i]);
+#pragma unroll
+                    for (int o = 1; o <= 2; ++o) {
                         C s = {};
 #pragma unroll
                         for (int i = 0; i < N; ++i) cmac(s, coef_ld(co, kC3Old + o * N + i), xs[i]);
                         w[N * g + o] = cmul(bn[o], cmul(coef_ld(cg, kC3AF + g * N + o), s));
                     }
+                    w[N * g] = cmul(bn[0], sd);
+                    w[N * g + 3] = cmul(bn[3], sd);
                 }
             }
             // ---- step n+1: groups (o, i''), slots o + N i' + N^2 i'' over i'
@@ -200,12 +216,18 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
 #pragma unroll
                         for (int o = 0; o < N; ++o) {
                             const T *cg = fresh(coef);
+                            C sd = w[o + N * N * ipp];
+#pragma unroll
+                            for (int ip = 1; ip < N; ++ip) sd = cadd(sd, w[o + N * ip + N * N * ipp]);
 #pragma unroll
                             for (int op = 0; op < N; ++op) {
-                                C sf = {};
+                                C sf = sd;
+                                if (op == 1 || op == 2) {
+                                    sf = C{};
 #pragma unroll
-                                for (int ip = 0; ip < N; ++ip)
-                                    cmac(sf, coef_ld(co, kC3Oldf + op * N + ip), w[o + N * ip + N * N * ipp]);
+                                    for (int ip = 0; ip < N; ++ip)
+                                        cmac(sf, coef_ld(co, kC3Oldf + op * N + ip), w[o + N * ip + N * N * ipp]);
+                                }
                                 cmac(tf[op], coef_ld(cg, kC3GHf + (ipp * N + o) * N + op), sf);
                             }
                         }
@@ -230,11 +252,17 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                         C ys[N];
 #pragma unroll
                         for (int ip = 0; ip < N; ++ip) ys[ip] = w[o + N * ip + N * N * ipp];
+                        C sd = ys[0];
+#pragma unroll
+                        for (int ip = 1; ip < N; ++ip) sd = cadd(sd, ys[ip]);
 #pragma unroll
                         for (int op = 0; op < N; ++op) {
-                            C s = {};
+                            C s = sd;
+                            if (op == 1 || op == 2) {
+                                s = C{};
 #pragma unroll
-                            for (int ip = 0; ip < N; ++ip) cmac(s, coef_ld(co, kC3Old + op * N + ip), ys[ip]);
+                                for (int ip = 0; ip < N; ++ip) cmac(s, coef_ld(co, kC3Old + op * N + ip), ys[ip]);
+                            }
                             w[o + N * op + N * N * ipp] =
                                 cmul(cn[op], cmul(coef_ld(cg, kC3GH + (ipp * N + o) * N + op), s));
                         }
@@ -252,12 +280,18 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
 #pragma unroll
                         for (int o = 0; o < N; ++o) {
                             const T *cg = fresh(coef);
+                            C sd = w[o + N * op];
+#pragma unroll
+                            for (int ipp = 1; ipp < N; ++ipp) sd = cadd(sd, w[o + N * op + N * N * ipp]);
 #pragma unroll
                             for (int opp = 0; opp < N; ++opp) {
-                                C sf = {};
+                                C sf = sd;
+                                if (opp == 1 || opp == 2) {
+                                    sf = C{};
 #pragma unroll
-                                for (int ipp = 0; ipp < N; ++ipp)
-                                    cmac(sf, coef_ld(co, kC3Oldf + opp * N + ipp), w[o + N * op + N * N * ipp]);
+                                    for (int ipp = 0; ipp < N; ++ipp)
+                                        cmac(sf, coef_ld(co, kC3Oldf + opp * N + ipp), w[o + N * op + N * N * ipp]);
+                                }
                                 cmac(tf[opp], coef_ld(cg, kC3PQf + (op * N + o) * N + opp), sf);
                             }
                         }
@@ -281,12 +315,21 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                         const T *cg = fresh(coef);
                         const long long st = fresh_stride(mc);
                         CS *const po = aout + m + st * (o + N * op);
+                        C zs[N];
+#pragma unroll
+                        for (int ipp = 0; ipp < N; ++ipp) zs[ipp] = w[o + N * op + N * N * ipp];
+                        C sd = zs[0];
+#pragma unroll
+                        for (int ipp = 1; ipp < N; ++ipp) sd = cadd(sd, zs[ipp]);
 #pragma unroll
                         for (int opp = 0; opp < N; ++opp) {
-                            C s = {};
+                            C s = sd;
+                            if (opp == 1 || opp == 2) {
+                                s = C{};
 #pragma unroll
-                            for (int ipp = 0; ipp < N; ++ipp)
-                                cmac(s, coef_ld(co, kC3Old + opp * N + ipp), w[o + N * op + N * N * ipp]);
+                                for (int ipp = 0; ipp < N; ++ipp)
+                                    cmac(s, coef_ld(co, kC3Old + opp * N + ipp), zs[ipp]);
+                            }
                             po[st * N * N * opp] =
                                 conv<CS>(cmul(dn[opp], cmul(coef_ld(cg, kC3PQ + (op * N + o) * N + opp), s)));
                         }

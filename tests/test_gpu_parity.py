@@ -180,7 +180,7 @@ def _sampled_fused_check(w, dtype, tol, F=None):
     with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
         if F is None:
             F = ctx.fused_steps()
-            assert F == (3 if dtype == "c128" and L >= 14 else 2), F
+            assert F == (3 if dtype in ("c128", "c64") and L >= 13 else 2), F
         else:
             ctx.set_fused_steps(F)
         mr = N ** (L - F)                   # items: digits of points n-L+F .. n-1
@@ -252,6 +252,31 @@ def test_every_group_width_against_oracle(F, dtype, tol):
     with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
         with pytest.raises(Q.QuapiError):
             ctx.set_fused_steps(4)
+
+
+@pytest.mark.parametrize("L,F", [(3, 2), (4, 2), (4, 3), (5, 3)])
+def test_smallest_windows_of_each_group_width(L, F):
+    # the fused kernels take the rows of the diagonal points of their
+    # oldest-point factors as ones, which needs those factors at lag >= 2
+    w = W.spin_boson_l7().with_(L=L, H=W.random_hermitian(np.random.default_rng(L), 2))
+    n = 40
+    with Q.create(Q.params_from(w)) as ctx:
+        ctx.set_fused_steps(F)
+        ctx.set_timing(True)
+        g = ctx.propagate(n, sel=list(range(n + 1)))
+        t = ctx.get_timing()
+        assert t["step_steps"] > t["step_launches"], t
+    err = rel_err_per_step(g, oracle_rho(w, n))
+    assert err.max() <= TOL_C128, (err.argmax(), err.max())
+
+
+@pytest.mark.parametrize("L,F", [(2, 2), (3, 3), (1, 2)])
+def test_group_widths_below_their_window_are_refused(L, F):
+    with Q.create(Q.params_from(W.spin_boson_l7().with_(L=L))) as ctx:
+        assert ctx.fused_steps() == (2 if L >= 3 else 1)
+        with pytest.raises(Q.QuapiError) as ei:
+            ctx.set_fused_steps(F)
+        assert ei.value.status == Q.ERR_INVALID
 
 
 def test_l15_single_steps_sampled_entries_c128():
