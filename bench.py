@@ -93,13 +93,16 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         tm = ctx.get_timing()
+        mirror = ctx.mirror() and ctx.fused_steps() == 3     # only the three-step kernel has a mirror mode
     finally:
         ctx.destroy()
         del ctx
         torch.cuda.empty_cache()
     entries = N ** L
     csize = 16 if dtype == "c128" else 8   # bytes per stored entry
-    bytes_per_launch = 2 * entries * csize
+    # every entry read once and written once; in mirror mode only the entries
+    # not above their mirror, (N^L + M^L) / 2 of them
+    bytes_per_launch = (entries + w.M ** L) * csize if mirror else 2 * entries * csize
     launches = max(tm["step_launches"], 1)
     kernel_ms = tm["step_ms"] / launches                  # per full-window launch
     steps_per_launch = tm["step_steps"] / launches        # 2 when two steps are fused
@@ -111,11 +114,14 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
         steps_per_launch=steps_per_launch,
         finalize_ms=tm["finalize_ms"] / max(tm["finalize_launches"], 1), setup_ms=tm["setup_ms"],
         setup_wall_ms=setup_wall * 1e3, grow_ms=grow_ms, bytes_per_launch=bytes_per_launch,
-        achieved_gbs=achieved, rho=rho)
+        achieved_gbs=achieved, rho=rho, mirror=mirror, step_bytes=2 * entries * csize)
 
 
-def kernel_name(tier: str, steps_per_launch: float) -> str:
+def kernel_name(tier: str, steps_per_launch: float, mirror: bool = False) -> str:
     st = {"c128": "double, double", "c64": "float, float", "c64f64": "float, double"}[tier]
+    if steps_per_launch > 2.5 and mirror:
+        return (f"step3_kernel<{st}, rho, mirror> (three steps fused per launch, the entries not above "
+                f"their mirror only)")
     if steps_per_launch > 2.5:
         return f"step3_kernel<{st}, rho> (three steps fused per launch)"
     if steps_per_launch > 1.5:
@@ -290,11 +296,11 @@ def main() -> int:
                    "xi": w.xi, "omega_c": w.omega_c, "kT": w.kT, "dt": w.dt},
         "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": kernel_name(main_t, r["steps_per_launch"]),
+                     "traffic": traffic, "kernel": kernel_name(main_t, r["steps_per_launch"], r["mirror"]),
                      "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_launch": r["bytes_per_launch"],
                      "steps_per_launch": round(r["steps_per_launch"], 3),
-                     # bytes a single (unfused) step reads and writes, per measured step time
-                     "step_equivalent_gbs": round(r["bytes_per_launch"] / (r["ms_per_step"] * 1e-3) / 1e9, 1)},
+                     # bytes a single full-tensor step reads and writes, per measured step time
+                     "step_equivalent_gbs": round(r["step_bytes"] / (r["ms_per_step"] * 1e-3) / 1e9, 1)},
         "setup_ms": round(r["setup_ms"], 3),
         "growth_ms": round(r["grow_ms"], 3),
         "finalize_ms": round(r["finalize_ms"], 4),
@@ -311,10 +317,10 @@ def main() -> int:
             "roofline": {"bound": "hbm", "achieved": round(a["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(a["achieved_gbs"] / HBM_PEAK_GBS, 4),
                          "traffic": measured_traffic(t),
-                         "kernel": kernel_name(t, a["steps_per_launch"]),
+                         "kernel": kernel_name(t, a["steps_per_launch"], a["mirror"]),
                          "kernel_ms": round(a["kernel_ms"], 4), "bytes_per_launch": a["bytes_per_launch"],
                          "steps_per_launch": round(a["steps_per_launch"], 3),
-                         "step_equivalent_gbs": round(a["bytes_per_launch"] / (a["ms_per_step"] * 1e-3) / 1e9, 1)},
+                         "step_equivalent_gbs": round(a["step_bytes"] / (a["ms_per_step"] * 1e-3) / 1e9, 1)},
             "max_abs_drho_vs_f64": d, "trace_drift_vs_f64": drift, "steps_compared": len(a["rho"]),
         }
     if not args.no_copy_ceiling:

@@ -146,7 +146,8 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
  * Results are deterministic.  For M = 2 full-window steps run in fused groups of
  * F = quapi_fused_steps() steps fixed by the global step number: (L+1 .. L+F),
  * (L+F+1 .. L+2F), ... (by default F = 3 at complex128 and QUAPI_C64 from
- * L = 13, F = 2 otherwise with L >= 3); a sequence of calls gives bit-identical results to one call when
+ * L = 13, and at complex128 from L = 12 where mirror mode is available, see
+ * quapi_set_mirror; F = 2 otherwise with L >= 3); a sequence of calls gives bit-identical results to one call when
  * every call ends at step c <= L or with c - L a multiple of F (otherwise the
  * steps of a split group run one by one and round differently, within 1e-15). */
 quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
@@ -188,13 +189,32 @@ quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries);
 quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps);
 
 /* Choose the full-window steps per launch: 1, 2 (N = 4, L >= 3), 3 (N = 4,
- * L >= 4), or 0 for the default (3 at complex128 and QUAPI_C64 from L = 13, else 2 where
+ * L >= 4), or 0 for the default (3 at complex128 and QUAPI_C64 from L = 13 -- from
+ * L = 12 at complex128 where mirror mode is available -- else 2 where
  * available, else 1; always 1 for a driven context).  Every choice gives the same results to within rounding
  * (the fused kernels apply the same factors in another order); use it to pin
  * the kernel, e.g. in tests.  It takes effect from the next call.
  * Errors: QUAPI_ERR_INVALID for an unavailable width; QUAPI_ERR_STATE while
  * another call runs on the context. */
 quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps);
+
+/* Mirror mode of the three-step kernel (M = 2, L >= 4).  Swapping the forward
+ * and backward path of every point maps the path sum of Sec. II to its complex
+ * conjugate: K = U (x) U* and every influence factor go to their conjugates,
+ * and so does rho(0) when it is Hermitian.  So the tensor entry of the
+ * mirrored paths is the conjugate of the entry itself, and a three-step pass
+ * reads and writes only the entries not above their mirror (flat index, each
+ * digit (a, b) -> (b, a)) -- about half the bytes.  rho at every step is
+ * unchanged up to rounding.  The entries above their mirror are filled in
+ * before anything that reads the whole tensor (single steps, the two-step
+ * kernel, quapi_read_tensor).  On by default where available.
+ *   quapi_mirror:      *enabled = 1 while on.
+ *   quapi_set_mirror:  enable = 0 turns it off; 1 turns it on.
+ * Errors: QUAPI_ERR_INVALID for NULL arguments, or enable = 1 where it is not
+ * available (M != 2, L < 4, or rho0 not exactly Hermitian); QUAPI_ERR_STATE
+ * while another call runs on the context. */
+quapi_status quapi_mirror(const quapi_ctx *ctx, int *enabled);
+quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable);
 
 /* Kernel timing with HIP events on the context's stream. */
 typedef struct {

@@ -104,12 +104,15 @@ bool triple_ok(int N, int L) { return N == 4 && L >= 4; }
 // Full-window steps per launch chosen by default: three at complex128 and at
 // complex64 with FP32 arithmetic from L = 13 (4^10 items and more; the step is
 // HBM bound there, and a third step in registers saves a third of the
-// traffic), two otherwise.  A three-step item runs one or two waves per SIMD
-// through three dependent stages, so with fewer items than that the two-step
-// kernel finishes first; with complex64 storage and FP64 arithmetic the
-// three-step kernel is bound by its arithmetic and the two-step one is not.
-int fusion_width(int N, int L, int prec) {
-    if (triple_ok(N, L) && L >= 13 && (prec == kPrecC128 || prec == kPrecC64)) return 3;
+// traffic), and at complex128 from L = 12 where the three-step kernel runs
+// in mirror mode (half the entries); two otherwise.  A three-step item runs
+// one or two waves per SIMD through three dependent stages, so with fewer
+// items than that the two-step kernel finishes first; with complex64 storage
+// and FP64 arithmetic the three-step kernel is bound by its arithmetic and the
+// two-step one is not.
+int fusion_width(int N, int L, int prec, bool mirror) {
+    const int from = prec == kPrecC128 && mirror ? 12 : 13;
+    if (triple_ok(N, L) && L >= from && (prec == kPrecC128 || prec == kPrecC64)) return 3;
     return fused_ok(N, L) ? 2 : 1;
 }
 
@@ -272,9 +275,10 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_Ht, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
-    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_pairs, off_sink;
+    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_pairs, off_sink;
     size_t total;
     int n_panels, n_tables, partial_blocks;
+    int n_canon3, n_diag3, parts3, span3;   // mirror mode of the three-step kernel (high-digit blocks)
     DigitSplit main_split;   // digit split of the full-window steps
     DigitSplit split2;       // digit split of the fused two-step kernel
     DigitSplit split3;       // digit split of the three-step kernel
@@ -295,6 +299,22 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.split2 = fused_ok(N, L) ? split_digits2(L - 2) : DigitSplit{0, 0, 1, 1, 1};
     const bool triple = triple_ok(N, L);
     l.split3 = triple ? split_digits2(L - 3) : DigitSplit{0, 0, 1, 1, 1};
+    if (triple) {
+        // mirror mode: blocks whose high digits are below their mirror, and
+        // those equal to it (all diagonal), split into one sweep row per thread
+        const DigitSplit &s3 = l.split3;
+        for (int h = 0; h < s3.grid; ++h) {
+            const long long hb = mirror4(h);
+            if (h < hb) ++l.n_canon3;
+            else if (h == hb) ++l.n_diag3;
+        }
+        // mode 2: about four sweep rows per thread per block
+        const int rows_per_pass = kBlock / s3.R;
+        const int passes = (s3.Q + rows_per_pass - 1) / rows_per_pass;
+        l.parts3 = (passes + 3) / 4;
+        l.span3 = ((passes + l.parts3 - 1) / l.parts3) * rows_per_pass;
+        l.partial_blocks = std::max(l.partial_blocks, l.n_canon3 + l.n_diag3 * (l.parts3 + 1));
+    }
     l.a_bytes = entries * cs;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -336,6 +356,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     const DigitSplit &s3 = l.split3;
     l.off_plan3 = take(triple ? (size_t)6 * N * (s3.R + s3.Q + s3.grid) * 16 : 0);
     l.off_coef3 = take(triple ? (size_t)kC3Count * 16 : 0);
+    l.off_blk3 = take(triple ? (size_t)(l.n_canon3 + l.n_diag3) * sizeof(int) : 0);
     l.total = off;
     return l;
 }
@@ -387,6 +408,13 @@ struct quapi_ctx {
     bool plan2_ready = false;     // fused-step factor tables computed
     bool plan3_ready = false;     // three-step factor tables computed
     int fuse = 1;                 // full-window steps per launch (fusion_width)
+    // Mirror mode of the three-step kernel: it reads and writes only the
+    // entries not above their mirror; half_cur says A[cur] holds only those.
+    bool mirror_ok = false;       // N = 4, three-step width available, rho0 exactly Hermitian
+    bool mirror = false;
+    bool half_cur = false;
+    int *blk3 = nullptr;          // high-digit values: n_canon3 below their mirror, then n_diag3 equal
+    std::vector<int> blk3_h;
     double2 *plan3 = nullptr;
     void *coef3 = nullptr;
     std::vector<double> rho0_h;
@@ -578,6 +606,16 @@ quapi_status join_side(quapi_ctx *c) {
     return QUAPI_OK;
 }
 
+// Before any kernel or copy that reads every entry of A[cur]: if the last
+// step ran in mirror mode, fill the entries above their mirror.
+quapi_status ensure_full(quapi_ctx *c) {
+    if (!c->half_cur) return QUAPI_OK;
+    hipError_t e = launch_mirror_complete(c->prec, c->A[c->cur], ipow_ll(c->N, c->L), c->stream);
+    if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "mirror completion launch: %s", hipGetErrorString(e));
+    c->half_cur = false;
+    return QUAPI_OK;
+}
+
 // Finalize the rho partials of `slots` (in order) on the side stream, after
 // the step kernel that wrote them.
 quapi_status finalize_side(quapi_ctx *c, const int *slots, int n, int grid) {
@@ -606,6 +644,7 @@ quapi_status finalize_side(quapi_ctx *c, const int *slots, int n, int grid) {
 // Enqueue step n (1-based); with rho, also rho(t_n) into the sink's next slot.
 // The finalize runs on the side stream, overlapped with the next step.
 quapi_status enqueue_step(quapi_ctx *c, int n, bool rho) {
+    if (quapi_status fs = ensure_full(c); fs != QUAPI_OK) return fs;
     StepPlan sp;
     quapi_status st = prepare_step(c, n, rho, &sp);
     if (st != QUAPI_OK) return st;
@@ -714,6 +753,7 @@ quapi_status prepare_step2(quapi_ctx *c, bool rho, Step2Args *out) {
 // Enqueue the fused steps n, n+1 (n > L); rho of the selected ones goes to
 // the sink in step order.
 quapi_status enqueue_step2(quapi_ctx *c, int n, bool sel_n, bool sel_n1) {
+    if (quapi_status fs = ensure_full(c); fs != QUAPI_OK) return fs;
     const bool rho = sel_n || sel_n1;
     Step2Args a;
     quapi_status st = prepare_step2(c, rho, &a);
@@ -830,13 +870,58 @@ quapi_status prepare_step3(quapi_ctx *c, bool rho, Step3Args *out) {
     return QUAPI_OK;
 }
 
-// Enqueue the steps n, n+1, n+2 (n > L) as one launch; rho of the selected
-// ones goes to the sink in step order.
+// Launch the three-step kernel with the arguments of prepare_step3: every
+// block (mode 0), or in mirror mode the launches over the high-digit values
+// below their mirror (mode 1) and equal to it (modes 2 and 3).  *rows: the
+// rho partial rows written.
+hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows) {
+    if (!c->mirror) {
+        a.mode = 0;
+        *rows = a.grid;
+        return launch_step3(c->prec, rho, a, c->stream);
+    }
+    const Layout &l = c->lay;
+    hipError_t e = hipSuccess;
+    if (l.n_canon3 > 0) {
+        a.mode = 1;
+        a.blk_hi = c->blk3;
+        a.n_blk = l.n_canon3;
+        a.parts = 1;
+        a.part_base = 0;
+        e = launch_step3(c->prec, rho, a, c->stream);
+    }
+    if (e == hipSuccess && l.n_diag3 > 0) {
+        a.mode = 2;
+        a.blk_hi = c->blk3 + l.n_canon3;
+        a.n_blk = l.n_diag3 * l.parts3;
+        a.parts = l.parts3;
+        a.q_span = l.span3;
+        a.part_base = l.n_canon3;
+        e = launch_step3(c->prec, rho, a, c->stream);
+    }
+    if (e == hipSuccess && l.n_diag3 > 0) {
+        a.mode = 3;
+        a.blk_hi = c->blk3 + l.n_canon3;
+        a.n_blk = l.n_diag3;
+        a.parts = 1;
+        a.part_base = l.n_canon3 + l.n_diag3 * l.parts3;
+        e = launch_step3(c->prec, rho, a, c->stream);
+    }
+    *rows = l.n_canon3 + l.n_diag3 * (l.parts3 + 1);
+    return e;
+}
+
+// Enqueue the steps n, n+1, n+2 (n > L) as one launch (three in mirror mode);
+// rho of the selected ones goes to the sink in step order.
 quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
     const bool rho = selk[0] || selk[1] || selk[2];
     Step3Args a;
     quapi_status st = prepare_step3(c, rho, &a);
     if (st != QUAPI_OK) return st;
+    if (!c->mirror) {                        // mode 0 reads every entry
+        st = ensure_full(c);
+        if (st != QUAPI_OK) return st;
+    }
     a.a_in = c->A[c->cur];
     a.a_out = c->A[1 - c->cur];
     int slots[3] = {-1, -1, -1};
@@ -854,7 +939,8 @@ quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
         e1 = take_event(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
-    hipError_t e = launch_step3(c->prec, rho, a, c->stream);
+    int rows = 0;
+    hipError_t e = launch_step3_modes(c, rho, a, &rows);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "three-step launch: %s", hipGetErrorString(e));
     if (c->timing && e0 && e1) {
         (void)hipEventRecord(e1, c->stream);
@@ -864,10 +950,11 @@ quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
         int fin[3], nf = 0;
         for (int k = 0; k < 3; ++k)
             if (selk[k]) fin[nf++] = slots[k];
-        st = finalize_side(c, fin, nf, a.grid);
+        st = finalize_side(c, fin, nf, rows);
         if (st != QUAPI_OK) return st;
     }
     c->cur = 1 - c->cur;
+    c->half_cur = c->mirror;
     c->step = n + 2;
     return QUAPI_OK;
 }
@@ -893,9 +980,10 @@ quapi_status build_graph(quapi_ctx *c, bool rho, int width, int par, hipGraphExe
         a3.a_in = c->A[par];
         a3.a_out = c->A[1 - par];
         for (int k = 0; k < 3; ++k) a3.partials[k] = c->partials[k];
-        e = launch_step3(c->prec, rho, a3, c->stream);
+        int rows = 0;
+        e = launch_step3_modes(c, rho, a3, &rows);
         for (int k = 0; k < 3 && rho && e == hipSuccess; ++k)
-            e = launch_rho_finalize(c->N, c->partials[k], a3.grid, c->pairs, c->sink, c->stream);
+            e = launch_rho_finalize(c->N, c->partials[k], rows, c->pairs, c->sink, c->stream);
     } else if (width == 2) {
         a2.a_in = c->A[par];
         a2.a_out = c->A[1 - par];
@@ -1017,9 +1105,11 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
                     c->graph_failed = true;   // stay on direct launches
                 } else {
                     st = join_side(c);        // the graph reuses partial buffers 0, 1 and 2
+                    if (st == QUAPI_OK && !c->mirror) st = ensure_full(c);
                     if (st != QUAPI_OK) return st;
                     HIP_TRY(c, hipGraphLaunch(gx, c->stream));
                     c->cur = 1 - c->cur;
+                    c->half_cur = c->mirror;
                     c->step = n + 2;
                     done = true;
                 }
@@ -1051,6 +1141,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
                     c->graph_failed = true;   // stay on direct launches
                 } else {
                     st = join_side(c);        // the graph reuses partial buffers 0 and 1
+                    if (st == QUAPI_OK) st = ensure_full(c);
                     if (st != QUAPI_OK) return st;
                     HIP_TRY(c, hipGraphLaunch(gx, c->stream));
                     if (fused) c->cur = 1 - c->cur;
@@ -1239,9 +1330,9 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->plan2 = (double2 *)(w + lay.off_plan2);
     c->plan3 = (double2 *)(w + lay.off_plan3);
     c->coef3 = w + lay.off_coef3;
+    c->blk3 = (int *)(w + lay.off_blk3);
     c->n_H = p->n_H;
     c->Ht_d = (const double2 *)(w + lay.off_Ht);
-    c->fuse = c->n_H > 0 ? 1 : fusion_width(N, p->dk_max, c->prec);
     c->coef = w + lay.off_coef;
     c->stage = (double2 *)(w + lay.off_stage);
     c->pairs = (double2 *)(w + lay.off_pairs);
@@ -1252,6 +1343,20 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->H_h.assign(p->H, p->H + 2 * M * M);
     if (p->n_H > 0) c->Ht_h.assign(p->H_t, p->H_t + (size_t)2 * M * M * p->n_H);
     c->rho0_h.assign(p->rho0, p->rho0 + 2 * N);
+    if (triple_ok(N, L)) {
+        for (int pass = 0; pass < 2; ++pass)
+            for (int h = 0; h < lay.split3.grid; ++h)
+                if (pass == 0 ? h < mirror4(h) : h == mirror4(h)) c->blk3_h.push_back(h);
+        // the path sum maps to its conjugate under the mirror only if rho0 does
+        bool herm = true;
+        for (int a = 0; a < M; ++a)
+            for (int b = 0; b < M; ++b)
+                herm = herm && p->rho0[2 * (a * M + b)] == p->rho0[2 * (b * M + a)] &&
+                       p->rho0[2 * (a * M + b) + 1] == -p->rho0[2 * (b * M + a) + 1];
+        c->mirror_ok = herm;
+        c->mirror = herm;
+    }
+    c->fuse = c->n_H > 0 ? 1 : fusion_width(N, L, c->prec, c->mirror_ok);
     c->pa_h = std::move(pa);
     c->ph_h = std::move(ph);
     c->pseg_h = std::move(pseg);
@@ -1272,6 +1377,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     if (e == hipSuccess) e = up(lay.off_H, c->H_h.data(), (size_t)M * M * 16);
     if (e == hipSuccess && c->n_H > 0) e = up(lay.off_Ht, c->Ht_h.data(), c->Ht_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_rho0, c->rho0_h.data(), (size_t)N * 16);
+    if (e == hipSuccess && !c->blk3_h.empty()) e = up(lay.off_blk3, c->blk3_h.data(), c->blk3_h.size() * sizeof(int));
     if (e == hipSuccess) e = up(lay.off_pa, c->pa_h.data(), c->pa_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_ph, c->ph_h.data(), c->ph_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_pseg, c->pseg_h.data(), c->pseg_h.size() * 4);
@@ -1373,7 +1479,7 @@ quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps) {
 quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
     if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
     const int N = ctx->N, L = ctx->L;
-    if (steps == 0) steps = ctx->n_H > 0 ? 1 : fusion_width(N, L, ctx->prec);
+    if (steps == 0) steps = ctx->n_H > 0 ? 1 : fusion_width(N, L, ctx->prec, ctx->mirror_ok);
     if (ctx->n_H > 0 && steps != 1)
         return fail(ctx, QUAPI_ERR_INVALID, "a driven context runs one step per launch");
     const bool ok = steps == 1 || (steps == 2 && fused_ok(N, L)) || (steps == 3 && triple_ok(N, L));
@@ -1382,6 +1488,29 @@ quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
                     "3: N = 4, L >= 4)", steps, N, L);
     if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
     ctx->fuse = steps;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_mirror(const quapi_ctx *ctx, int *enabled) {
+    if (!ctx || !enabled) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    *enabled = ctx->mirror ? 1 : 0;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable) {
+    if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
+    if (enable && !ctx->mirror_ok)
+        return fail(ctx, QUAPI_ERR_INVALID, "mirror mode needs M = 2, L >= 4 and an exactly Hermitian rho0");
+    if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
+    if ((enable != 0) == ctx->mirror) return QUAPI_OK;
+    // the captured three-step graphs hold the launches of the old mode
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &row : ctx->graph3)
+        for (auto &g : row) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    ctx->mirror = enable != 0;
     return QUAPI_OK;
 }
 
@@ -1419,6 +1548,7 @@ quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count,
         return fail(c, QUAPI_ERR_INVALID, "range [%zu, %zu) exceeds the tensor of %zu entries", first,
                     first + count, entries);
     if (!count) return QUAPI_OK;
+    if (quapi_status fs = ensure_full(c); fs != QUAPI_OK) return fs;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->prec == kPrecC128) {
         HIP_TRY(c, hipMemcpy(out, (const char *)c->A[c->cur] + first * 16, count * 16, hipMemcpyDeviceToHost));

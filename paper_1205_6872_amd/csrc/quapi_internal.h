@@ -112,7 +112,25 @@ struct Step3Args {
     long long m_count;
     int R, Q, grid;
     const void *coef;           // kC3Count complex entries in the compute precision
+    // Mirror mode (half of the tensor), three launches over high-digit values
+    // blk_hi[..]: mode 1 the values below their mirror (every item below its
+    // mirror), one block each; mode 2 the values equal to their mirror (all
+    // digits diagonal), each split into `parts` blocks of q_span sweep rows,
+    // n_blk = values * parts, running the items below their mirror; mode 3
+    // the same values, one block each, running the items that are their own
+    // mirror.  rho partials go to row part_base + block.  Mode 0 runs every
+    // block of the grid.
+    const int *blk_hi;
+    int n_blk, parts, q_span, part_base, mode;
 };
+
+// The mirror of an entry (N = 4, M = 2): every digit o = (a, b) -> (b, a),
+// i.e. 1 <-> 2, which swaps the two bits of each base-4 digit.  The path sum
+// maps to its complex conjugate under it (K, every influence factor and a
+// Hermitian rho(0) do), so A[mirror(x)] = conj(A[x]) for every entry x.
+__host__ __device__ constexpr long long mirror4(long long x) {
+    return ((x & 0x5555555555555555LL) << 1) | ((x >> 1) & 0x5555555555555555LL);
+}
 
 // Coefficients of the three-step kernel (compute precision), the four of one
 // group of a stage contiguous (indexed by the stage's new point last):
@@ -190,6 +208,8 @@ size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q);
 hipError_t launch_step2(int prec, bool with_rho, const Step2Args &a, hipStream_t st);
 hipError_t launch_step2_coef(const CoefArgs &a, hipStream_t st);
 hipError_t launch_step3(int prec, bool with_rho, const Step3Args &a, hipStream_t st);
+// Fill every entry above its mirror (N = 4) with the conjugate of the mirror.
+hipError_t launch_mirror_complete(int prec, void *a, long long entries, hipStream_t st);
 hipError_t launch_step3_coef(const Coef3Args &a, hipStream_t st);
 size_t step3_lds_bytes(int prec, bool with_rho, int R, int Q);
 size_t step2_lds_bytes(int prec, bool with_rho, int R, int Q);

@@ -8,6 +8,8 @@
 // bytes of a single step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "quapi_device.h"
 #include "quapi_internal.h"
 
@@ -87,8 +89,38 @@ __global__ void step3_coef_kernel(const Coef3Args a) {
 // four slots it reads, so w holds x, then y (slot o + N i' + N^2 i''), then z
 // (slot o + N o' + N^2 i'').  With RHO, rho at each of the three steps comes
 // from the values that stage reads, with the final-point classes.
-template <typename S, typename T, bool RHO>
+//
+// MODE 1, 2, 3 (mirror mode): an entry and its mirror are conjugates, so
+// only the items m not above their mirror mb are run, and of each output
+// entry only the one not above its mirror is stored (the conjugate goes to
+// the mirrored address).  Only those entries of the input need be valid: an
+// item that is its own mirror (all digits diagonal) takes its other entries
+// as the conjugates of theirs.  rho gets each item's terms and, for the
+// mirrored item that is not run, their conjugates at the mirrored point.
+// Mode 1 runs the blocks whose high digits are below their mirror, where
+// every item is below its mirror; mode 2 the few blocks whose high digits are
+// all diagonal, skipping the items not below their mirror; mode 3, one block
+// per such high-digit value, the items that are their own mirror.  So each
+// mode knows at compile time which of the cases it handles.
+__device__ __forceinline__ constexpr int mirror_digit(int d) { return d == 1 ? 2 : d == 2 ? 1 : d; }
+// The item digits whose bits are those of x: bit i -> digit i = 3 (else 0).
+__device__ __forceinline__ int diagonal_digits(unsigned x) {
+    x &= 0xffffu;
+    x = (x | (x << 8)) & 0x00ff00ffu;
+    x = (x | (x << 4)) & 0x0f0f0f0fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return (int)(3u * x);
+}
+template <typename C>
+__device__ __forceinline__ C cconj(C v) {
+    v.y = -v.y;
+    return v;
+}
+
+template <typename S, typename T, bool RHO, int MODE>
 __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
+    constexpr bool HALF = MODE != 0;
     constexpr int N = 4, NNN = 64;
     constexpr int NS = RHO ? 6 : 3;
     using C = typename Cx<T>::type;
@@ -104,7 +136,10 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
 
     const int t = threadIdx.x;
     const int cR = kBlock / R, active = cR * R;
-    const long long blk = blockIdx.x;
+    // high digits of m
+    const long long blk = MODE == 0   ? (long long)blockIdx.x
+                          : MODE == 2 ? (long long)a.blk_hi[blockIdx.x / a.parts]
+                                      : (long long)a.blk_hi[blockIdx.x];
     if (t < NS * N) {
         const int s = t / N, o = t % N;
         s_phi[t] = a.t_hi[s][(size_t)o * a.grid + blk];
@@ -125,21 +160,57 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
     for (int s = 0; s < (RHO ? 3 : 1); ++s)
 #pragma unroll
         for (int o = 0; o < (RHO ? N : 1); ++o) acc[s][o] = make_double2(0.0, 0.0);
-    const int r = t % R;
-    auto factor = [&](int set, int o, int qm) {
+    auto factor = [&](int set, int o, int r, int qm) {
         return cmul(s_plo[(set * N + o) * R + r], s_tq[(set * N + o) * Q + qm]);
+    };
+    // rho terms v[o] of one item; in mirror mode the mirrored item adds
+    // conj(v[mirror(o)]) (o = 0, 3 are their own mirrors, 1 and 2 swap)
+    auto add_rho = [&](double2 *ac, const double2 *v, bool both) {
+        if (HALF && both) {
+            ac[0].x += 2.0 * v[0].x;
+            ac[1].x += v[1].x + v[2].x;
+            ac[1].y += v[1].y - v[2].y;
+            ac[2].x += v[2].x + v[1].x;
+            ac[2].y += v[2].y - v[1].y;
+            ac[3].x += 2.0 * v[3].x;
+        } else {
+#pragma unroll
+            for (int o = 0; o < N; ++o) {
+                ac[o].x += v[o].x;
+                ac[o].y += v[o].y;
+            }
+        }
     };
     if (t < active) {
         const long long m0 = blk * (long long)R * Q;
         const CS *__restrict__ ain = (const CS *)a.a_in;
         CS *__restrict__ aout = (CS *)a.a_out;
         const long long mc = a.m_count;
-        for (int qm = t / R; qm < Q; qm += cR) {
+        // iterations: sweep rows qm (thread digits r = t % R), a part of
+        // them in mode 2; in mode 3 the items with all digits diagonal, whose
+        // bits give the low and the sweep digits
+        const int dl = (31 - __clz(R)) >> 1, dm = (31 - __clz(Q)) >> 1;
+        const int part = MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
+        const int i0 = MODE == 3 ? t : MODE == 2 ? part * a.q_span + t / R : t / R;
+        const int i1 = MODE == 3 ? (1 << (dl + dm)) : MODE == 2 ? min(Q, (part + 1) * a.q_span) : Q;
+        const int istep = MODE == 3 ? kBlock : cR;
+        for (int it = i0; it < i1; it += istep) {
             asm volatile("" ::: "memory");
+            const int r = MODE == 3 ? diagonal_digits((unsigned)it & ((1u << dl) - 1)) : t % R;
+            const int qm = MODE == 3 ? diagonal_digits((unsigned)it >> dl) : it;
             const long long m = m0 + (long long)qm * R + r;
+            const long long mb = HALF ? mirror4(m) : m;
+            if (MODE == 2 && mb <= m) continue;   // own mirror (mode 3), or run by its mirror
+            constexpr bool selfm = MODE == 3;
+            // an item that is its own mirror holds valid values only at the
+            // slots not above their mirror: the others are their mirrors' conjugates
             C w[NNN];
 #pragma unroll
-            for (int k = 0; k < NNN; ++k) w[k] = conv<C>(ain[(long long)NNN * m + k]);
+            for (int k = 0; k < NNN; ++k) {
+                const int kb = (int)mirror4(k);
+                w[k] = conv<C>(ain[(long long)NNN * m + (selfm && kb < k ? kb : k)]);
+                if (selfm && kb < k) w[k].y = -w[k].y;
+            }
 
             // Each stage runs two passes over its 16 groups of four slots: first
             // the rho terms (the final-point table old_f resident in scalar
@@ -173,18 +244,16 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                             cmac(tf[o], coef_ld(cg, kC3AFf + g * N + o), sf);
                         }
                     }
+                    double2 v[N];
 #pragma unroll
-                    for (int o = 0; o < N; ++o) {
-                        const double2 v = to_d2(cmul(factor(3, o, qm), tf[o == 3 ? 0 : o]));
-                        acc[0][o].x += v.x;
-                        acc[0][o].y += v.y;
-                    }
+                    for (int o = 0; o < N; ++o) v[o] = to_d2(cmul(factor(3, o, r, qm), tf[o == 3 ? 0 : o]));
+                    add_rho(acc[0], v, !selfm);
                 }
                 asm volatile("" ::: "memory");
                 const T *co = fresh(coef);
                 C bn[N];
 #pragma unroll
-                for (int o = 0; o < N; ++o) bn[o] = factor(0, o, qm);
+                for (int o = 0; o < N; ++o) bn[o] = factor(0, o, r, qm);
 #pragma unroll
                 for (int g = 0; g < N * N; ++g) {
                     const T *cg = fresh(coef);
@@ -232,18 +301,16 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                             }
                         }
                     }
+                    double2 v[N];
 #pragma unroll
-                    for (int op = 0; op < N; ++op) {
-                        const double2 v = to_d2(cmul(factor(4, op, qm), tf[op]));
-                        acc[1][op].x += v.x;
-                        acc[1][op].y += v.y;
-                    }
+                    for (int op = 0; op < N; ++op) v[op] = to_d2(cmul(factor(4, op, r, qm), tf[op]));
+                    add_rho(acc[1], v, !selfm);
                 }
                 asm volatile("" ::: "memory");
                 const T *co = fresh(coef);
                 C cn[N];
 #pragma unroll
-                for (int op = 0; op < N; ++op) cn[op] = factor(1, op, qm);
+                for (int op = 0; op < N; ++op) cn[op] = factor(1, op, r, qm);
 #pragma unroll
                 for (int ipp = 0; ipp < N; ++ipp) {
 #pragma unroll
@@ -296,18 +363,16 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                             }
                         }
                     }
+                    double2 v[N];
 #pragma unroll
-                    for (int opp = 0; opp < N; ++opp) {
-                        const double2 v = to_d2(cmul(factor(5, opp, qm), tf[opp]));
-                        acc[2][opp].x += v.x;
-                        acc[2][opp].y += v.y;
-                    }
+                    for (int opp = 0; opp < N; ++opp) v[opp] = to_d2(cmul(factor(5, opp, r, qm), tf[opp]));
+                    add_rho(acc[2], v, !selfm);
                 }
                 asm volatile("" ::: "memory");
                 const T *co = fresh(coef);
                 C dn[N];
 #pragma unroll
-                for (int opp = 0; opp < N; ++opp) dn[opp] = factor(2, opp, qm);
+                for (int opp = 0; opp < N; ++opp) dn[opp] = factor(2, opp, r, qm);
 #pragma unroll
                 for (int op = 0; op < N; ++op) {
 #pragma unroll
@@ -315,6 +380,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                         const T *cg = fresh(coef);
                         const long long st = fresh_stride(mc);
                         CS *const po = aout + m + st * (o + N * op);
+                        CS *const pb = aout + mb + st * (mirror_digit(o) + N * mirror_digit(op));
                         C zs[N];
 #pragma unroll
                         for (int ipp = 0; ipp < N; ++ipp) zs[ipp] = w[o + N * op + N * N * ipp];
@@ -330,8 +396,10 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                                 for (int ipp = 0; ipp < N; ++ipp)
                                     cmac(s, coef_ld(co, kC3Old + opp * N + ipp), zs[ipp]);
                             }
-                            po[st * N * N * opp] =
-                                conv<CS>(cmul(dn[opp], cmul(coef_ld(cg, kC3PQ + (op * N + o) * N + opp), s)));
+                            const C v = cmul(dn[opp], cmul(coef_ld(cg, kC3PQ + (op * N + o) * N + opp), s));
+                            const int c3 = o + N * op + N * N * opp;
+                            if (!HALF || (int)mirror4(c3) >= c3) po[st * N * N * opp] = conv<CS>(v);
+                            else if (!selfm) pb[st * N * N * mirror_digit(opp)] = conv<CS>(cconj(v));
                         }
                     }
                 }
@@ -360,7 +428,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                 sum.x += s_red[(s * (kBlock / 64) + w) * N + o].x;
                 sum.y += s_red[(s * (kBlock / 64) + w) * N + o].y;
             }
-            a.partials[s][blk * N + o] = sum;
+            a.partials[s][((size_t)a.part_base + blockIdx.x) * N + o] = sum;
         }
     }
 }
@@ -369,8 +437,25 @@ template <typename S, typename T, bool RHO>
 hipError_t launch_step3_t(const Step3Args &a, hipStream_t st) {
     using C = typename Cx<T>::type;
     const Step3Lds lay = step3_lds_layout((int)sizeof(C), RHO, a.R, a.Q);
-    hipLaunchKernelGGL((step3_kernel<S, T, RHO>), dim3(a.grid), dim3(kBlock), lay.total, st, a);
+    if (a.mode == 1)
+        hipLaunchKernelGGL((step3_kernel<S, T, RHO, 1>), dim3(a.n_blk), dim3(kBlock), lay.total, st, a);
+    else if (a.mode == 2)
+        hipLaunchKernelGGL((step3_kernel<S, T, RHO, 2>), dim3(a.n_blk), dim3(kBlock), lay.total, st, a);
+    else if (a.mode == 3)
+        hipLaunchKernelGGL((step3_kernel<S, T, RHO, 3>), dim3(a.n_blk), dim3(kBlock), lay.total, st, a);
+    else
+        hipLaunchKernelGGL((step3_kernel<S, T, RHO, 0>), dim3(a.grid), dim3(kBlock), lay.total, st, a);
     return hipGetLastError();
+}
+
+// One thread per entry x: entries above their mirror take the conjugate of it.
+template <typename CS>
+__global__ void __launch_bounds__(kBlock) mirror_complete_kernel(CS *__restrict__ a, long long entries) {
+    for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < entries;
+         x += (long long)gridDim.x * kBlock) {
+        const long long xb = mirror4(x);
+        if (xb < x) a[x] = cconj(a[xb]);
+    }
 }
 
 }  // namespace
@@ -389,6 +474,18 @@ hipError_t launch_step3(int prec, bool with_rho, const Step3Args &a, hipStream_t
         return with_rho ? launch_step3_t<float, double, true>(a, st) : launch_step3_t<float, double, false>(a, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_mirror_complete(int prec, void *a, long long entries, hipStream_t st) {
+    const long long blocks = std::min<long long>((entries + kBlock - 1) / kBlock, 1 << 20);
+    if (blocks < 1) return hipSuccess;
+    if (prec == kPrecC128)
+        hipLaunchKernelGGL(mirror_complete_kernel<double2>, dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                           (double2 *)a, entries);
+    else
+        hipLaunchKernelGGL(mirror_complete_kernel<float2>, dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                           (float2 *)a, entries);
+    return hipGetLastError();
 }
 
 hipError_t launch_step3_coef(const Coef3Args &a, hipStream_t st) {

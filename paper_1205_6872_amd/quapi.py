@@ -30,6 +30,7 @@ SETUP_G, SETUP_ETA, SETUP_U, SETUP_K = 0, 1, 2, 3
 EXPORTED_SYMBOLS = (
     "quapi_footprint", "quapi_paper_pmc_bytes", "quapi_create", "quapi_propagate",
     "quapi_propagate_async", "quapi_step_count", "quapi_fused_steps", "quapi_set_fused_steps",
+    "quapi_mirror", "quapi_set_mirror",
     "quapi_get_setup", "quapi_read_tensor",
     "quapi_tensor_size", "quapi_set_timing", "quapi_get_timing", "quapi_destroy",
     "quapi_last_error",
@@ -77,6 +78,8 @@ def load_library() -> ctypes.CDLL:
     lib.quapi_step_count.argtypes = [vp, ip]
     lib.quapi_fused_steps.argtypes = [vp, ip]
     lib.quapi_set_fused_steps.argtypes = [vp, ctypes.c_int]
+    lib.quapi_mirror.argtypes = [vp, ip]
+    lib.quapi_set_mirror.argtypes = [vp, ctypes.c_int]
     lib.quapi_get_setup.argtypes = [vp, ctypes.c_int, _DP, sz]
     lib.quapi_read_tensor.argtypes = [vp, sz, sz, _DP]
     lib.quapi_tensor_size.argtypes = [vp, ctypes.POINTER(sz)]
@@ -226,6 +229,17 @@ class Context:
         """Pin the full-window steps per launch (1, 2, 3; 0 = default)."""
         h = self._live()
         _check(lib().quapi_set_fused_steps(h, int(steps)), h)
+
+    def mirror(self) -> bool:
+        """Whether the three-step kernel runs in mirror mode (half of the
+        tensor's entries read and written per pass)."""
+        v = ctypes.c_int(0)
+        _check(lib().quapi_mirror(self._live(), ctypes.byref(v)))
+        return bool(v.value)
+
+    def set_mirror(self, enable: bool) -> None:
+        h = self._live()
+        _check(lib().quapi_set_mirror(h, int(bool(enable))), h)
 
     def step_count(self) -> int:
         v = ctypes.c_int(0)

@@ -1,0 +1,140 @@
+"""GPU parity of the three-step kernel's mirror mode (half of the tensor's
+entries read and written per pass; the rest are their mirrors' conjugates).
+
+Each run is compared with the oracle (complex128: per step
+max|drho| <= 1e-12 max|rho|; complex64 storage 1e-5 / 1e-6 absolute) and
+with the same run with mirror mode off.  The tensor read back after mirror
+passes (the mirrored half filled in by the completion kernel) is compared
+entry by entry with the full-tensor run.
+"""
+import numpy as np
+import pytest
+
+from oracle import run as orun
+from paper_1205_6872_amd import quapi as Q
+from paper_1205_6872_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_C128 = 1e-12
+
+
+def rel_err_per_step(a, b):
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)
+
+
+def hermitian_rho0(seed):
+    rng = np.random.default_rng(seed)
+    r = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+    r = r @ r.conj().T
+    r = r / np.trace(r)
+    r[1, 0] = np.conj(r[0, 1])                     # exactly Hermitian
+    r[0, 0], r[1, 1] = r[0, 0].real, r[1, 1].real
+    return r
+
+
+def case(L, seed):
+    rng = np.random.default_rng(100 + seed)
+    return W.spin_boson_l7().with_(L=L, H=W.random_hermitian(rng, 2), rho0=hermitian_rho0(seed), xi=0.4)
+
+
+def run(w, n, mirror, dtype="c128", chunks=None):
+    with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
+        ctx.set_fused_steps(3)
+        ctx.set_mirror(mirror)
+        assert ctx.mirror() == mirror
+        if chunks is None:
+            rho = ctx.propagate(n, list(range(n + 1)))
+        else:
+            parts = [ctx.propagate(0, [0])]
+            for k in chunks:
+                parts.append(ctx.propagate(k))
+            rho = np.concatenate(parts)
+        size = ctx.tensor_size()
+        A = ctx.read_tensor(0, size)
+    return rho, A
+
+
+@pytest.mark.parametrize("L,seed,n", [(4, 1, 40), (5, 2, 45), (7, 3, 60), (8, 4, 50), (10, 5, 31)])
+def test_mirror_mode_against_oracle_and_full_mode(L, seed, n):
+    w = case(L, seed)
+    print(f"L={L} seed={seed} steps={n}", flush=True)
+    rho_m, A_m = run(w, n, True)
+    rho_f, A_f = run(w, n, False)
+    o = orun.oracle_run(w, n)
+    assert rel_err_per_step(rho_m, o).max() <= TOL_C128
+    assert rel_err_per_step(rho_m, rho_f).max() <= 1e-13
+    scale = np.abs(A_f).max()
+    assert np.abs(A_m - A_f).max() <= 1e-13 * scale
+    x = np.arange(len(A_m))
+    mirror = ((x & 0x5555555555555555) << 1) | ((x >> 1) & 0x5555555555555555)
+    pair = mirror != x
+    if (n - L) % 3 == 0:
+        # the last step was a mirror pass: the filled-in half is exactly the conjugate
+        assert np.array_equal(A_m[mirror[pair]], np.conj(A_m[pair]))
+    else:
+        # the call ended inside a group: its last steps ran singly on the whole tensor
+        assert np.abs(A_m[mirror[pair]] - np.conj(A_m[pair])).max() <= 1e-13 * scale
+    assert np.abs(A_m[~pair].imag).max() <= 1e-13 * scale       # entries that are their own mirror are real
+
+
+@pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c64f64", 1e-6)])
+def test_mirror_mode_complex64_tiers(dtype, tol):
+    w = case(7, 6)
+    n = 90
+    rho_m, _ = run(w, n, True, dtype=dtype)
+    o = orun.oracle_run(w, n)
+    assert np.abs(rho_m - o).max() <= tol
+    tr = np.trace(rho_m, axis1=1, axis2=2)
+    assert np.abs(tr - 1).max() <= 1e-6
+
+
+def test_calls_ending_inside_groups_fill_the_mirrored_half_first():
+    # single steps at the call ends read the whole tensor after mirror passes
+    w = case(6, 7)
+    chunks = [7, 4, 5, 1, 9, 2, 13, 3]
+    n = sum(chunks)
+    rho_m, A_m = run(w, n, True, chunks=chunks)
+    rho_f, A_f = run(w, n, False, chunks=chunks)
+    o = orun.oracle_run(w, n)
+    assert rel_err_per_step(rho_m, o).max() <= TOL_C128
+    assert rel_err_per_step(rho_m, rho_f).max() <= 1e-13
+    assert np.abs(A_m - A_f).max() <= 1e-13 * np.abs(A_f).max()
+
+
+def test_switching_mirror_mode_mid_run():
+    w = case(7, 8)
+    n = 60
+    with Q.create(Q.params_from(w)) as ctx:
+        ctx.set_fused_steps(3)
+        parts = [ctx.propagate(0, [0]), ctx.propagate(22)]          # ends on a group boundary
+        ctx.set_mirror(False)
+        parts.append(ctx.propagate(18))
+        ctx.set_mirror(True)
+        parts.append(ctx.propagate(20))
+        rho = np.concatenate(parts)
+    assert rel_err_per_step(rho, orun.oracle_run(w, n)).max() <= TOL_C128
+
+
+def test_defaults_and_refusals():
+    w = case(7, 9)
+    with Q.create(Q.params_from(w)) as ctx:
+        assert ctx.mirror()                                        # M = 2, L >= 4, Hermitian rho0
+    rho0 = np.array([[0.7, 0.2 + 0.1j], [0.05 - 0.3j, 0.3]])      # not Hermitian
+    wn = w.with_(rho0=rho0)
+    with Q.create(Q.params_from(wn)) as ctx:
+        assert not ctx.mirror()
+        with pytest.raises(Q.QuapiError) as ei:
+            ctx.set_mirror(True)
+        assert ei.value.status == Q.ERR_INVALID
+        ctx.set_fused_steps(3)
+        rho = ctx.propagate(40, list(range(41)))
+    assert rel_err_per_step(rho, orun.oracle_run(wn, 40)).max() <= TOL_C128
+    for L, M in [(3, 2), (4, 3)]:
+        ww = W.three_site_l8().with_(L=L) if M == 3 else w.with_(L=L)
+        with Q.create(Q.params_from(ww)) as ctx:
+            assert not ctx.mirror()
+            with pytest.raises(Q.QuapiError):
+                ctx.set_mirror(True)
