@@ -6,8 +6,8 @@ default, rho(t_n) extracted at every step ('allPoints').  Inputs are
 synthetic (seeded parameters, no dataset).
 
 A timed "step" is one full-window propagation step.  For M = 2 the library
-fuses consecutive steps into one kernel launch (three at complex128 and at
-complex64 with FP32 arithmetic from L = 13, else two): it reads the tensor once, keeps the intermediate tensors
+fuses consecutive steps into one kernel launch (three at L = 15 in every
+precision mode): it reads the tensor once, keeps the intermediate tensors
 in registers, writes the tensor of the group's last step once, and produces
 per-block partial sums of rho at every step of the group in the same pass; a
 small finalize kernel on a side stream sums them.  So one launch moves
@@ -130,7 +130,7 @@ def kernel_name(tier: str, steps_per_launch: float, mirror: bool = False) -> str
 
 
 # The dominant kernel of each tier at M = 2, L = 15 and the sources it is built from.
-TIER_KERNEL = {"c128": "step3", "c64": "step3", "c64f64": "step2"}
+TIER_KERNEL = {"c128": "step3", "c64": "step3", "c64f64": "step3"}
 KERNEL_SOURCES = {"step2": ("quapi_step2.hip", "quapi_device.h", "quapi_internal.h"),
                   "step3": ("quapi_step3.hip", "quapi_device.h", "quapi_internal.h")}
 

@@ -146,8 +146,8 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
  * Results are deterministic.  For M = 2 full-window steps run in fused groups of
  * F = quapi_fused_steps() steps fixed by the global step number: (L+1 .. L+F),
  * (L+F+1 .. L+2F), ... (by default F = 3 at complex128 and QUAPI_C64 from
- * L = 13, and at complex128 from L = 12 where mirror mode is available, see
- * quapi_set_mirror; F = 2 otherwise with L >= 3); a sequence of calls gives bit-identical results to one call when
+ * L = 13; where mirror mode is available (see quapi_set_mirror) at complex128
+ * from L = 12 and at QUAPI_C64_F64 from L = 14; F = 2 otherwise with L >= 3); a sequence of calls gives bit-identical results to one call when
  * every call ends at step c <= L or with c - L a multiple of F (otherwise the
  * steps of a split group run one by one and round differently, within 1e-15). */
 quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
@@ -189,8 +189,9 @@ quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries);
 quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps);
 
 /* Choose the full-window steps per launch: 1, 2 (N = 4, L >= 3), 3 (N = 4,
- * L >= 4), or 0 for the default (3 at complex128 and QUAPI_C64 from L = 13 -- from
- * L = 12 at complex128 where mirror mode is available -- else 2 where
+ * L >= 4), or 0 for the default (3 at complex128 and QUAPI_C64 from L = 13 -- where
+ * mirror mode is available from L = 12 at complex128 and from L = 14 at
+ * QUAPI_C64_F64 -- else 2 where
  * available, else 1; always 1 for a driven context).  Every choice gives the same results to within rounding
  * (the fused kernels apply the same factors in another order); use it to pin
  * the kernel, e.g. in tests.  It takes effect from the next call.

@@ -101,18 +101,19 @@ bool fused_ok(int N, int L) { return N == 4 && L >= 3; }
 // step-n group factors at lags L-1 and L-2 >= 2, for the same reason).
 bool triple_ok(int N, int L) { return N == 4 && L >= 4; }
 
-// Full-window steps per launch chosen by default: three at complex128 and at
-// complex64 with FP32 arithmetic from L = 13 (4^10 items and more; the step is
-// HBM bound there, and a third step in registers saves a third of the
-// traffic), and at complex128 from L = 12 where the three-step kernel runs
-// in mirror mode (half the entries); two otherwise.  A three-step item runs
-// one or two waves per SIMD through three dependent stages, so with fewer
+// Full-window steps per launch chosen by default: three from L = 13 at
+// complex128 and at complex64 with FP32 arithmetic (4^10 items and more; the
+// step is HBM bound there, and a third step in registers saves a third of
+// the traffic); where the three-step kernel runs in mirror mode (half the
+// entries, and half the arithmetic) from L = 12 at complex128 and from L = 14
+// with complex64 storage and FP64 arithmetic; two otherwise.  A three-step
+// item runs one wave per SIMD through three dependent stages, so with fewer
 // items than that the two-step kernel finishes first; with complex64 storage
-// and FP64 arithmetic the three-step kernel is bound by its arithmetic and the
-// two-step one is not.
+// and FP64 arithmetic the full-tensor three-step kernel is bound by its
+// arithmetic.
 int fusion_width(int N, int L, int prec, bool mirror) {
-    const int from = prec == kPrecC128 && mirror ? 12 : 13;
-    if (triple_ok(N, L) && L >= from && (prec == kPrecC128 || prec == kPrecC64)) return 3;
+    const int from = prec == kPrecC128 ? (mirror ? 12 : 13) : prec == kPrecC64 ? 13 : (mirror ? 14 : 1 << 20);
+    if (triple_ok(N, L) && L >= from) return 3;
     return fused_ok(N, L) ? 2 : 1;
 }
 
