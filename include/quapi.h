@@ -199,21 +199,22 @@ quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps);
  * another call runs on the context. */
 quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps);
 
-/* Mirror mode of the three-step kernel (M = 2, L >= 4).  Swapping the forward
- * and backward path of every point maps the path sum of Sec. II to its complex
+/* Mirror mode of the full-window kernels: the three-step kernel (M = 2,
+ * L >= 4) and the M = 4 MFMA step (L >= 2).  Swapping the forward and
+ * backward path of every point maps the path sum of Sec. II to its complex
  * conjugate: K = U (x) U* and every influence factor go to their conjugates,
  * and so does rho(0) when it is Hermitian.  So the tensor entry of the
- * mirrored paths is the conjugate of the entry itself, and a three-step pass
- * reads and writes only the entries not above their mirror (flat index, each
- * digit (a, b) -> (b, a)) -- about half the bytes.  rho at every step is
- * unchanged up to rounding.  The entries above their mirror are filled in
- * before anything that reads the whole tensor (single steps, the two-step
+ * mirrored paths is the conjugate of the entry itself, and a pass reads and
+ * writes only the entries not above their mirror (flat index, each digit
+ * (a, b) -> (b, a)) -- about half the bytes.  rho at every step is unchanged
+ * up to rounding.  The entries above their mirror are filled in before
+ * anything that reads the whole tensor (single steps at M = 2, the two-step
  * kernel, quapi_read_tensor).  On by default where available.
  *   quapi_mirror:      *enabled = 1 while on.
  *   quapi_set_mirror:  enable = 0 turns it off; 1 turns it on.
  * Errors: QUAPI_ERR_INVALID for NULL arguments, or enable = 1 where it is not
- * available (M != 2, L < 4, or rho0 not exactly Hermitian); QUAPI_ERR_STATE
- * while another call runs on the context. */
+ * available (M other than 2 or 4, L below the limits, or rho0 not exactly
+ * Hermitian); QUAPI_ERR_STATE while another call runs on the context. */
 quapi_status quapi_mirror(const quapi_ctx *ctx, int *enabled);
 quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable);
 

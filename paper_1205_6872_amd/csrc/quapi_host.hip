@@ -276,10 +276,11 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_Ht, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
-    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_pairs, off_sink;
+    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_blk1, off_pairs, off_sink;
     size_t total;
     int n_panels, n_tables, partial_blocks;
     int n_canon3, n_diag3, parts3, span3;   // mirror mode of the three-step kernel (high-digit blocks)
+    int n_canon1, n_diag1, parts1, span1;   // mirror mode of the N = 16 MFMA step (main split)
     DigitSplit main_split;   // digit split of the full-window steps
     DigitSplit split2;       // digit split of the fused two-step kernel
     DigitSplit split3;       // digit split of the three-step kernel
@@ -315,6 +316,21 @@ Layout make_layout(const quapi_params &p, int n_panels) {
         l.parts3 = (passes + 3) / 4;
         l.span3 = ((passes + l.parts3 - 1) / l.parts3) * rows_per_pass;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon3 + l.n_diag3 * (l.parts3 + 1));
+    }
+    if (N == 16 && l.main_split.R == 16) {
+        // the MFMA step: the same partition over its block digits; a block
+        // sweeps its rows with its 4 waves
+        const DigitSplit &s1 = l.main_split;
+        for (int h = 0; h < s1.grid; ++h) {
+            const long long hb = mirror16(h);
+            if (h < hb) ++l.n_canon1;
+            else if (h == hb) ++l.n_diag1;
+        }
+        const int rows_per_pass = kBlock / 64;
+        const int passes = (s1.Q + rows_per_pass - 1) / rows_per_pass;
+        l.parts1 = (passes + 3) / 4;
+        l.span1 = ((passes + l.parts1 - 1) / l.parts1) * rows_per_pass;
+        l.partial_blocks = std::max(l.partial_blocks, l.n_canon1 + l.n_diag1 * (l.parts1 + 1));
     }
     l.a_bytes = entries * cs;
     size_t off = 0;
@@ -358,6 +374,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_plan3 = take(triple ? (size_t)6 * N * (s3.R + s3.Q + s3.grid) * 16 : 0);
     l.off_coef3 = take(triple ? (size_t)kC3Count * 16 : 0);
     l.off_blk3 = take(triple ? (size_t)(l.n_canon3 + l.n_diag3) * sizeof(int) : 0);
+    l.off_blk1 = take((size_t)(l.n_canon1 + l.n_diag1) * sizeof(int));
     l.total = off;
     return l;
 }
@@ -416,6 +433,8 @@ struct quapi_ctx {
     bool half_cur = false;
     int *blk3 = nullptr;          // high-digit values: n_canon3 below their mirror, then n_diag3 equal
     std::vector<int> blk3_h;
+    int *blk1 = nullptr;          // the same for the N = 16 MFMA step (n_canon1, n_diag1)
+    std::vector<int> blk1_h;
     double2 *plan3 = nullptr;
     void *coef3 = nullptr;
     std::vector<double> rho0_h;
@@ -611,7 +630,7 @@ quapi_status join_side(quapi_ctx *c) {
 // step ran in mirror mode, fill the entries above their mirror.
 quapi_status ensure_full(quapi_ctx *c) {
     if (!c->half_cur) return QUAPI_OK;
-    hipError_t e = launch_mirror_complete(c->prec, c->A[c->cur], ipow_ll(c->N, c->L), c->stream);
+    hipError_t e = launch_mirror_complete(c->N, c->prec, c->A[c->cur], ipow_ll(c->N, c->L), c->stream);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "mirror completion launch: %s", hipGetErrorString(e));
     c->half_cur = false;
     return QUAPI_OK;
@@ -644,11 +663,56 @@ quapi_status finalize_side(quapi_ctx *c, const int *slots, int n, int grid) {
 
 // Enqueue step n (1-based); with rho, also rho(t_n) into the sink's next slot.
 // The finalize runs on the side stream, overlapped with the next step.
+// The N = 16 MFMA step runs in mirror mode (half of the entries).
+bool mirror16_on(const quapi_ctx *c) { return c->mirror && c->N == 16; }
+
+// Launch a full-window single step with the arguments of prepare_step: one
+// launch, or in mirror mode (N = 16) the launches over the high-digit values
+// below their mirror (mode 1) and equal to it (modes 2, 3).  *rows: the rho
+// partial rows written.
+hipError_t launch_full_step(quapi_ctx *c, bool rho, StepArgs a, int grid, int *rows) {
+    if (!mirror16_on(c)) {
+        a.mode = 0;
+        *rows = grid;
+        return launch_step(c->N, c->prec, rho, false, a, grid, c->stream);
+    }
+    const Layout &l = c->lay;
+    hipError_t e = hipSuccess;
+    if (l.n_canon1 > 0) {
+        a.mode = 1;
+        a.blk_hi = c->blk1;
+        a.n_blk = l.n_canon1;
+        a.parts = 1;
+        a.part_base = 0;
+        e = launch_step(c->N, c->prec, rho, false, a, grid, c->stream);
+    }
+    if (e == hipSuccess && l.n_diag1 > 0) {
+        a.mode = 2;
+        a.blk_hi = c->blk1 + l.n_canon1;
+        a.n_blk = l.n_diag1 * l.parts1;
+        a.parts = l.parts1;
+        a.q_span = l.span1;
+        a.part_base = l.n_canon1;
+        e = launch_step(c->N, c->prec, rho, false, a, grid, c->stream);
+    }
+    if (e == hipSuccess && l.n_diag1 > 0) {
+        a.mode = 3;
+        a.blk_hi = c->blk1 + l.n_canon1;
+        a.n_blk = l.n_diag1;
+        a.parts = 1;
+        a.part_base = l.n_canon1 + l.n_diag1 * l.parts1;
+        e = launch_step(c->N, c->prec, rho, false, a, grid, c->stream);
+    }
+    *rows = l.n_canon1 + l.n_diag1 * (l.parts1 + 1);
+    return e;
+}
+
 quapi_status enqueue_step(quapi_ctx *c, int n, bool rho) {
-    if (quapi_status fs = ensure_full(c); fs != QUAPI_OK) return fs;
     StepPlan sp;
     quapi_status st = prepare_step(c, n, rho, &sp);
     if (st != QUAPI_OK) return st;
+    const bool half = !sp.grow && mirror16_on(c);       // reads and writes the kept half only
+    if (!half && (st = ensure_full(c)) != QUAPI_OK) return st;
     StepArgs &a = sp.args;
     a.a_in = c->A[c->cur];
     a.a_out = c->A[1 - c->cur];
@@ -665,17 +729,20 @@ quapi_status enqueue_step(quapi_ctx *c, int n, bool rho) {
         e1 = take_event(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
-    hipError_t e = launch_step(c->N, c->prec, rho, sp.grow, a, sp.split.grid, c->stream);
+    int rows = sp.split.grid;
+    hipError_t e = sp.grow ? launch_step(c->N, c->prec, rho, true, a, sp.split.grid, c->stream)
+                           : launch_full_step(c, rho, a, sp.split.grid, &rows);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "step kernel launch: %s", hipGetErrorString(e));
     if (c->timing && e0 && e1) {
         (void)hipEventRecord(e1, c->stream);
         c->recs.push_back({sp.grow ? 1 : 0, e0, e1, sp.grow ? 0 : 1});
     }
     if (rho) {
-        st = finalize_side(c, &slot, 1, sp.split.grid);
+        st = finalize_side(c, &slot, 1, rows);
         if (st != QUAPI_OK) return st;
     }
     c->cur = 1 - c->cur;
+    c->half_cur = half;
     c->step = n;
     return QUAPI_OK;
 }
@@ -999,9 +1066,10 @@ quapi_status build_graph(quapi_ctx *c, bool rho, int width, int par, hipGraphExe
             a.a_in = c->A[k];
             a.a_out = c->A[1 - k];
             a.partials = c->partials[k];
-            e = launch_step(c->N, c->prec, rho, false, a, sp.split.grid, c->stream);
+            int rows = 0;
+            e = launch_full_step(c, rho, a, sp.split.grid, &rows);
             if (e == hipSuccess && rho)
-                e = launch_rho_finalize(c->N, c->partials[k], sp.split.grid, c->pairs, c->sink, c->stream);
+                e = launch_rho_finalize(c->N, c->partials[k], rows, c->pairs, c->sink, c->stream);
         }
     }
     hipError_t e2 = hipStreamEndCapture(c->stream, &g);
@@ -1142,9 +1210,11 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
                     c->graph_failed = true;   // stay on direct launches
                 } else {
                     st = join_side(c);        // the graph reuses partial buffers 0 and 1
-                    if (st == QUAPI_OK) st = ensure_full(c);
+                    const bool half = !fused && mirror16_on(c);
+                    if (st == QUAPI_OK && !half) st = ensure_full(c);
                     if (st != QUAPI_OK) return st;
                     HIP_TRY(c, hipGraphLaunch(gx, c->stream));
+                    c->half_cur = half;
                     if (fused) c->cur = 1 - c->cur;
                     c->step = n + 1;
                     done = true;
@@ -1332,6 +1402,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->plan3 = (double2 *)(w + lay.off_plan3);
     c->coef3 = w + lay.off_coef3;
     c->blk3 = (int *)(w + lay.off_blk3);
+    c->blk1 = (int *)(w + lay.off_blk1);
     c->n_H = p->n_H;
     c->Ht_d = (const double2 *)(w + lay.off_Ht);
     c->coef = w + lay.off_coef;
@@ -1344,18 +1415,26 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->H_h.assign(p->H, p->H + 2 * M * M);
     if (p->n_H > 0) c->Ht_h.assign(p->H_t, p->H_t + (size_t)2 * M * M * p->n_H);
     c->rho0_h.assign(p->rho0, p->rho0 + 2 * N);
-    if (triple_ok(N, L)) {
-        for (int pass = 0; pass < 2; ++pass)
-            for (int h = 0; h < lay.split3.grid; ++h)
-                if (pass == 0 ? h < mirror4(h) : h == mirror4(h)) c->blk3_h.push_back(h);
+    {
         // the path sum maps to its conjugate under the mirror only if rho0 does
         bool herm = true;
         for (int a = 0; a < M; ++a)
             for (int b = 0; b < M; ++b)
                 herm = herm && p->rho0[2 * (a * M + b)] == p->rho0[2 * (b * M + a)] &&
                        p->rho0[2 * (a * M + b) + 1] == -p->rho0[2 * (b * M + a) + 1];
-        c->mirror_ok = herm;
-        c->mirror = herm;
+        if (triple_ok(N, L)) {
+            for (int pass = 0; pass < 2; ++pass)
+                for (int h = 0; h < lay.split3.grid; ++h)
+                    if (pass == 0 ? h < mirror4(h) : h == mirror4(h)) c->blk3_h.push_back(h);
+            c->mirror_ok = herm;
+        }
+        if (N == 16 && lay.main_split.R == 16) {
+            for (int pass = 0; pass < 2; ++pass)
+                for (int h = 0; h < lay.main_split.grid; ++h)
+                    if (pass == 0 ? h < mirror16(h) : h == mirror16(h)) c->blk1_h.push_back(h);
+            c->mirror_ok = herm;
+        }
+        c->mirror = c->mirror_ok;
     }
     c->fuse = c->n_H > 0 ? 1 : fusion_width(N, L, c->prec, c->mirror_ok);
     c->pa_h = std::move(pa);
@@ -1379,6 +1458,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     if (e == hipSuccess && c->n_H > 0) e = up(lay.off_Ht, c->Ht_h.data(), c->Ht_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_rho0, c->rho0_h.data(), (size_t)N * 16);
     if (e == hipSuccess && !c->blk3_h.empty()) e = up(lay.off_blk3, c->blk3_h.data(), c->blk3_h.size() * sizeof(int));
+    if (e == hipSuccess && !c->blk1_h.empty()) e = up(lay.off_blk1, c->blk1_h.data(), c->blk1_h.size() * sizeof(int));
     if (e == hipSuccess) e = up(lay.off_pa, c->pa_h.data(), c->pa_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_ph, c->ph_h.data(), c->ph_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_pseg, c->pseg_h.data(), c->pseg_h.size() * 4);
@@ -1501,7 +1581,8 @@ quapi_status quapi_mirror(const quapi_ctx *ctx, int *enabled) {
 quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable) {
     if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
     if (enable && !ctx->mirror_ok)
-        return fail(ctx, QUAPI_ERR_INVALID, "mirror mode needs M = 2, L >= 4 and an exactly Hermitian rho0");
+        return fail(ctx, QUAPI_ERR_INVALID,
+                    "mirror mode needs M = 2 and L >= 4, or M = 4 and L >= 2, and an exactly Hermitian rho0");
     if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
     if ((enable != 0) == ctx->mirror) return QUAPI_OK;
     // the captured three-step graphs hold the launches of the old mode
@@ -1511,6 +1592,10 @@ quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable) {
             if (g) (void)hipGraphExecDestroy(g);
             g = nullptr;
         }
+    for (auto &g : ctx->graph1) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
     ctx->mirror = enable != 0;
     return QUAPI_OK;
 }

@@ -61,6 +61,13 @@ struct StepArgs {
     int old_tab, oldf_tab;      // bank indices of the oldest-point tables
     int16_t tab[kMaxL];         // bank index of the interior table for digit j
     int16_t tabf[kMaxL];        // bank index of the final-point table for digit j
+    // Mirror mode of the N = 16 MFMA step (as for the three-step kernel):
+    // mode 1 the high-digit values blk_hi[..] below their mirror, mode 2 those
+    // equal to it in `parts` blocks of q_span sweep rows (items below their
+    // mirror), mode 3 the same values, the items that are their own mirror;
+    // rho partials at row part_base + block.  Mode 0: every block.
+    const int *blk_hi;
+    int n_blk, parts, q_span, part_base, mode;
 };
 
 // Two consecutive full-window steps n, n+1 (n > L, N = 4) in one pass:
@@ -130,6 +137,11 @@ struct Step3Args {
 // Hermitian rho(0) do), so A[mirror(x)] = conj(A[x]) for every entry x.
 __host__ __device__ constexpr long long mirror4(long long x) {
     return ((x & 0x5555555555555555LL) << 1) | ((x >> 1) & 0x5555555555555555LL);
+}
+// The same for N = 16 (M = 4): digit o = 4a + b -> 4b + a swaps the two bit
+// pairs of each base-16 digit.
+__host__ __device__ constexpr long long mirror16(long long x) {
+    return ((x & 0x3333333333333333LL) << 2) | ((x >> 2) & 0x3333333333333333LL);
 }
 
 // Coefficients of the three-step kernel (compute precision), the four of one
@@ -208,8 +220,8 @@ size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q);
 hipError_t launch_step2(int prec, bool with_rho, const Step2Args &a, hipStream_t st);
 hipError_t launch_step2_coef(const CoefArgs &a, hipStream_t st);
 hipError_t launch_step3(int prec, bool with_rho, const Step3Args &a, hipStream_t st);
-// Fill every entry above its mirror (N = 4) with the conjugate of the mirror.
-hipError_t launch_mirror_complete(int prec, void *a, long long entries, hipStream_t st);
+// Fill every entry above its mirror (N = 4 or 16) with the conjugate of the mirror.
+hipError_t launch_mirror_complete(int N, int prec, void *a, long long entries, hipStream_t st);
 hipError_t launch_step3_coef(const Coef3Args &a, hipStream_t st);
 size_t step3_lds_bytes(int prec, bool with_rho, int R, int Q);
 size_t step2_lds_bytes(int prec, bool with_rho, int R, int Q);

@@ -683,6 +683,31 @@ __global__ void __launch_bounds__(kBlock) plan_tables_kernel(const PlanArgs a) {
 // imaginary parts of outputs o = 8(b % 2) + 2g + v / 2.  Lane j + 16g therefore
 // holds outputs o = 2g, 2g+1 (block 0), 8+2g, 9+2g (block 1) of item j, and the
 // same four with the final-point table in blocks 2, 3.
+//
+// MODE 1, 2, 3 (mirror mode, as in the three-step kernel): an entry and its
+// mirror (every digit o = 4a + b -> 4b + a) are conjugates, so only the items
+// not above their mirror run, each output entry above its mirror is stored as
+// the conjugate at the mirrored address, and an item that is its own mirror
+// (every digit diagonal) reads its input slots above their mirror from the
+// mirrored slot, conjugated.  Mode 1 runs the blocks whose high digits are
+// below their mirror; mode 2 those with all high digits diagonal, the items
+// below their mirror; mode 3 the items that are their own mirror.  The MFMA
+// runs on the whole wave, so a lane whose item does not run feeds zeros and
+// stores nothing.  rho: a lane holds outputs of one lane group only, so the
+// mirrored item's terms, conj(S[mirror(o)]), are added to each block's sums
+// S[o] (modes 1, 2), whose items are never their own mirror.
+__device__ __forceinline__ int mirror_digit16(int o) { return ((o & 3) << 2) | (o >> 2); }
+template <typename C>
+__device__ __forceinline__ C cconj16(C v) {
+    v.y = -v.y;
+    return v;
+}
+// Sweep index with all base-16 digits diagonal: base-4 digit d -> 5 d.
+__device__ __forceinline__ int diagonal_digits16(int x, int nd) {
+    int out = 0;
+    for (int k = 0; k < nd; ++k) out += (5 * ((x >> (2 * k)) & 3)) << (4 * k);
+    return out;
+}
 struct Step16Lds {
     unsigned tq, tqf, red, total;
 };
@@ -712,7 +737,7 @@ template <> struct Mfma16<double> {
     }
 };
 
-template <typename S, typename T, bool RHO>
+template <typename S, typename T, bool RHO, int MODE>
 __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
     constexpr int N = 16, NB = RHO ? 4 : 2;
     using C = typename Cx<T>::type;
@@ -726,7 +751,9 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
     double2 *s_red = (double2 *)(smem + lay.red);        // [waves][N]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int j = lane & 15, g = lane >> 4;
-    const long long blk = blockIdx.x;
+    const long long blk = MODE == 0   ? (long long)blockIdx.x
+                          : MODE == 2 ? (long long)a.blk_hi[blockIdx.x / a.parts]
+                                      : (long long)a.blk_hi[blockIdx.x];     // high digits
 
     for (int idx = t; idx < N * Q; idx += kBlock) {
         const int o = idx / Q;
@@ -769,11 +796,31 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
     const long long mc = a.m_count;
     const S *__restrict__ ain = (const S *)a.a_in;
     CS *__restrict__ aout = (CS *)a.a_out;
-    for (int qm = wave; qm < Q; qm += kBlock / 64) {
+    // sweep rows: all (mode 0, 1), a part of them (mode 2), or those whose
+    // digits are all diagonal (mode 3)
+    const int dm = (31 - __clz(Q)) >> 2;
+    const int part = MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
+    const int i0 = (MODE == 2 ? part * a.q_span : 0) + wave;
+    const int i1 = MODE == 3 ? (1 << (2 * dm)) : MODE == 2 ? min(Q, (part + 1) * a.q_span) : Q;
+    for (int it = i0; it < i1; it += kBlock / 64) {
+        const int qm = MODE == 3 ? diagonal_digits16(it, dm) : it;
         const long long m = m0 + 16LL * qm + j;
+        const long long mb = MODE == 0 ? m : mirror16(m);
+        const bool run = MODE == 0 || MODE == 1 || (MODE == 2 ? m < mb : j % 5 == 0);
         T xw[8];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) xw[s] = (T)ain[32 * m + 8 * g + s];
+        for (int s = 0; s < 8; ++s) {
+            if (MODE == 3) {
+                // word 8g + s is part (w & 1) of slot i = w / 2; slots above
+                // their mirror come from the mirrored slot, conjugated
+                const int w = 8 * g + s, i = w >> 1, ib = mirror_digit16(i);
+                const bool flip = ib < i;
+                const T v = run ? (T)ain[32 * m + (flip ? 2 * ib + (w & 1) : w)] : T(0);
+                xw[s] = flip && (w & 1) ? -v : v;
+            } else {
+                xw[s] = (MODE != 2 || run) ? (T)ain[32 * m + 8 * g + s] : T(0);
+            }
+        }
         V4 d[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) d[b] = V4{0, 0, 0, 0};
@@ -789,8 +836,11 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
             z.x = d[b][e];
             z.y = d[b][e + 1];
             const C p = cmul(plo[q], s_tq[oo[q] * Q + qm]);
-            aout[m + mc * oo[q]] = conv<CS>(cmul(p, z));
-            if (RHO) {
+            const C v = cmul(p, z);
+            const int ob = mirror_digit16(oo[q]);
+            if (MODE == 0 || (run && ob >= oo[q])) aout[m + mc * oo[q]] = conv<CS>(v);
+            else if (MODE != 3 && run) aout[mb + mc * ob] = conv<CS>(cconj16(v));
+            if (RHO && run) {
                 C zf;
                 zf.x = d[2 + b][e];
                 zf.y = d[2 + b][e + 1];
@@ -813,12 +863,19 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
         }
         __syncthreads();
         if (t < N) {
-            double2 s = make_double2(0.0, 0.0);
+            double2 s = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+            const int tb = mirror_digit16(t);
             for (int w = 0; w < kBlock / 64; ++w) {
                 s.x += s_red[w * N + t].x;
                 s.y += s_red[w * N + t].y;
+                sb.x += s_red[w * N + tb].x;
+                sb.y += s_red[w * N + tb].y;
             }
-            a.partials[blk * N + t] = s;
+            if (MODE == 1 || MODE == 2) {
+                s.x += sb.x;
+                s.y -= sb.y;
+            }
+            a.partials[((size_t)a.part_base + blockIdx.x) * N + t] = s;
         }
     }
 }
@@ -827,7 +884,14 @@ template <typename S, typename T, bool RHO>
 hipError_t launch_step16_t(const StepArgs &a, int grid, hipStream_t st) {
     using C = typename Cx<T>::type;
     const Step16Lds lay = step16_lds_layout((int)sizeof(C), RHO, a.Q);
-    hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO>), dim3(grid), dim3(kBlock), lay.total, st, a);
+    const dim3 b(kBlock);
+    switch (a.mode) {
+    case 0: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 0>), dim3(grid), b, lay.total, st, a); break;
+    case 1: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 1>), dim3(a.n_blk), b, lay.total, st, a); break;
+    case 2: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 2>), dim3(a.n_blk), b, lay.total, st, a); break;
+    case 3: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 3>), dim3(a.n_blk), b, lay.total, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -449,11 +449,11 @@ hipError_t launch_step3_t(const Step3Args &a, hipStream_t st) {
 }
 
 // One thread per entry x: entries above their mirror take the conjugate of it.
-template <typename CS>
+template <int N, typename CS>
 __global__ void __launch_bounds__(kBlock) mirror_complete_kernel(CS *__restrict__ a, long long entries) {
     for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < entries;
          x += (long long)gridDim.x * kBlock) {
-        const long long xb = mirror4(x);
+        const long long xb = N == 4 ? mirror4(x) : mirror16(x);
         if (xb < x) a[x] = cconj(a[xb]);
     }
 }
@@ -476,15 +476,18 @@ hipError_t launch_step3(int prec, bool with_rho, const Step3Args &a, hipStream_t
     }
 }
 
-hipError_t launch_mirror_complete(int prec, void *a, long long entries, hipStream_t st) {
+hipError_t launch_mirror_complete(int N, int prec, void *a, long long entries, hipStream_t st) {
     const long long blocks = std::min<long long>((entries + kBlock - 1) / kBlock, 1 << 20);
     if (blocks < 1) return hipSuccess;
-    if (prec == kPrecC128)
-        hipLaunchKernelGGL(mirror_complete_kernel<double2>, dim3((unsigned)blocks), dim3(kBlock), 0, st,
-                           (double2 *)a, entries);
-    else
-        hipLaunchKernelGGL(mirror_complete_kernel<float2>, dim3((unsigned)blocks), dim3(kBlock), 0, st,
-                           (float2 *)a, entries);
+    if (N != 4 && N != 16) return hipErrorInvalidValue;
+    const dim3 g((unsigned)blocks), b(kBlock);
+    if (prec == kPrecC128) {
+        if (N == 4) hipLaunchKernelGGL((mirror_complete_kernel<4, double2>), g, b, 0, st, (double2 *)a, entries);
+        else hipLaunchKernelGGL((mirror_complete_kernel<16, double2>), g, b, 0, st, (double2 *)a, entries);
+    } else {
+        if (N == 4) hipLaunchKernelGGL((mirror_complete_kernel<4, float2>), g, b, 0, st, (float2 *)a, entries);
+        else hipLaunchKernelGGL((mirror_complete_kernel<16, float2>), g, b, 0, st, (float2 *)a, entries);
+    }
     return hipGetLastError();
 }
 

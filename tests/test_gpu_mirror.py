@@ -1,5 +1,6 @@
-"""GPU parity of the three-step kernel's mirror mode (half of the tensor's
-entries read and written per pass; the rest are their mirrors' conjugates).
+"""GPU parity of mirror mode (half of the tensor's entries read and written
+per pass; the rest are their mirrors' conjugates): the three-step kernel at
+M = 2 and the MFMA step at M = 4.
 
 Each run is compared with the oracle (complex128: per step
 max|drho| <= 1e-12 max|rho|; complex64 storage 1e-5 / 1e-6 absolute) and
@@ -132,9 +133,86 @@ def test_defaults_and_refusals():
         ctx.set_fused_steps(3)
         rho = ctx.propagate(40, list(range(41)))
     assert rel_err_per_step(rho, orun.oracle_run(wn, 40)).max() <= TOL_C128
-    for L, M in [(3, 2), (4, 3)]:
-        ww = W.three_site_l8().with_(L=L) if M == 3 else w.with_(L=L)
+    for L, M in [(3, 2), (4, 3), (1, 4)]:
+        ww = W.three_site_l8().with_(L=L) if M == 3 else case_m4(L, 1) if M == 4 else w.with_(L=L)
         with Q.create(Q.params_from(ww)) as ctx:
             assert not ctx.mirror()
             with pytest.raises(Q.QuapiError):
                 ctx.set_mirror(True)
+
+
+# ------------------------------------------------- M = 4: the N = 16 MFMA step
+def hermitian_rho0_m4(seed):
+    rng = np.random.default_rng(seed)
+    r = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+    r = r @ r.conj().T
+    t = np.trace(r).real
+    r = r.real / t + 1j * (r.imag / t)
+    for a in range(4):                               # exactly Hermitian
+        r[a, a] = r[a, a].real
+        for b in range(a + 1, 4):
+            r[b, a] = np.conj(r[a, b])
+    return r
+
+
+def case_m4(L, seed):
+    rng = np.random.default_rng(200 + seed)
+    return W.spin_boson_l7().with_(M=4, s=np.linspace(-1, 1, 4), H=W.random_hermitian(rng, 4),
+                                   rho0=hermitian_rho0_m4(seed), L=L, xi=0.3)
+
+
+def run_m4(w, n, mirror, dtype="c128", chunks=None):
+    with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
+        ctx.set_mirror(mirror)
+        assert ctx.mirror() == mirror
+        if chunks is None:
+            rho = ctx.propagate(n, list(range(n + 1)))
+        else:
+            rho = np.concatenate([ctx.propagate(0, [0])] + [ctx.propagate(k) for k in chunks])
+        A = ctx.read_tensor(0, ctx.tensor_size())
+    return rho, A
+
+
+@pytest.mark.parametrize("L,seed,n", [(2, 1, 20), (3, 2, 20), (4, 3, 14), (5, 4, 10), (6, 5, 9)])
+def test_m4_mirror_mode_against_oracle_and_full_mode(L, seed, n):
+    w = case_m4(L, seed)
+    print(f"M=4 L={L} seed={seed} steps={n}", flush=True)
+    rho_m, A_m = run_m4(w, n, True)
+    rho_f, A_f = run_m4(w, n, False)
+    o = orun.oracle_run(w, n)
+    assert rel_err_per_step(rho_m, o).max() <= TOL_C128
+    assert rel_err_per_step(rho_m, rho_f).max() <= 1e-13
+    scale = np.abs(A_f).max()
+    assert np.abs(A_m - A_f).max() <= 1e-13 * scale
+    x = np.arange(len(A_m))
+    mirror = ((x & 0x3333333333333333) << 2) | ((x >> 2) & 0x3333333333333333)
+    pair = mirror != x
+    assert np.array_equal(A_m[mirror[pair]], np.conj(A_m[pair]))       # filled in by the completion kernel
+    assert np.abs(A_m[~pair].imag).max() <= 1e-13 * scale
+    tr = np.trace(rho_m, axis1=1, axis2=2)
+    assert np.abs(tr - 1).max() <= 1e-12
+
+
+@pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c64f64", 1e-6)])
+def test_m4_mirror_mode_complex64_tiers(dtype, tol):
+    w = case_m4(4, 6)
+    n = 25
+    rho_m, _ = run_m4(w, n, True, dtype=dtype)
+    assert np.abs(rho_m - orun.oracle_run(w, n)).max() <= tol
+
+
+def test_m4_mirror_mode_chunked_calls_and_switching():
+    w = case_m4(5, 7)
+    chunks = [3, 6, 1, 4, 2]
+    n = sum(chunks)
+    rho_m, A_m = run_m4(w, n, True, chunks=chunks)
+    o = orun.oracle_run(w, n)
+    assert rel_err_per_step(rho_m, o).max() <= TOL_C128
+    with Q.create(Q.params_from(w)) as ctx:
+        parts = [ctx.propagate(0, [0]), ctx.propagate(7)]
+        ctx.set_mirror(False)
+        parts.append(ctx.propagate(4))
+        ctx.set_mirror(True)
+        parts.append(ctx.propagate(5))
+        rho = np.concatenate(parts)
+    assert rel_err_per_step(rho, o).max() <= TOL_C128

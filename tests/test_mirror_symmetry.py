@@ -221,3 +221,81 @@ def test_mirror_pass_index_rules(nd):
     up = ~keep
     out[up] = np.conj(out[mirror4(x[up])])
     assert np.array_equal(out, Y)
+
+
+# ---------------------------------------------------------------- M = 4 (N = 16)
+def mirror16(x):
+    """Each base-16 digit o = 4a + b -> 4b + a (the kernel's bit form)."""
+    x = np.asarray(x, dtype=np.int64)
+    return ((x & 0x3333333333333333) << 2) | ((x >> 2) & 0x3333333333333333)
+
+
+def test_bit_form_is_the_digit_swap_m4():
+    xs = np.arange(16 ** 3)
+    want = []
+    for x in xs:
+        out = 0
+        for j in range(3):
+            d = (int(x) // 16 ** j) % 16
+            out += (4 * (d % 4) + d // 4) * 16 ** j
+        want.append(out)
+    assert np.array_equal(mirror16(xs), want)
+
+
+def test_path_sum_entries_are_conjugate_under_the_mirror_m4():
+    rng = np.random.default_rng(12)
+    r = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+    rho0 = r @ r.conj().T
+    rho0 /= np.trace(rho0)
+    w = W.spin_boson_l7().with_(M=4, s=np.linspace(-1, 1, 4), H=W.random_hermitian(rng, 4), rho0=rho0,
+                                L=2, xi=0.3)
+    A = _brute(w, 3)
+    x = np.arange(len(A))
+    scale = np.abs(A).max()
+    assert np.abs(A[mirror16(x)] - np.conj(A)).max() <= 1e-14 * scale
+    assert np.abs(A[mirror16(x)] - A).max() > 1e-3 * scale
+
+
+def mfma_mirror_launches(Q, grid, waves=4):
+    """Items run by the N = 16 MFMA step's mirror launches: 16 items per wave
+    row (lane column j = the lowest digit), Q sweep rows over the block's
+    `waves` waves; mode 1 the high-digit values below their mirror; mode 2
+    the values equal to it, `parts` blocks of q_span rows, items below their
+    mirror; mode 3 the same values, rows whose digits are all diagonal
+    (base-4 digit d -> 5 d), lanes j with a diagonal digit."""
+    canon = [h for h in range(grid) if h < mirror16(h)]
+    diag = [h for h in range(grid) if h == mirror16(h)]
+    passes = (Q + waves - 1) // waves
+    parts = (passes + 3) // 4
+    span = ((passes + parts - 1) // parts) * waves
+    dm = int(round(np.log(Q) / np.log(16)))
+    runs = []
+    for b, h in enumerate(canon):
+        for q in range(Q):
+            for j in range(16):
+                runs.append((1, b, h * 16 * Q + 16 * q + j))
+    for b in range(len(diag) * parts):
+        h, part = diag[b // parts], b % parts
+        for wv in range(waves):
+            for q in range(part * span + wv, min(Q, (part + 1) * span), waves):
+                for j in range(16):
+                    m = h * 16 * Q + 16 * q + j
+                    if m < mirror16(m):
+                        runs.append((2, len(canon) + b, m))
+    for b, h in enumerate(diag):
+        for it in range(4 ** dm):
+            q = sum((5 * ((it >> (2 * k)) & 3)) << (4 * k) for k in range(dm))
+            for j in range(0, 16, 5):
+                runs.append((3, len(canon) + len(diag) * parts + b, h * 16 * Q + 16 * q + j))
+    return runs, len(canon) + len(diag) * (parts + 1)
+
+
+@pytest.mark.parametrize("Q,grid", [(1, 1), (16, 1), (1, 16), (16, 16), (256, 16), (16, 256)])
+def test_mfma_mirror_launches_run_each_kept_item_once(Q, grid):
+    runs, n_rows = mfma_mirror_launches(Q, grid)
+    items = [m for _, _, m in runs]
+    assert len(items) == len(set(items))
+    assert set(items) == {m for m in range(16 * Q * grid) if m <= mirror16(m)}
+    assert all(mode == 3 for mode, _, m in runs if mirror16(m) == m)
+    assert all(mode != 3 for mode, _, m in runs if mirror16(m) != m)
+    assert max(row for _, row, _ in runs) < n_rows
