@@ -280,13 +280,19 @@ struct Layout {
     size_t total;
     int n_panels, n_tables, partial_blocks;
     int n_canon3, n_diag3, parts3, span3;   // mirror mode of the three-step kernel (high-digit blocks)
-    int n_canon1, n_diag1, parts1, span1;   // mirror mode of the N = 16 MFMA step (main split)
+    int n_canon1, n_diag1, parts1, span1;   // mirror mode of the N = 9, 16 single step (main split)
     DigitSplit main_split;   // digit split of the full-window steps
     DigitSplit split2;       // digit split of the fused two-step kernel
     DigitSplit split3;       // digit split of the three-step kernel
 };
 
 constexpr int kSlots = 4;    // rho partial buffers: a fused launch takes two
+
+// The full-window single step has a mirror mode at N = 9 (vector kernel) and
+// N = 16 (MFMA kernel, which needs R = 16), from L = 2.
+bool single_mirror_ok(int N, int L, const DigitSplit &main_split) {
+    return L >= 2 && (N == 9 || (N == 16 && main_split.R == 16));
+}
 
 Layout make_layout(const quapi_params &p, int n_panels) {
     Layout l{};
@@ -317,16 +323,17 @@ Layout make_layout(const quapi_params &p, int n_panels) {
         l.span3 = ((passes + l.parts3 - 1) / l.parts3) * rows_per_pass;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon3 + l.n_diag3 * (l.parts3 + 1));
     }
-    if (N == 16 && l.main_split.R == 16) {
-        // the MFMA step: the same partition over its block digits; a block
-        // sweeps its rows with its 4 waves
+    if (single_mirror_ok(N, L, l.main_split)) {
+        // the N = 9 step and the N = 16 MFMA step: the same partition over
+        // their block digits; a block sweeps its rows with its 4 waves (MFMA)
+        // or its kBlock / R thread columns
         const DigitSplit &s1 = l.main_split;
         for (int h = 0; h < s1.grid; ++h) {
-            const long long hb = mirror16(h);
+            const long long hb = mirror_n(N, h);
             if (h < hb) ++l.n_canon1;
             else if (h == hb) ++l.n_diag1;
         }
-        const int rows_per_pass = kBlock / 64;
+        const int rows_per_pass = N == 16 ? kBlock / 64 : kBlock / s1.R;
         const int passes = (s1.Q + rows_per_pass - 1) / rows_per_pass;
         l.parts1 = (passes + 3) / 4;
         l.span1 = ((passes + l.parts1 - 1) / l.parts1) * rows_per_pass;
@@ -663,15 +670,16 @@ quapi_status finalize_side(quapi_ctx *c, const int *slots, int n, int grid) {
 
 // Enqueue step n (1-based); with rho, also rho(t_n) into the sink's next slot.
 // The finalize runs on the side stream, overlapped with the next step.
-// The N = 16 MFMA step runs in mirror mode (half of the entries).
-bool mirror16_on(const quapi_ctx *c) { return c->mirror && c->N == 16; }
+// The full-window single step runs in mirror mode (half of the entries):
+// N = 9 and N = 16 (N = 4 has it in the three-step kernel only).
+bool single_mirror_on(const quapi_ctx *c) { return c->mirror && (c->N == 9 || c->N == 16); }
 
 // Launch a full-window single step with the arguments of prepare_step: one
-// launch, or in mirror mode (N = 16) the launches over the high-digit values
-// below their mirror (mode 1) and equal to it (modes 2, 3).  *rows: the rho
-// partial rows written.
+// launch, or in mirror mode (N = 9, 16) the launches over the high-digit
+// values below their mirror (mode 1) and equal to it (modes 2, 3).  *rows:
+// the rho partial rows written.
 hipError_t launch_full_step(quapi_ctx *c, bool rho, StepArgs a, int grid, int *rows) {
-    if (!mirror16_on(c)) {
+    if (!single_mirror_on(c)) {
         a.mode = 0;
         *rows = grid;
         return launch_step(c->N, c->prec, rho, false, a, grid, c->stream);
@@ -711,7 +719,7 @@ quapi_status enqueue_step(quapi_ctx *c, int n, bool rho) {
     StepPlan sp;
     quapi_status st = prepare_step(c, n, rho, &sp);
     if (st != QUAPI_OK) return st;
-    const bool half = !sp.grow && mirror16_on(c);       // reads and writes the kept half only
+    const bool half = !sp.grow && single_mirror_on(c);       // reads and writes the kept half only
     if (!half && (st = ensure_full(c)) != QUAPI_OK) return st;
     StepArgs &a = sp.args;
     a.a_in = c->A[c->cur];
@@ -1210,7 +1218,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
                     c->graph_failed = true;   // stay on direct launches
                 } else {
                     st = join_side(c);        // the graph reuses partial buffers 0 and 1
-                    const bool half = !fused && mirror16_on(c);
+                    const bool half = !fused && single_mirror_on(c);
                     if (st == QUAPI_OK && !half) st = ensure_full(c);
                     if (st != QUAPI_OK) return st;
                     HIP_TRY(c, hipGraphLaunch(gx, c->stream));
@@ -1428,10 +1436,10 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
                     if (pass == 0 ? h < mirror4(h) : h == mirror4(h)) c->blk3_h.push_back(h);
             c->mirror_ok = herm;
         }
-        if (N == 16 && lay.main_split.R == 16) {
+        if (single_mirror_ok(N, L, lay.main_split)) {
             for (int pass = 0; pass < 2; ++pass)
                 for (int h = 0; h < lay.main_split.grid; ++h)
-                    if (pass == 0 ? h < mirror16(h) : h == mirror16(h)) c->blk1_h.push_back(h);
+                    if (pass == 0 ? h < mirror_n(N, h) : h == mirror_n(N, h)) c->blk1_h.push_back(h);
             c->mirror_ok = herm;
         }
         c->mirror = c->mirror_ok;
@@ -1582,7 +1590,7 @@ quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable) {
     if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
     if (enable && !ctx->mirror_ok)
         return fail(ctx, QUAPI_ERR_INVALID,
-                    "mirror mode needs M = 2 and L >= 4, or M = 4 and L >= 2, and an exactly Hermitian rho0");
+                    "mirror mode needs M = 2 and L >= 4, or M = 3, 4 and L >= 2, and an exactly Hermitian rho0");
     if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
     if ((enable != 0) == ctx->mirror) return QUAPI_OK;
     // the captured three-step graphs hold the launches of the old mode

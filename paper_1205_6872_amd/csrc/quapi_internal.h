@@ -61,7 +61,7 @@ struct StepArgs {
     int old_tab, oldf_tab;      // bank indices of the oldest-point tables
     int16_t tab[kMaxL];         // bank index of the interior table for digit j
     int16_t tabf[kMaxL];        // bank index of the final-point table for digit j
-    // Mirror mode of the N = 16 MFMA step (as for the three-step kernel):
+    // Mirror mode of the N = 9 and N = 16 steps (as for the three-step kernel):
     // mode 1 the high-digit values blk_hi[..] below their mirror, mode 2 those
     // equal to it in `parts` blocks of q_span sweep rows (items below their
     // mirror), mode 3 the same values, the items that are their own mirror;
@@ -143,6 +143,20 @@ __host__ __device__ constexpr long long mirror4(long long x) {
 __host__ __device__ constexpr long long mirror16(long long x) {
     return ((x & 0x3333333333333333LL) << 2) | ((x >> 2) & 0x3333333333333333LL);
 }
+// N = 9 (M = 3): digit o = 3a + b -> 3b + a, digit by digit.
+__host__ __device__ inline long long mirror9(long long x) {
+    long long out = 0, w = 1;
+    while (x > 0) {
+        const int d = (int)(x % 9);
+        out += (long long)(3 * (d % 3) + d / 3) * w;
+        x /= 9;
+        w *= 9;
+    }
+    return out;
+}
+__host__ __device__ inline long long mirror_n(int N, long long x) {
+    return N == 4 ? mirror4(x) : N == 16 ? mirror16(x) : N == 9 ? mirror9(x) : x;
+}
 
 // Coefficients of the three-step kernel (compute precision), the four of one
 // group of a stage contiguous (indexed by the stage's new point last):
@@ -220,7 +234,7 @@ size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q);
 hipError_t launch_step2(int prec, bool with_rho, const Step2Args &a, hipStream_t st);
 hipError_t launch_step2_coef(const CoefArgs &a, hipStream_t st);
 hipError_t launch_step3(int prec, bool with_rho, const Step3Args &a, hipStream_t st);
-// Fill every entry above its mirror (N = 4 or 16) with the conjugate of the mirror.
+// Fill every entry above its mirror (N = 4, 9 or 16) with the conjugate of the mirror.
 hipError_t launch_mirror_complete(int N, int prec, void *a, long long entries, hipStream_t st);
 hipError_t launch_step3_coef(const Coef3Args &a, hipStream_t st);
 size_t step3_lds_bytes(int prec, bool with_rho, int R, int Q);

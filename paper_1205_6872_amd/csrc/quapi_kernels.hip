@@ -380,8 +380,30 @@ __device__ double2 digit_product(const double2 *__restrict__ bank, const int16_t
 // S is the storage scalar of the tensor and T the arithmetic scalar: double /
 // double (complex128), float / float (complex64 tier), float / double
 // (complex64 storage, each loaded value widened and every product in FP64).
-template <int N, typename S, typename T, bool RHO, bool GROW>
+//
+// MODE 1, 2, 3 (mirror mode, full-window steps at N = 9): as in the N = 16
+// MFMA step, with the base-9 mirror (digit 3a + b -> 3b + a): mode 1 the
+// blocks whose high digits are below their mirror; mode 2 those with all
+// high digits diagonal, the items below their mirror; mode 3 the items whose
+// digits are all diagonal (threads whose low digits are diagonal, sweep rows
+// whose digits are), which read their input slots above the mirror from the
+// mirrored slot, conjugated.  Outputs above their mirror are stored as the
+// conjugate at the mirrored address; each block adds the mirrored items' rho
+// terms as S[o] + conj(S[mirror(o)]) (modes 1, 2).
+__host__ __device__ constexpr int mirror_digit9(int d) { return 3 * (d % 3) + d / 3; }
+__device__ __forceinline__ bool diagonal_digits_only9(int v) {
+    for (; v > 0; v /= 9)
+        if (v % 9 % 4 != 0) return false;          // diagonal digits: 0, 4, 8
+    return true;
+}
+__device__ __forceinline__ int diagonal_digits9(int x) {   // base-3 digit d -> base-9 digit 4 d
+    int out = 0, w = 1;
+    for (; x > 0; x /= 3, w *= 9) out += 4 * (x % 3) * w;
+    return out;
+}
+template <int N, typename S, typename T, bool RHO, bool GROW, int MODE = 0>
 __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
+    static_assert(MODE == 0 || (N == 9 && !GROW), "mirror mode: full-window N = 9 steps");
     using C = typename Cx<T>::type;
     using CS = typename Cx<S>::type;
     constexpr int I = GROW ? 1 : N;
@@ -404,7 +426,9 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
     const int cR = kBlock / R;       // sweep stride in units of R
     const int active = cR * R;       // threads that own items
     const double2 *__restrict__ bank = a.bank;
-    const long long blk = blockIdx.x;
+    const long long blk = MODE == 0   ? (long long)blockIdx.x
+                          : MODE == 2 ? (long long)a.blk_hi[blockIdx.x / a.parts]
+                                      : (long long)a.blk_hi[blockIdx.x];     // high digits
     const double2 one = make_double2(1.0, 0.0);
     const bool planned = a.t_lo != nullptr;
     const int j_hi = a.d_lo + a.d_mid;
@@ -480,7 +504,16 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
         const CS *__restrict__ ain = (const CS *)a.a_in;
         CS *__restrict__ aout = (CS *)a.a_out;
         const long long mc = a.m_count;
-        for (int qm0 = t / R; qm0 < Q; qm0 += ILP * cR) {
+        // sweep rows: all (mode 0, 1), a part (mode 2), or in mode 3 those with
+        // all digits diagonal, for threads whose low digits are diagonal
+        const int part = MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
+        const bool thread_runs = MODE != 3 || diagonal_digits_only9(r);
+        int n_diag_rows = 1;
+        if (MODE == 3)
+            for (int q = Q; q > 1; q /= 9) n_diag_rows *= 3;
+        const int i0 = (MODE == 2 ? part * a.q_span : 0) + t / R;
+        const int i1 = !thread_runs ? 0 : MODE == 3 ? n_diag_rows : MODE == 2 ? min(Q, (part + 1) * a.q_span) : Q;
+        for (int qm0 = i0; qm0 < i1; qm0 += ILP * cR) {
             // For N >= 9 the N*N table reads must stay in the loop: hoisted as
             // loop invariants they would need more registers than a thread has.
             if (!OLD_REG) asm volatile("" ::: "memory");
@@ -488,19 +521,29 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
             bool has[ILP];
 #pragma unroll
             for (int u = 0; u < ILP; ++u) {      // issue every load first
-                const int qm = qm0 + u * cR;
-                has[u] = qm < Q;
+                const int it = qm0 + u * cR;
+                const int qm = MODE == 3 ? diagonal_digits9(it) : it;
                 const long long m = m0 + (long long)qm * R + r;
+                has[u] = it < i1 && (MODE != 2 || m < mirror9(m));
                 if (has[u]) {
 #pragma unroll
-                    for (int i = 0; i < I; ++i) x[u][i] = conv<C>(ain[(long long)I * m + i]);
+                    for (int i = 0; i < I; ++i) {
+                        // a self-mirror item holds valid values only at the slots
+                        // not above their mirror
+                        constexpr bool fix = MODE == 3;
+                        const int ib = MODE == 3 ? mirror_digit9(i) : i;
+                        x[u][i] = conv<C>(ain[(long long)I * m + (fix && ib < i ? ib : i)]);
+                        if (fix && ib < i) x[u][i].y = -x[u][i].y;
+                    }
                 }
             }
 #pragma unroll
             for (int u = 0; u < ILP; ++u) {
                 if (!has[u]) continue;
-                const int qm = qm0 + u * cR;
+                const int it = qm0 + u * cR;
+                const int qm = MODE == 3 ? diagonal_digits9(it) : it;
                 const long long m = m0 + (long long)qm * R + r;
+                const long long mb = MODE == 0 ? m : mirror9(m);
 #pragma unroll
                 for (int o = 0; o < N; ++o) {
                     if (!OLD_REG) asm volatile("" ::: "memory");   // table reads of this o only
@@ -508,7 +551,14 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 #pragma unroll
                     for (int i = 0; i < I; ++i) cmac(s, OLD_REG ? old_r[o * I + i] : coef_ld(old_c, o * N + i), x[u][i]);
                     const C p = cmul(PLO_REG ? plo[o] : s_plo[o * R + r], s_tq[o * Q + qm]);
-                    aout[m + mc * o] = conv<CS>(cmul(s, p));
+                    const C v = cmul(s, p);
+                    if (MODE == 0 || mirror_digit9(o) >= o) {
+                        aout[m + mc * o] = conv<CS>(v);
+                    } else if (MODE != 3) {
+                        C vc = v;
+                        vc.y = -vc.y;
+                        aout[mb + mc * mirror_digit9(o)] = conv<CS>(vc);
+                    }
                     if (RHO) {
                         if (!OLD_REG) asm volatile("" ::: "memory");
                         C sf = {};
@@ -542,7 +592,14 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
                 s.x += s_red[w * N + t].x;
                 s.y += s_red[w * N + t].y;
             }
-            a.partials[blk * N + t] = s;
+            if (MODE == 1 || MODE == 2) {               // the mirrored items' terms
+                const int tb = mirror_digit9(t);
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    s.x += s_red[w * N + tb].x;
+                    s.y -= s_red[w * N + tb].y;
+                }
+            }
+            a.partials[((size_t)a.part_base + (MODE == 0 ? blk : (long long)blockIdx.x)) * N + t] = s;
         }
     }
 }
@@ -903,7 +960,19 @@ template <int N, typename S, typename T, bool RHO, bool GROW>
 hipError_t launch_step_t(const StepArgs &a, int grid, hipStream_t st) {
     using C = typename Cx<T>::type;
     const StepLds lay = step_lds_layout(N, (int)sizeof(C), RHO, GROW ? 1 : N, a.R, a.Q, N <= 4);
-    hipLaunchKernelGGL((step_kernel<N, S, T, RHO, GROW>), dim3(grid), dim3(kBlock), lay.total, st, a);
+    const dim3 b(kBlock);
+    if constexpr (N == 9 && !GROW) {
+        switch (a.mode) {
+        case 0: break;
+        case 1: hipLaunchKernelGGL((step_kernel<N, S, T, RHO, GROW, 1>), dim3(a.n_blk), b, lay.total, st, a); return hipGetLastError();
+        case 2: hipLaunchKernelGGL((step_kernel<N, S, T, RHO, GROW, 2>), dim3(a.n_blk), b, lay.total, st, a); return hipGetLastError();
+        case 3: hipLaunchKernelGGL((step_kernel<N, S, T, RHO, GROW, 3>), dim3(a.n_blk), b, lay.total, st, a); return hipGetLastError();
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        if (a.mode != 0) return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((step_kernel<N, S, T, RHO, GROW>), dim3(grid), b, lay.total, st, a);
     return hipGetLastError();
 }
 

@@ -453,7 +453,7 @@ template <int N, typename CS>
 __global__ void __launch_bounds__(kBlock) mirror_complete_kernel(CS *__restrict__ a, long long entries) {
     for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < entries;
          x += (long long)gridDim.x * kBlock) {
-        const long long xb = N == 4 ? mirror4(x) : mirror16(x);
+        const long long xb = N == 4 ? mirror4(x) : N == 16 ? mirror16(x) : mirror9(x);
         if (xb < x) a[x] = cconj(a[xb]);
     }
 }
@@ -479,14 +479,18 @@ hipError_t launch_step3(int prec, bool with_rho, const Step3Args &a, hipStream_t
 hipError_t launch_mirror_complete(int N, int prec, void *a, long long entries, hipStream_t st) {
     const long long blocks = std::min<long long>((entries + kBlock - 1) / kBlock, 1 << 20);
     if (blocks < 1) return hipSuccess;
-    if (N != 4 && N != 16) return hipErrorInvalidValue;
+    if (N != 4 && N != 9 && N != 16) return hipErrorInvalidValue;
     const dim3 g((unsigned)blocks), b(kBlock);
     if (prec == kPrecC128) {
-        if (N == 4) hipLaunchKernelGGL((mirror_complete_kernel<4, double2>), g, b, 0, st, (double2 *)a, entries);
-        else hipLaunchKernelGGL((mirror_complete_kernel<16, double2>), g, b, 0, st, (double2 *)a, entries);
+        double2 *p = (double2 *)a;
+        if (N == 4) hipLaunchKernelGGL((mirror_complete_kernel<4, double2>), g, b, 0, st, p, entries);
+        else if (N == 9) hipLaunchKernelGGL((mirror_complete_kernel<9, double2>), g, b, 0, st, p, entries);
+        else hipLaunchKernelGGL((mirror_complete_kernel<16, double2>), g, b, 0, st, p, entries);
     } else {
-        if (N == 4) hipLaunchKernelGGL((mirror_complete_kernel<4, float2>), g, b, 0, st, (float2 *)a, entries);
-        else hipLaunchKernelGGL((mirror_complete_kernel<16, float2>), g, b, 0, st, (float2 *)a, entries);
+        float2 *p = (float2 *)a;
+        if (N == 4) hipLaunchKernelGGL((mirror_complete_kernel<4, float2>), g, b, 0, st, p, entries);
+        else if (N == 9) hipLaunchKernelGGL((mirror_complete_kernel<9, float2>), g, b, 0, st, p, entries);
+        else hipLaunchKernelGGL((mirror_complete_kernel<16, float2>), g, b, 0, st, p, entries);
     }
     return hipGetLastError();
 }

@@ -1,6 +1,6 @@
 """GPU parity of mirror mode (half of the tensor's entries read and written
 per pass; the rest are their mirrors' conjugates): the three-step kernel at
-M = 2 and the MFMA step at M = 4.
+M = 2, the vector step at M = 3 and the MFMA step at M = 4.
 
 Each run is compared with the oracle (complex128: per step
 max|drho| <= 1e-12 max|rho|; complex64 storage 1e-5 / 1e-6 absolute) and
@@ -133,7 +133,7 @@ def test_defaults_and_refusals():
         ctx.set_fused_steps(3)
         rho = ctx.propagate(40, list(range(41)))
     assert rel_err_per_step(rho, orun.oracle_run(wn, 40)).max() <= TOL_C128
-    for L, M in [(3, 2), (4, 3), (1, 4)]:
+    for L, M in [(3, 2), (1, 3), (1, 4)]:
         ww = W.three_site_l8().with_(L=L) if M == 3 else case_m4(L, 1) if M == 4 else w.with_(L=L)
         with Q.create(Q.params_from(ww)) as ctx:
             assert not ctx.mirror()
@@ -216,3 +216,74 @@ def test_m4_mirror_mode_chunked_calls_and_switching():
         parts.append(ctx.propagate(5))
         rho = np.concatenate(parts)
     assert rel_err_per_step(rho, o).max() <= TOL_C128
+
+
+# ------------------------------------------------ M = 3: the N = 9 vector step
+def hermitian_rho0_m(M, seed):
+    rng = np.random.default_rng(seed)
+    r = rng.normal(size=(M, M)) + 1j * rng.normal(size=(M, M))
+    r = r @ r.conj().T
+    t = np.trace(r).real
+    r = r.real / t + 1j * (r.imag / t)
+    for a in range(M):                               # exactly Hermitian
+        r[a, a] = r[a, a].real
+        for b in range(a + 1, M):
+            r[b, a] = np.conj(r[a, b])
+    return r
+
+
+def case_m3(L, seed):
+    rng = np.random.default_rng(300 + seed)
+    return W.three_site_l8().with_(L=L, H=W.random_hermitian(rng, 3), rho0=hermitian_rho0_m(3, seed), xi=0.3)
+
+
+def mirror9_array(x):
+    x = np.asarray(x, dtype=np.int64).copy()
+    out = np.zeros_like(x)
+    w = 1
+    while (x > 0).any():
+        d = x % 9
+        out += (3 * (d % 3) + d // 3) * w
+        x //= 9
+        w *= 9
+    return out
+
+
+@pytest.mark.parametrize("L,seed,n", [(2, 1, 20), (3, 2, 20), (4, 3, 16), (6, 4, 12), (8, 5, 8)])
+def test_m3_mirror_mode_against_oracle_and_full_mode(L, seed, n):
+    w = case_m3(L, seed)
+    print(f"M=3 L={L} seed={seed} steps={n}", flush=True)
+    rho_m, A_m = run_m4(w, n, True)
+    rho_f, A_f = run_m4(w, n, False)
+    o = orun.oracle_run(w, n)
+    assert rel_err_per_step(rho_m, o).max() <= TOL_C128
+    assert rel_err_per_step(rho_m, rho_f).max() <= 1e-13
+    scale = np.abs(A_f).max()
+    assert np.abs(A_m - A_f).max() <= 1e-13 * scale
+    x = np.arange(len(A_m))
+    mirror = mirror9_array(x)
+    pair = mirror != x
+    assert np.array_equal(A_m[mirror[pair]], np.conj(A_m[pair]))
+    assert np.abs(A_m[~pair].imag).max() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c64f64", 1e-6)])
+def test_m3_mirror_mode_complex64_tiers(dtype, tol):
+    w = case_m3(5, 6)
+    n = 25
+    rho_m, _ = run_m4(w, n, True, dtype=dtype)
+    assert np.abs(rho_m - orun.oracle_run(w, n)).max() <= tol
+
+
+def test_m3_mirror_mode_switching():
+    w = case_m3(5, 7)
+    n = 20
+    with Q.create(Q.params_from(w)) as ctx:
+        assert ctx.mirror()
+        parts = [ctx.propagate(0, [0]), ctx.propagate(8)]
+        ctx.set_mirror(False)
+        parts.append(ctx.propagate(5))
+        ctx.set_mirror(True)
+        parts.append(ctx.propagate(7))
+        rho = np.concatenate(parts)
+    assert rel_err_per_step(rho, orun.oracle_run(w, n)).max() <= TOL_C128

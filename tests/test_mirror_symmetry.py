@@ -299,3 +299,91 @@ def test_mfma_mirror_launches_run_each_kept_item_once(Q, grid):
     assert all(mode == 3 for mode, _, m in runs if mirror16(m) == m)
     assert all(mode != 3 for mode, _, m in runs if mirror16(m) != m)
     assert max(row for _, row, _ in runs) < n_rows
+
+
+# ----------------------------------------------------------------- M = 3 (N = 9)
+def mirror9(x):
+    out, w = 0, 1
+    x = int(x)
+    while x > 0:
+        d = x % 9
+        out += (3 * (d % 3) + d // 3) * w
+        x //= 9
+        w *= 9
+    return out
+
+
+def test_path_sum_entries_are_conjugate_under_the_mirror_m3():
+    rng = np.random.default_rng(13)
+    r = rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3))
+    rho0 = r @ r.conj().T
+    rho0 /= np.trace(rho0)
+    w = W.three_site_l8().with_(L=2, H=W.random_hermitian(rng, 3), rho0=rho0, xi=0.3)
+    A = _brute(w, 3)
+    mb = np.array([mirror9(x) for x in range(len(A))])
+    scale = np.abs(A).max()
+    assert np.abs(A[mb] - np.conj(A)).max() <= 1e-14 * scale
+    assert np.abs(A[mb] - A).max() > 1e-3 * scale
+
+
+def vector_mirror_launches(R, Q, grid, block=256):
+    """Items run by the N = 9 vector step's mirror launches: thread columns
+    r = t % R (block // R of them per row), Q sweep rows; mode 1 the
+    high-digit values below their mirror; mode 2 those equal to it, `parts`
+    blocks of q_span rows, items below their mirror; mode 3 the same values,
+    threads whose low digits are all diagonal, rows whose digits are."""
+    def diag_only(v):
+        while v > 0:
+            if v % 9 % 4:
+                return False
+            v //= 9
+        return True
+
+    def diag_digits(x):
+        out, w = 0, 1
+        while x > 0:
+            out += 4 * (x % 3) * w
+            x //= 3
+            w *= 9
+        return out
+
+    canon = [h for h in range(grid) if h < mirror9(h)]
+    diag = [h for h in range(grid) if h == mirror9(h)]
+    cR = block // R
+    passes = (Q + cR - 1) // cR
+    parts = (passes + 3) // 4
+    span = ((passes + parts - 1) // parts) * cR
+    n_rows = 1
+    q = Q
+    while q > 1:
+        n_rows *= 3
+        q //= 9
+    runs = []
+    for b, h in enumerate(canon):
+        for qm in range(Q):
+            for r in range(R):
+                runs.append((1, b, h * R * Q + qm * R + r))
+    for b in range(len(diag) * parts):
+        h, part = diag[b // parts], b % parts
+        for t in range(cR * R):
+            for qm in range(part * span + t // R, min(Q, (part + 1) * span), cR):
+                m = h * R * Q + qm * R + t % R
+                if m < mirror9(m):
+                    runs.append((2, len(canon) + b, m))
+    for b, h in enumerate(diag):
+        for t in range(cR * R):
+            if not diag_only(t % R):
+                continue
+            for it in range(t // R, n_rows, cR):
+                runs.append((3, len(canon) + len(diag) * parts + b, h * R * Q + diag_digits(it) * R + t % R))
+    return runs, len(canon) + len(diag) * (parts + 1)
+
+
+@pytest.mark.parametrize("R,Q,grid", [(1, 1, 1), (9, 1, 1), (81, 9, 1), (81, 81, 9), (9, 9, 81), (81, 1, 729)])
+def test_vector_mirror_launches_run_each_kept_item_once(R, Q, grid):
+    runs, n_rows = vector_mirror_launches(R, Q, grid)
+    items = [m for _, _, m in runs]
+    assert len(items) == len(set(items))
+    assert set(items) == {m for m in range(R * Q * grid) if m <= mirror9(m)}
+    assert all(mode == 3 for mode, _, m in runs if mirror9(m) == m)
+    assert max(row for _, row, _ in runs) < n_rows
