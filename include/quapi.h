@@ -200,7 +200,7 @@ quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps);
 quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps);
 
 /* Mirror mode of the full-window kernels: the three-step kernel (M = 2,
- * L >= 4) and the M = 4 MFMA step (L >= 2).  Swapping the forward and
+ * L >= 4) and the single step (M = 2, 3, 4; L >= 2).  Swapping the forward and
  * backward path of every point maps the path sum of Sec. II to its complex
  * conjugate: K = U (x) U* and every influence factor go to their conjugates,
  * and so does rho(0) when it is Hermitian.  So the tensor entry of the
@@ -208,13 +208,15 @@ quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps);
  * writes only the entries not above their mirror (flat index, each digit
  * (a, b) -> (b, a)) -- about half the bytes.  rho at every step is unchanged
  * up to rounding.  The entries above their mirror are filled in before
- * anything that reads the whole tensor (single steps at M = 2, the two-step
- * kernel, quapi_read_tensor).  On by default where available.
- *   quapi_mirror:      *enabled = 1 while on.
- *   quapi_set_mirror:  enable = 0 turns it off; 1 turns it on.
- * Errors: QUAPI_ERR_INVALID for NULL arguments, or enable = 1 where it is not
- * available (M other than 2 or 4, L below the limits, or rho0 not exactly
- * Hermitian); QUAPI_ERR_STATE while another call runs on the context. */
+ * anything that reads the whole tensor (the two-step kernel,
+ * quapi_read_tensor).  On by default where available.  The single step
+ * uses it for tensors above 2^22 entries only (smaller steps are bound by
+ * their launches, and mirror mode takes three); the three-step kernel always.
+ *   quapi_mirror:      *enabled = the mode: 0 off, 1 on (default), 2 on at every size.
+ *   quapi_set_mirror:  enable = 0, 1 or 2 as above.
+ * Errors: QUAPI_ERR_INVALID for NULL arguments, enable outside 0..2, or enable > 0 where it is not
+ * available (M other than 2, 3 or 4, L = 1, or rho0 not exactly Hermitian);
+ * QUAPI_ERR_STATE while another call runs on the context. */
 quapi_status quapi_mirror(const quapi_ctx *ctx, int *enabled);
 quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable);
 

@@ -274,7 +274,7 @@ std::string validate(const quapi_params *p) {
 // ------------------------------------------------------------------ layout
 struct Layout {
     size_t a_bytes;                  // one tensor buffer
-    size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_Ht, off_rho0;
+    size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_Ht, off_Ut, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
     size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_blk1, off_pairs, off_sink;
     size_t total;
@@ -288,10 +288,10 @@ struct Layout {
 
 constexpr int kSlots = 4;    // rho partial buffers: a fused launch takes two
 
-// The full-window single step has a mirror mode at N = 9 (vector kernel) and
-// N = 16 (MFMA kernel, which needs R = 16), from L = 2.
+// The full-window single step has a mirror mode at N = 4, 9 (vector kernel)
+// and N = 16 (MFMA kernel, which needs R = 16), from L = 2.
 bool single_mirror_ok(int N, int L, const DigitSplit &main_split) {
-    return L >= 2 && (N == 9 || (N == 16 && main_split.R == 16));
+    return L >= 2 && (N == 4 || N == 9 || (N == 16 && main_split.R == 16));
 }
 
 Layout make_layout(const quapi_params &p, int n_panels) {
@@ -356,6 +356,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_s = take((size_t)M * 8);
     l.off_H = take((size_t)M * M * 16);
     l.off_Ht = take((size_t)std::max(p.n_H, 0) * M * M * 16);
+    l.off_Ut = take((size_t)std::max(p.n_H, 0) * M * M * 16);
     l.off_rho0 = take((size_t)N * 16);
     l.off_pa = take((size_t)n_panels * 8);
     l.off_ph = take((size_t)n_panels * 8);
@@ -421,6 +422,7 @@ struct quapi_ctx {
     void *coef = nullptr;         // fused-step coefficients (compute precision)
     int n_H = 0;                  // driven: per-interval Hamiltonians on the device
     const double2 *Ht_d = nullptr;
+    double2 *Ut_d = nullptr;      // driven: U_k = exp(-i H_t[k] dt), computed at create
     std::vector<double> Ht_h;
     TablesArgs drive_ta{};        // the setup tables call, reused per step with k_only
     float2 *bank_f = nullptr;     // the bank rounded to complex64 (FP32 arithmetic only)
@@ -436,7 +438,7 @@ struct quapi_ctx {
     // Mirror mode of the three-step kernel: it reads and writes only the
     // entries not above their mirror; half_cur says A[cur] holds only those.
     bool mirror_ok = false;       // N = 4, three-step width available, rho0 exactly Hermitian
-    bool mirror = false;
+    int mirror = 0;               // 0 off, 1 where it pays, 2 at every size (quapi_set_mirror)
     bool half_cur = false;
     int *blk3 = nullptr;          // high-digit values: n_canon3 below their mirror, then n_diag3 equal
     std::vector<int> blk3_h;
@@ -670,14 +672,19 @@ quapi_status finalize_side(quapi_ctx *c, const int *slots, int n, int grid) {
 
 // Enqueue step n (1-based); with rho, also rho(t_n) into the sink's next slot.
 // The finalize runs on the side stream, overlapped with the next step.
-// The full-window single step runs in mirror mode (half of the entries):
-// N = 9 and N = 16 (N = 4 has it in the three-step kernel only).
-bool single_mirror_on(const quapi_ctx *c) { return c->mirror && (c->N == 9 || c->N == 16); }
+// The full-window single step runs in mirror mode (half of the entries) for
+// tensors above the graph size: smaller steps are bound by their launches,
+// and the three mirror launches then cost more than the bytes they save
+// (measured crossover: M = 2 at L = 11-12, M = 3 at L = 7, M = 4 at L = 5-6).
+bool single_mirror_on(const quapi_ctx *c) {
+    return c->mirror != 0 && single_mirror_ok(c->N, c->L, c->lay.main_split) &&
+           (c->mirror == 2 || (size_t)ipow_ll(c->N, c->L) > kGraphMaxEntries);
+}
 
 // Launch a full-window single step with the arguments of prepare_step: one
-// launch, or in mirror mode (N = 9, 16) the launches over the high-digit
-// values below their mirror (mode 1) and equal to it (modes 2, 3).  *rows:
-// the rho partial rows written.
+// launch, or in mirror mode the launches over the high-digit values below
+// their mirror (mode 1) and equal to it (modes 2, 3).  *rows: the rho
+// partial rows written.
 hipError_t launch_full_step(quapi_ctx *c, bool rho, StepArgs a, int grid, int *rows) {
     if (!single_mirror_on(c)) {
         a.mode = 0;
@@ -951,7 +958,7 @@ quapi_status prepare_step3(quapi_ctx *c, bool rho, Step3Args *out) {
 // below their mirror (mode 1) and equal to it (modes 2 and 3).  *rows: the
 // rho partial rows written.
 hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows) {
-    if (!c->mirror) {
+    if (c->mirror == 0) {
         a.mode = 0;
         *rows = a.grid;
         return launch_step3(c->prec, rho, a, c->stream);
@@ -994,7 +1001,7 @@ quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
     Step3Args a;
     quapi_status st = prepare_step3(c, rho, &a);
     if (st != QUAPI_OK) return st;
-    if (!c->mirror) {                        // mode 0 reads every entry
+    if (c->mirror == 0) {                    // mode 0 reads every entry
         st = ensure_full(c);
         if (st != QUAPI_OK) return st;
     }
@@ -1030,7 +1037,7 @@ quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
         if (st != QUAPI_OK) return st;
     }
     c->cur = 1 - c->cur;
-    c->half_cur = c->mirror;
+    c->half_cur = c->mirror != 0;
     c->step = n + 2;
     return QUAPI_OK;
 }
@@ -1182,11 +1189,11 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
                     c->graph_failed = true;   // stay on direct launches
                 } else {
                     st = join_side(c);        // the graph reuses partial buffers 0, 1 and 2
-                    if (st == QUAPI_OK && !c->mirror) st = ensure_full(c);
+                    if (st == QUAPI_OK && c->mirror == 0) st = ensure_full(c);
                     if (st != QUAPI_OK) return st;
                     HIP_TRY(c, hipGraphLaunch(gx, c->stream));
                     c->cur = 1 - c->cur;
-                    c->half_cur = c->mirror;
+                    c->half_cur = c->mirror != 0;
                     c->step = n + 2;
                     done = true;
                 }
@@ -1249,7 +1256,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
             // driven: the propagator tables of step n, and the plan tables
             // built from them, before the step
             TablesArgs ta = c->drive_ta;
-            ta.H = c->Ht_d + (size_t)std::min(n - 1, c->n_H - 1) * c->M * c->M;
+            ta.U_given = c->Ut_d + (size_t)std::min(n - 1, c->n_H - 1) * c->M * c->M;
             ta.k_only = 1;
             hipError_t e = launch_tables(ta, c->stream);
             if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "tables launch: %s", hipGetErrorString(e));
@@ -1413,6 +1420,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->blk1 = (int *)(w + lay.off_blk1);
     c->n_H = p->n_H;
     c->Ht_d = (const double2 *)(w + lay.off_Ht);
+    c->Ut_d = (double2 *)(w + lay.off_Ut);
     c->coef = w + lay.off_coef;
     c->stage = (double2 *)(w + lay.off_stage);
     c->pairs = (double2 *)(w + lay.off_pairs);
@@ -1442,7 +1450,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
                     if (pass == 0 ? h < mirror_n(N, h) : h == mirror_n(N, h)) c->blk1_h.push_back(h);
             c->mirror_ok = herm;
         }
-        c->mirror = c->mirror_ok;
+        c->mirror = c->mirror_ok ? 1 : 0;
     }
     c->fuse = c->n_H > 0 ? 1 : fusion_width(N, L, c->prec, c->mirror_ok);
     c->pa_h = std::move(pa);
@@ -1504,7 +1512,6 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     ta.L = L;
     ta.dt = p->dt;
     ta.s = (const double *)(w + lay.off_s);
-    ta.H = (const double2 *)(w + lay.off_H);
     ta.g = c->g;
     ta.U = c->U;
     ta.eta = c->eta;
@@ -1512,7 +1519,15 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     ta.bank_f = c->bank_f;
     ta.k_trace_exact = c->prec == kPrecC64;            // FP32 arithmetic: keep the trace exact per step
     c->drive_ta = ta;
-    if (c->n_H > 0) ta.H = c->Ht_d;                    // driven: step 1 uses the first matrix
+    // U = exp(-i H dt): for a driven system every interval's, once, in
+    // parallel (step 1 uses the first); the tables kernel takes it from there
+    if (c->n_H > 0) {
+        if (e == hipSuccess) e = launch_u_stack(c->Ht_d, c->n_H, M, p->dt, c->Ut_d, c->stream);
+        ta.U_given = c->Ut_d;
+    } else {
+        if (e == hipSuccess) e = launch_u_stack((const double2 *)(w + lay.off_H), 1, M, p->dt, c->U, c->stream);
+        ta.U_given = c->U;
+    }
     if (e == hipSuccess) e = launch_tables(ta, c->stream);
     if (e == hipSuccess)
         e = launch_init_tensor(N, c->prec, c->rho0_d, c->bank, BankLayout{L}.self_end(), c->A[0], c->stream);
@@ -1582,17 +1597,17 @@ quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
 
 quapi_status quapi_mirror(const quapi_ctx *ctx, int *enabled) {
     if (!ctx || !enabled) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
-    *enabled = ctx->mirror ? 1 : 0;
+    *enabled = ctx->mirror;
     return QUAPI_OK;
 }
 
 quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable) {
     if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
     if (enable && !ctx->mirror_ok)
-        return fail(ctx, QUAPI_ERR_INVALID,
-                    "mirror mode needs M = 2 and L >= 4, or M = 3, 4 and L >= 2, and an exactly Hermitian rho0");
+        return fail(ctx, QUAPI_ERR_INVALID, "mirror mode needs M = 2, 3 or 4, L >= 2 and an exactly Hermitian rho0");
     if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
-    if ((enable != 0) == ctx->mirror) return QUAPI_OK;
+    if (enable < 0 || enable > 2) return fail(ctx, QUAPI_ERR_INVALID, "enable must be 0, 1 or 2");
+    if (enable == ctx->mirror) return QUAPI_OK;
     // the captured three-step graphs hold the launches of the old mode
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     for (auto &row : ctx->graph3)
@@ -1604,7 +1619,7 @@ quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable) {
         if (g) (void)hipGraphExecDestroy(g);
         g = nullptr;
     }
-    ctx->mirror = enable != 0;
+    ctx->mirror = enable;
     return QUAPI_OK;
 }
 

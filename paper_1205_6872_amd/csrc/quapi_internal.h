@@ -198,7 +198,6 @@ struct TablesArgs {
     int M, L;
     double dt;
     const double *s;
-    const double2 *H;
     const double2 *g;           // G(j dt/2), j = 0..2L+2
     double2 *U;                 // out: M x M
     double2 *eta;               // out: 4L+2 classes
@@ -206,11 +205,14 @@ struct TablesArgs {
     float2 *bank_f;             // out (if not NULL): the same tables rounded to complex64
     int k_trace_exact;          // K rows (a, a) chosen on the FP32 grid with exact column sums
     int k_only;                 // rewrite only the tables that carry K (driven H: per step); eta, U untouched
+    const double2 *U_given;     // U (M x M) from launch_u_stack
 };
 
 // Kernel launchers (quapi_kernels.hip).  They return the launch status.
 hipError_t launch_g_quad(const QuadArgs &a, int n_t, double2 *g, hipStream_t st);
 hipError_t launch_tables(const TablesArgs &a, hipStream_t st);
+// U_k = exp(-i H_t[k] dt) for k < n_H (M x M each), a thread each.
+hipError_t launch_u_stack(const double2 *H_t, int n_H, int M, double dt, double2 *U_t, hipStream_t st);
 hipError_t launch_init_tensor(int N, int prec, const double2 *rho0, const double2 *bank,
                               int self_end_tab, void *a0, hipStream_t st);
 hipError_t launch_step(int N, int prec, bool with_rho, bool grow, const StepArgs &a, int grid,

@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(kBlock) tables_kernel(const TablesArgs a) {
     __shared__ double2 sKd[kMaxM * kMaxM * kMaxM];    // [a][p]: K[(a, a)][p], trace-exact
     const int M = a.M, N = M * M, NN = N * N, L = a.L;
     const int t = threadIdx.x;
-    if (t == 0) expm_minus_i_h_dt(a.H, M, a.dt, sU);
+    if (t < M * M) sU[t] = a.U_given[t];
     if (t < M) sS[t] = a.s[t];
     // eta classes from g_j = G(j dt/2) (second differences of G over the
     // intervals [0, dt/2], [k dt - dt/2, k dt + dt/2] and [n dt - dt/2, n dt])
@@ -381,8 +381,8 @@ __device__ double2 digit_product(const double2 *__restrict__ bank, const int16_t
 // double (complex128), float / float (complex64 tier), float / double
 // (complex64 storage, each loaded value widened and every product in FP64).
 //
-// MODE 1, 2, 3 (mirror mode, full-window steps at N = 9): as in the N = 16
-// MFMA step, with the base-9 mirror (digit 3a + b -> 3b + a): mode 1 the
+// MODE 1, 2, 3 (mirror mode, full-window steps at N = 4 and 9): as in the
+// N = 16 MFMA step, with the mirror of digit o = Ma + b -> Mb + a: mode 1 the
 // blocks whose high digits are below their mirror; mode 2 those with all
 // high digits diagonal, the items below their mirror; mode 3 the items whose
 // digits are all diagonal (threads whose low digits are diagonal, sweep rows
@@ -390,20 +390,26 @@ __device__ double2 digit_product(const double2 *__restrict__ bank, const int16_t
 // mirrored slot, conjugated.  Outputs above their mirror are stored as the
 // conjugate at the mirrored address; each block adds the mirrored items' rho
 // terms as S[o] + conj(S[mirror(o)]) (modes 1, 2).
-__host__ __device__ constexpr int mirror_digit9(int d) { return 3 * (d % 3) + d / 3; }
-__device__ __forceinline__ bool diagonal_digits_only9(int v) {
-    for (; v > 0; v /= 9)
-        if (v % 9 % 4 != 0) return false;          // diagonal digits: 0, 4, 8
-    return true;
-}
-__device__ __forceinline__ int diagonal_digits9(int x) {   // base-3 digit d -> base-9 digit 4 d
-    int out = 0, w = 1;
-    for (; x > 0; x /= 3, w *= 9) out += 4 * (x % 3) * w;
-    return out;
-}
+template <int N>
+struct MirrorDigits {
+    static constexpr int M = N == 4 ? 2 : N == 9 ? 3 : 4;
+    static __host__ __device__ constexpr int digit(int d) { return M * (d % M) + d / M; }
+    static __device__ long long index(long long x) { return N == 4 ? mirror4(x) : mirror9(x); }
+    static __device__ bool diagonal_only(int v) {          // every digit a (M + 1)
+        for (; v > 0; v /= N)
+            if (v % N % (M + 1) != 0) return false;
+        return true;
+    }
+    static __device__ int diagonal(int x) {                // base-M digit a -> base-N digit a (M + 1)
+        int out = 0, w = 1;
+        for (; x > 0; x /= M, w *= N) out += (M + 1) * (x % M) * w;
+        return out;
+    }
+};
 template <int N, typename S, typename T, bool RHO, bool GROW, int MODE = 0>
 __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
-    static_assert(MODE == 0 || (N == 9 && !GROW), "mirror mode: full-window N = 9 steps");
+    static_assert(MODE == 0 || ((N == 4 || N == 9) && !GROW), "mirror mode: full-window N = 4, 9 steps");
+    using MD = MirrorDigits<N == 9 ? 9 : 4>;
     using C = typename Cx<T>::type;
     using CS = typename Cx<S>::type;
     constexpr int I = GROW ? 1 : N;
@@ -507,10 +513,10 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
         // sweep rows: all (mode 0, 1), a part (mode 2), or in mode 3 those with
         // all digits diagonal, for threads whose low digits are diagonal
         const int part = MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
-        const bool thread_runs = MODE != 3 || diagonal_digits_only9(r);
+        const bool thread_runs = MODE != 3 || MD::diagonal_only(r);
         int n_diag_rows = 1;
         if (MODE == 3)
-            for (int q = Q; q > 1; q /= 9) n_diag_rows *= 3;
+            for (int q = Q; q > 1; q /= N) n_diag_rows *= MD::M;
         const int i0 = (MODE == 2 ? part * a.q_span : 0) + t / R;
         const int i1 = !thread_runs ? 0 : MODE == 3 ? n_diag_rows : MODE == 2 ? min(Q, (part + 1) * a.q_span) : Q;
         for (int qm0 = i0; qm0 < i1; qm0 += ILP * cR) {
@@ -522,16 +528,16 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 #pragma unroll
             for (int u = 0; u < ILP; ++u) {      // issue every load first
                 const int it = qm0 + u * cR;
-                const int qm = MODE == 3 ? diagonal_digits9(it) : it;
+                const int qm = MODE == 3 ? MD::diagonal(it) : it;
                 const long long m = m0 + (long long)qm * R + r;
-                has[u] = it < i1 && (MODE != 2 || m < mirror9(m));
+                has[u] = it < i1 && (MODE != 2 || m < MD::index(m));
                 if (has[u]) {
 #pragma unroll
                     for (int i = 0; i < I; ++i) {
                         // a self-mirror item holds valid values only at the slots
                         // not above their mirror
                         constexpr bool fix = MODE == 3;
-                        const int ib = MODE == 3 ? mirror_digit9(i) : i;
+                        const int ib = MODE == 3 ? MD::digit(i) : i;
                         x[u][i] = conv<C>(ain[(long long)I * m + (fix && ib < i ? ib : i)]);
                         if (fix && ib < i) x[u][i].y = -x[u][i].y;
                     }
@@ -541,9 +547,9 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
             for (int u = 0; u < ILP; ++u) {
                 if (!has[u]) continue;
                 const int it = qm0 + u * cR;
-                const int qm = MODE == 3 ? diagonal_digits9(it) : it;
+                const int qm = MODE == 3 ? MD::diagonal(it) : it;
                 const long long m = m0 + (long long)qm * R + r;
-                const long long mb = MODE == 0 ? m : mirror9(m);
+                const long long mb = MODE == 0 ? m : MD::index(m);
 #pragma unroll
                 for (int o = 0; o < N; ++o) {
                     if (!OLD_REG) asm volatile("" ::: "memory");   // table reads of this o only
@@ -552,12 +558,12 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
                     for (int i = 0; i < I; ++i) cmac(s, OLD_REG ? old_r[o * I + i] : coef_ld(old_c, o * N + i), x[u][i]);
                     const C p = cmul(PLO_REG ? plo[o] : s_plo[o * R + r], s_tq[o * Q + qm]);
                     const C v = cmul(s, p);
-                    if (MODE == 0 || mirror_digit9(o) >= o) {
+                    if (MODE == 0 || MD::digit(o) >= o) {
                         aout[m + mc * o] = conv<CS>(v);
                     } else if (MODE != 3) {
                         C vc = v;
                         vc.y = -vc.y;
-                        aout[mb + mc * mirror_digit9(o)] = conv<CS>(vc);
+                        aout[mb + mc * MD::digit(o)] = conv<CS>(vc);
                     }
                     if (RHO) {
                         if (!OLD_REG) asm volatile("" ::: "memory");
@@ -593,7 +599,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
                 s.y += s_red[w * N + t].y;
             }
             if (MODE == 1 || MODE == 2) {               // the mirrored items' terms
-                const int tb = mirror_digit9(t);
+                const int tb = MD::digit(t);
                 for (int w = 0; w < kBlock / 64; ++w) {
                     s.x += s_red[w * N + tb].x;
                     s.y -= s_red[w * N + tb].y;
@@ -961,7 +967,7 @@ hipError_t launch_step_t(const StepArgs &a, int grid, hipStream_t st) {
     using C = typename Cx<T>::type;
     const StepLds lay = step_lds_layout(N, (int)sizeof(C), RHO, GROW ? 1 : N, a.R, a.Q, N <= 4);
     const dim3 b(kBlock);
-    if constexpr (N == 9 && !GROW) {
+    if constexpr ((N == 4 || N == 9) && !GROW) {
         switch (a.mode) {
         case 0: break;
         case 1: hipLaunchKernelGGL((step_kernel<N, S, T, RHO, GROW, 1>), dim3(a.n_blk), b, lay.total, st, a); return hipGetLastError();
@@ -1003,6 +1009,19 @@ size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q) {
 
 hipError_t launch_g_quad(const QuadArgs &a, int n_t, double2 *g, hipStream_t st) {
     hipLaunchKernelGGL(g_quad_kernel, dim3(n_t), dim3(kBlock), 0, st, a, g);
+    return hipGetLastError();
+}
+
+// U = exp(-i H dt) for each of n_H Hamiltonians (one for a static system,
+// one per time interval for a driven one), a thread each.
+__global__ void __launch_bounds__(64) u_stack_kernel(const double2 *H_t, int n_H, int M, double dt, double2 *U_t) {
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k < n_H) expm_minus_i_h_dt(H_t + (size_t)k * M * M, M, dt, U_t + (size_t)k * M * M);
+}
+
+hipError_t launch_u_stack(const double2 *H_t, int n_H, int M, double dt, double2 *U_t, hipStream_t st) {
+    if (n_H <= 0) return hipSuccess;
+    hipLaunchKernelGGL(u_stack_kernel, dim3((n_H + 63) / 64), dim3(64), 0, st, H_t, n_H, M, dt, U_t);
     return hipGetLastError();
 }
 

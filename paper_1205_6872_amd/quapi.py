@@ -230,16 +230,17 @@ class Context:
         h = self._live()
         _check(lib().quapi_set_fused_steps(h, int(steps)), h)
 
-    def mirror(self) -> bool:
-        """Whether the three-step kernel runs in mirror mode (half of the
-        tensor's entries read and written per pass)."""
+    def mirror(self) -> int:
+        """Mirror mode (half of the tensor's entries read and written per
+        pass): 0 off, 1 on where it pays (default), 2 on at every size."""
         v = ctypes.c_int(0)
         _check(lib().quapi_mirror(self._live(), ctypes.byref(v)))
-        return bool(v.value)
+        return int(v.value)
 
-    def set_mirror(self, enable: bool) -> None:
+    def set_mirror(self, enable) -> None:
+        """enable: 0 / False, 1 / True, or 2 (every size, e.g. in tests)."""
         h = self._live()
-        _check(lib().quapi_set_mirror(h, int(bool(enable))), h)
+        _check(lib().quapi_set_mirror(h, int(enable)), h)
 
     def step_count(self) -> int:
         v = ctypes.c_int(0)

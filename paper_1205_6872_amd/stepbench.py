@@ -1,6 +1,7 @@
 """Per-shape step timing through the C ABI (library timing events on its stream).
 
     python3 -m paper_1205_6872_amd.stepbench [--cases M:L,...] [--dtypes c128,c64,c64f64] [--steps K]
+                                             [--fused-steps 1,2,3] [--mirror on,off]
     python3 -m paper_1205_6872_amd.stepbench --paper-table1
 
 For each case (M levels, memory length L) and storage/arithmetic mode it runs
@@ -32,11 +33,14 @@ def case_workload(M: int, L: int, dtype: str, seed: int = 1) -> W.Workload:
                       n_steps=0, xi=0.3, omega_c=7.5, dtype=dtype)
 
 
-def time_case(M: int, L: int, dtype: str, steps: int, fused_steps: int = 0) -> dict:
+def time_case(M: int, L: int, dtype: str, steps: int, fused_steps: int = 0, mirror=None) -> dict:
     w = case_workload(M, L, dtype)
     N = M * M
     with Q.create(Q.params_from(w)) as ctx:
         ctx.set_fused_steps(fused_steps)
+        if mirror is not None:
+            ctx.set_mirror(mirror)
+        mirror = ctx.mirror()
         F = ctx.fused_steps()
         steps -= steps % F                                # whole groups
         ctx.propagate(L)                                  # growth and the first full-window step
@@ -58,7 +62,7 @@ def time_case(M: int, L: int, dtype: str, steps: int, fused_steps: int = 0) -> d
 
     ms_r, spl_r, gbs_r = per(t_rho)
     ms_n, spl_n, gbs_n = per(t_no)
-    return {"M": M, "L": L, "dtype": dtype, "entries": N ** L, "steps": steps, "fused_steps": F,
+    return {"M": M, "L": L, "dtype": dtype, "entries": N ** L, "steps": steps, "fused_steps": F, "mirror": mirror,
             "rho_launch_ms": round(ms_r, 4), "rho_steps_per_launch": round(spl_r, 3), "rho_gbs": round(gbs_r, 1),
             "norho_launch_ms": round(ms_n, 4), "norho_steps_per_launch": round(spl_n, 3),
             "norho_gbs": round(gbs_n, 1)}
@@ -96,6 +100,7 @@ def main(argv=None) -> int:
     ap.add_argument("--dtypes", default="c128,c64,c64f64")
     ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--fused-steps", default="0", help="comma list of widths to pin (0 = default)")
+    ap.add_argument("--mirror", default="default", help="comma list of on (every size) / off / default")
     ap.add_argument("--paper-table1", action="store_true",
                     help="the paper's Table 1 sweep (its model system, dk = 2..15, 989 main steps)")
     args = ap.parse_args(argv)
@@ -107,7 +112,9 @@ def main(argv=None) -> int:
         M, L = (int(v) for v in c.split(":"))
         for d in args.dtypes.split(","):
             for f in args.fused_steps.split(","):
-                print(json.dumps(time_case(M, L, d, args.steps, int(f))), flush=True)
+                for mm in args.mirror.split(","):
+                    mirror = {"on": 2, "off": 0, "default": None}[mm]     # on: at every size
+                    print(json.dumps(time_case(M, L, d, args.steps, int(f), mirror)), flush=True)
     return 0
 
 

@@ -117,10 +117,11 @@ def test_driven_count_and_pointer_are_checked():
 
 
 def test_footprint_holds_the_driven_hamiltonians():
+    # the Hamiltonians and their propagators, one M x M complex128 each per interval
     base = Q.footprint(_p())
     n_H = 10000
     fp = Q.footprint(_p(H_t=np.broadcast_to(np.eye(2, dtype=complex), (n_H, 2, 2))))
-    assert n_H * 4 * 16 <= fp - base <= n_H * 4 * 16 + 512
+    assert 2 * n_H * 4 * 16 <= fp - base <= 2 * n_H * 4 * 16 + 1024
 
 
 def test_memory_cap_gives_nomem_before_touching_a_device(monkeypatch):

@@ -42,10 +42,11 @@ def case(L, seed):
 
 
 def run(w, n, mirror, dtype="c128", chunks=None):
+    # mirror mode on at every size (2): the single steps at the call ends too
     with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
         ctx.set_fused_steps(3)
-        ctx.set_mirror(mirror)
-        assert ctx.mirror() == mirror
+        ctx.set_mirror(2 if mirror else 0)
+        assert ctx.mirror() == (2 if mirror else 0)
         if chunks is None:
             rho = ctx.propagate(n, list(range(n + 1)))
         else:
@@ -113,7 +114,7 @@ def test_switching_mirror_mode_mid_run():
         parts = [ctx.propagate(0, [0]), ctx.propagate(22)]          # ends on a group boundary
         ctx.set_mirror(False)
         parts.append(ctx.propagate(18))
-        ctx.set_mirror(True)
+        ctx.set_mirror(2)
         parts.append(ctx.propagate(20))
         rho = np.concatenate(parts)
     assert rel_err_per_step(rho, orun.oracle_run(w, n)).max() <= TOL_C128
@@ -122,7 +123,10 @@ def test_switching_mirror_mode_mid_run():
 def test_defaults_and_refusals():
     w = case(7, 9)
     with Q.create(Q.params_from(w)) as ctx:
-        assert ctx.mirror()                                        # M = 2, L >= 4, Hermitian rho0
+        assert ctx.mirror() == 1                                   # M = 2, Hermitian rho0: on
+        with pytest.raises(Q.QuapiError) as ei:
+            ctx.set_mirror(3)
+        assert ei.value.status == Q.ERR_INVALID
     rho0 = np.array([[0.7, 0.2 + 0.1j], [0.05 - 0.3j, 0.3]])      # not Hermitian
     wn = w.with_(rho0=rho0)
     with Q.create(Q.params_from(wn)) as ctx:
@@ -133,7 +137,7 @@ def test_defaults_and_refusals():
         ctx.set_fused_steps(3)
         rho = ctx.propagate(40, list(range(41)))
     assert rel_err_per_step(rho, orun.oracle_run(wn, 40)).max() <= TOL_C128
-    for L, M in [(3, 2), (1, 3), (1, 4)]:
+    for L, M in [(1, 2), (1, 3), (1, 4)]:
         ww = W.three_site_l8().with_(L=L) if M == 3 else case_m4(L, 1) if M == 4 else w.with_(L=L)
         with Q.create(Q.params_from(ww)) as ctx:
             assert not ctx.mirror()
@@ -162,9 +166,11 @@ def case_m4(L, seed):
 
 
 def run_m4(w, n, mirror, dtype="c128", chunks=None):
+    # mirror mode at every size (2): these tensors are below the size where
+    # the single step takes it by default
     with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
-        ctx.set_mirror(mirror)
-        assert ctx.mirror() == mirror
+        ctx.set_mirror(2 if mirror else 0)
+        assert ctx.mirror() == (2 if mirror else 0)
         if chunks is None:
             rho = ctx.propagate(n, list(range(n + 1)))
         else:
@@ -212,7 +218,7 @@ def test_m4_mirror_mode_chunked_calls_and_switching():
         parts = [ctx.propagate(0, [0]), ctx.propagate(7)]
         ctx.set_mirror(False)
         parts.append(ctx.propagate(4))
-        ctx.set_mirror(True)
+        ctx.set_mirror(2)
         parts.append(ctx.propagate(5))
         rho = np.concatenate(parts)
     assert rel_err_per_step(rho, o).max() <= TOL_C128
@@ -283,7 +289,39 @@ def test_m3_mirror_mode_switching():
         parts = [ctx.propagate(0, [0]), ctx.propagate(8)]
         ctx.set_mirror(False)
         parts.append(ctx.propagate(5))
-        ctx.set_mirror(True)
+        ctx.set_mirror(2)
         parts.append(ctx.propagate(7))
         rho = np.concatenate(parts)
     assert rel_err_per_step(rho, orun.oracle_run(w, n)).max() <= TOL_C128
+
+
+# ------------------------------------- M = 2 single steps and pairs after them
+@pytest.mark.parametrize("L,F,seed,n", [(2, 1, 1, 30), (3, 1, 2, 30), (3, 2, 3, 31), (5, 1, 4, 25),
+                                        (8, 1, 5, 20), (8, 2, 6, 21), (12, 1, 7, 14)])
+def test_m2_single_steps_in_mirror_mode(L, F, seed, n):
+    w = case(L, seed)
+    print(f"M=2 L={L} F={F} steps={n}", flush=True)
+    out = []
+    for mirror in (2, 0):
+        with Q.create(Q.params_from(w)) as ctx:
+            ctx.set_fused_steps(F)
+            ctx.set_mirror(mirror)
+            rho = ctx.propagate(n, list(range(n + 1)))
+            out.append((rho, ctx.read_tensor(0, ctx.tensor_size())))
+    (rho_m, A_m), (rho_f, A_f) = out
+    o = orun.oracle_run(w, n)
+    assert rel_err_per_step(rho_m, o).max() <= TOL_C128
+    assert rel_err_per_step(rho_m, rho_f).max() <= 1e-13
+    assert np.abs(A_m - A_f).max() <= 1e-13 * np.abs(A_f).max()
+
+
+def test_driven_context_runs_mirror_single_steps():
+    rng = np.random.default_rng(17)
+    w = case(6, 9)
+    H_t = np.stack([W.random_hermitian(rng, 2) for _ in range(30)])
+    w = w.with_(H=H_t[0].copy(), H_t=H_t)
+    with Q.create(Q.params_from(w)) as ctx:
+        assert ctx.mirror() == 1 and ctx.fused_steps() == 1
+        ctx.set_mirror(2)                  # L = 6 is below the default size
+        rho = ctx.propagate(30, list(range(31)))
+    assert rel_err_per_step(rho, orun.oracle_run(w, 30)).max() <= TOL_C128

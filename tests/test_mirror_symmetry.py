@@ -326,29 +326,32 @@ def test_path_sum_entries_are_conjugate_under_the_mirror_m3():
     assert np.abs(A[mb] - A).max() > 1e-3 * scale
 
 
-def vector_mirror_launches(R, Q, grid, block=256):
-    """Items run by the N = 9 vector step's mirror launches: thread columns
-    r = t % R (block // R of them per row), Q sweep rows; mode 1 the
+def vector_mirror_launches(N, R, Q, grid, block=256):
+    """Items run by the vector step's mirror launches (N = 4 or 9): thread
+    columns r = t % R (block // R of them per row), Q sweep rows; mode 1 the
     high-digit values below their mirror; mode 2 those equal to it, `parts`
     blocks of q_span rows, items below their mirror; mode 3 the same values,
     threads whose low digits are all diagonal, rows whose digits are."""
+    M = 2 if N == 4 else 3
+    mir = (lambda x: int(mirror4(x))) if N == 4 else mirror9
+
     def diag_only(v):
         while v > 0:
-            if v % 9 % 4:
+            if v % N % (M + 1):
                 return False
-            v //= 9
+            v //= N
         return True
 
     def diag_digits(x):
         out, w = 0, 1
         while x > 0:
-            out += 4 * (x % 3) * w
-            x //= 3
-            w *= 9
+            out += (M + 1) * (x % M) * w
+            x //= M
+            w *= N
         return out
 
-    canon = [h for h in range(grid) if h < mirror9(h)]
-    diag = [h for h in range(grid) if h == mirror9(h)]
+    canon = [h for h in range(grid) if h < mir(h)]
+    diag = [h for h in range(grid) if h == mir(h)]
     cR = block // R
     passes = (Q + cR - 1) // cR
     parts = (passes + 3) // 4
@@ -356,8 +359,8 @@ def vector_mirror_launches(R, Q, grid, block=256):
     n_rows = 1
     q = Q
     while q > 1:
-        n_rows *= 3
-        q //= 9
+        n_rows *= M
+        q //= N
     runs = []
     for b, h in enumerate(canon):
         for qm in range(Q):
@@ -368,7 +371,7 @@ def vector_mirror_launches(R, Q, grid, block=256):
         for t in range(cR * R):
             for qm in range(part * span + t // R, min(Q, (part + 1) * span), cR):
                 m = h * R * Q + qm * R + t % R
-                if m < mirror9(m):
+                if m < mir(m):
                     runs.append((2, len(canon) + b, m))
     for b, h in enumerate(diag):
         for t in range(cR * R):
@@ -376,14 +379,16 @@ def vector_mirror_launches(R, Q, grid, block=256):
                 continue
             for it in range(t // R, n_rows, cR):
                 runs.append((3, len(canon) + len(diag) * parts + b, h * R * Q + diag_digits(it) * R + t % R))
-    return runs, len(canon) + len(diag) * (parts + 1)
+    return runs, len(canon) + len(diag) * (parts + 1), mir
 
 
-@pytest.mark.parametrize("R,Q,grid", [(1, 1, 1), (9, 1, 1), (81, 9, 1), (81, 81, 9), (9, 9, 81), (81, 1, 729)])
-def test_vector_mirror_launches_run_each_kept_item_once(R, Q, grid):
-    runs, n_rows = vector_mirror_launches(R, Q, grid)
+@pytest.mark.parametrize("N,R,Q,grid", [(9, 1, 1, 1), (9, 9, 1, 1), (9, 81, 9, 1), (9, 81, 81, 9), (9, 9, 9, 81),
+                                        (9, 81, 1, 729), (4, 1, 1, 1), (4, 4, 1, 1), (4, 256, 16, 4),
+                                        (4, 256, 1, 64), (4, 64, 4, 16), (4, 256, 16, 256)])
+def test_vector_mirror_launches_run_each_kept_item_once(N, R, Q, grid):
+    runs, n_rows, mir = vector_mirror_launches(N, R, Q, grid)
     items = [m for _, _, m in runs]
     assert len(items) == len(set(items))
-    assert set(items) == {m for m in range(R * Q * grid) if m <= mirror9(m)}
-    assert all(mode == 3 for mode, _, m in runs if mirror9(m) == m)
+    assert set(items) == {m for m in range(R * Q * grid) if m <= mir(m)}
+    assert all(mode == 3 for mode, _, m in runs if mir(m) == m)
     assert max(row for _, row, _ in runs) < n_rows
