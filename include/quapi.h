@@ -99,16 +99,19 @@ typedef struct {
      * Sec. III): n_H Hamiltonians, each M*M complex and Hermitian like H.  The
      * bare propagator of step k (interval (t_{k-1}, t_k]) is exp(-i H_t[k-1] dt)
      * for k <= n_H and uses H_t[n_H-1] after that.  NULL / n_H = 0: H for every
-     * step.  A driven context recomputes its propagator tables before every
-     * step and runs one step per launch. */
+     * step.  A driven context computes every interval's propagator during
+     * quapi_create, rewrites the tables that carry K before every step, and
+     * runs one step per launch. */
     const double *H_t;
     int n_H;                  /* 0 <= n_H <= 1,000,000 */
 } quapi_params;
 
 /* Device bytes that quapi_create needs for these parameters (the two
  * ping-pong tensors of N^L entries dominate; factor tables and rho
- * reduction scratch add less than 0.2% of that plus 4 MB).  Validates the parameters; needs
- * no GPU.  INVALID on malformed parameters or size overflow. */
+ * reduction scratch add less than 0.2% of that plus 4 MB, and a driven
+ * system 2 * n_H * M*M * 16 bytes for its Hamiltonians and propagators).
+ * Validates the parameters; needs no GPU.  INVALID on malformed parameters
+ * or size overflow. */
 quapi_status quapi_footprint(const quapi_params *p, size_t *device_bytes);
 
 /* The paper's primary memory cost (primary-memory-cost equation, Sec. II):
@@ -143,13 +146,13 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
  *   rho_out  host buffer of n_out * M*M complex (n_out = n_sel, or n_steps when
  *            sel is NULL), written in selection order; caller-owned.
  * Blocking: returns when the results are on the host.
- * Results are deterministic.  For M = 2 full-window steps run in fused groups of
- * F = quapi_fused_steps() steps fixed by the global step number: (L+1 .. L+F),
- * (L+F+1 .. L+2F), ... (by default F = 3 at complex128 and QUAPI_C64 from
- * L = 13; where mirror mode is available (see quapi_set_mirror) at complex128
- * from L = 12 and at QUAPI_C64_F64 from L = 14; F = 2 otherwise with L >= 3); a sequence of calls gives bit-identical results to one call when
- * every call ends at step c <= L or with c - L a multiple of F (otherwise the
- * steps of a split group run one by one and round differently, within 1e-15). */
+ * Results are deterministic.  For M = 2 full-window steps run in fused groups
+ * of F = quapi_fused_steps() steps fixed by the global step number:
+ * (L+1 .. L+F), (L+F+1 .. L+2F), ...  A sequence of calls gives bit-identical
+ * results to one call when every call ends at step c <= L or with c - L a
+ * multiple of F (otherwise the steps of a split group run one by one and
+ * round differently, within 1e-15).  F is chosen as quapi_set_fused_steps
+ * describes. */
 quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
                              double *rho_out);
 
@@ -189,12 +192,12 @@ quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries);
 quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps);
 
 /* Choose the full-window steps per launch: 1, 2 (N = 4, L >= 3), 3 (N = 4,
- * L >= 4), or 0 for the default (3 at complex128 and QUAPI_C64 from L = 13 -- where
- * mirror mode is available from L = 12 at complex128 and from L = 14 at
- * QUAPI_C64_F64 -- else 2 where
- * available, else 1; always 1 for a driven context).  Every choice gives the same results to within rounding
- * (the fused kernels apply the same factors in another order); use it to pin
- * the kernel, e.g. in tests.  It takes effect from the next call.
+ * L >= 4), or 0 for the default: 3 at complex128 and QUAPI_C64 from L = 13
+ * (where mirror mode is available, from L = 12 at complex128 and from L = 14
+ * at QUAPI_C64_F64), else 2 where available, else 1; always 1 for a driven
+ * context.  Every choice gives the same results to within rounding (the
+ * fused kernels apply the same factors in another order); use it to pin the
+ * kernel, e.g. in tests.  It takes effect from the next call.
  * Errors: QUAPI_ERR_INVALID for an unavailable width; QUAPI_ERR_STATE while
  * another call runs on the context. */
 quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps);
@@ -207,11 +210,12 @@ quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps);
  * mirrored paths is the conjugate of the entry itself, and a pass reads and
  * writes only the entries not above their mirror (flat index, each digit
  * (a, b) -> (b, a)) -- about half the bytes.  rho at every step is unchanged
- * up to rounding.  The entries above their mirror are filled in before
- * anything that reads the whole tensor (the two-step kernel,
- * quapi_read_tensor).  On by default where available.  The single step
- * uses it for tensors above 2^22 entries only (smaller steps are bound by
- * their launches, and mirror mode takes three); the three-step kernel always.
+ * up to rounding.  On by default where available.  The single step uses it
+ * for tensors above 2^22 entries only (smaller steps are bound by their
+ * launches, and mirror mode takes three); the three-step kernel always.  The
+ * entries above their mirror are filled in (one pass over the tensor)
+ * before anything that reads the whole tensor: the two-step kernel, a single
+ * step that does not take mirror mode, quapi_read_tensor.
  *   quapi_mirror:      *enabled = the mode: 0 off, 1 on (default), 2 on at every size.
  *   quapi_set_mirror:  enable = 0, 1 or 2 as above.
  * Errors: QUAPI_ERR_INVALID for NULL arguments, enable outside 0..2, or enable > 0 where it is not
@@ -224,7 +228,7 @@ quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable);
 typedef struct {
     double setup_ms;          /* device time of the setup kernels in quapi_create */
     double step_ms;           /* summed duration of full-window step kernels (n >= L) */
-    long long step_launches;  /* number of those launches */
+    long long step_launches;  /* number of those launches (in mirror mode: of their groups of three) */
     long long step_steps;     /* full-window steps they covered (a fused launch covers two or three) */
     double grow_ms;           /* summed duration of growth-step kernels (n < L) */
     long long grow_launches;
