@@ -408,6 +408,10 @@ struct quapi_ctx {
     // step; the block partials rotate over kSlots buffers between the streams
     hipStream_t side = nullptr;
     hipEvent_t ev_step[kSlots] = {}, ev_fin[kSlots] = {};
+    // the small mirror-mode launches of a three-step group (modes 2, 3) run
+    // on a third stream, concurrently with mode 1, joined before the next work
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool fin_pending[kSlots] = {};
     int next_slot = 0;
     char *ws = nullptr;
@@ -957,7 +961,9 @@ quapi_status prepare_step3(quapi_ctx *c, bool rho, Step3Args *out) {
 // block (mode 0), or in mirror mode the launches over the high-digit values
 // below their mirror (mode 1) and equal to it (modes 2 and 3).  *rows: the
 // rho partial rows written.
-hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows) {
+// concurrent: modes 2 and 3 on the aux stream (forked from and joined back
+// into the context's stream) while mode 1 runs; not inside a graph capture.
+hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows, bool concurrent) {
     if (c->mirror == 0) {
         a.mode = 0;
         *rows = a.grid;
@@ -965,13 +971,11 @@ hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows) {
     }
     const Layout &l = c->lay;
     hipError_t e = hipSuccess;
-    if (l.n_canon3 > 0) {
-        a.mode = 1;
-        a.blk_hi = c->blk3;
-        a.n_blk = l.n_canon3;
-        a.parts = 1;
-        a.part_base = 0;
-        e = launch_step3(c->prec, rho, a, c->stream);
+    const bool fork = concurrent && l.n_diag3 > 0 && l.n_canon3 > 0;
+    hipStream_t small = fork ? c->aux : c->stream;
+    if (fork) {
+        e = hipEventRecord(c->ev_fork, c->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
     }
     if (e == hipSuccess && l.n_diag3 > 0) {
         a.mode = 2;
@@ -980,7 +984,7 @@ hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows) {
         a.parts = l.parts3;
         a.q_span = l.span3;
         a.part_base = l.n_canon3;
-        e = launch_step3(c->prec, rho, a, c->stream);
+        e = launch_step3(c->prec, rho, a, small);
     }
     if (e == hipSuccess && l.n_diag3 > 0) {
         a.mode = 3;
@@ -988,8 +992,18 @@ hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows) {
         a.n_blk = l.n_diag3;
         a.parts = 1;
         a.part_base = l.n_canon3 + l.n_diag3 * l.parts3;
+        e = launch_step3(c->prec, rho, a, small);
+    }
+    if (e == hipSuccess && fork) e = hipEventRecord(c->ev_join, c->aux);
+    if (e == hipSuccess && l.n_canon3 > 0) {
+        a.mode = 1;
+        a.blk_hi = c->blk3;
+        a.n_blk = l.n_canon3;
+        a.parts = 1;
+        a.part_base = 0;
         e = launch_step3(c->prec, rho, a, c->stream);
     }
+    if (e == hipSuccess && fork) e = hipStreamWaitEvent(c->stream, c->ev_join, 0);
     *rows = l.n_canon3 + l.n_diag3 * (l.parts3 + 1);
     return e;
 }
@@ -1022,8 +1036,11 @@ quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
         e1 = take_event(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
+    // the fork and join cost ~10-20 us: worth it from L = 14 (M = 2) only
+    // (L = 15: 3.79 -> 3.71 ms per launch; L = 13: 0.37 -> 0.38 ms)
+    const bool concurrent = ipow_ll(c->N, c->L) >= (1LL << 28);
     int rows = 0;
-    hipError_t e = launch_step3_modes(c, rho, a, &rows);
+    hipError_t e = launch_step3_modes(c, rho, a, &rows, concurrent);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "three-step launch: %s", hipGetErrorString(e));
     if (c->timing && e0 && e1) {
         (void)hipEventRecord(e1, c->stream);
@@ -1064,7 +1081,7 @@ quapi_status build_graph(quapi_ctx *c, bool rho, int width, int par, hipGraphExe
         a3.a_out = c->A[1 - par];
         for (int k = 0; k < 3; ++k) a3.partials[k] = c->partials[k];
         int rows = 0;
-        e = launch_step3_modes(c, rho, a3, &rows);
+        e = launch_step3_modes(c, rho, a3, &rows, false);
         for (int k = 0; k < 3 && rho && e == hipSuccess; ++k)
             e = launch_rho_finalize(c->N, c->partials[k], rows, c->pairs, c->sink, c->stream);
     } else if (width == 2) {
@@ -1289,6 +1306,12 @@ void release(quapi_ctx *c) {
         if (c->ev_fin[k]) (void)hipEventDestroy(c->ev_fin[k]);
     }
     if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        (void)hipStreamDestroy(c->aux);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (auto &g : c->graph1)
         if (g) (void)hipGraphExecDestroy(g);
     for (auto &row : c->graph2)
@@ -1373,7 +1396,10 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
         }
         c->own_stream = true;
     }
-    bool side_ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
+    bool side_ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
+                   hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess &&
+                   hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
+                   hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
     for (int k = 0; k < kSlots && side_ok; ++k)
         side_ok = hipEventCreateWithFlags(&c->ev_step[k], hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&c->ev_fin[k], hipEventDisableTiming) == hipSuccess;
