@@ -288,6 +288,18 @@ struct Layout {
 
 constexpr int kSlots = 4;    // rho partial buffers: a fused launch takes two
 
+// The three-step mirror launches run modes 2, 3 concurrently with mode 1 from
+// 2^28 entries: the fork and join cost ~10-20 us, more than they hide below
+// (L = 15: 3.79 -> 3.71 ms per launch with rho; L = 13: 0.37 -> 0.38 ms).
+bool step3_concurrent(size_t entries) { return entries >= (size_t(1) << 28); }
+
+// Blocks per high-digit value in mirror mode 2: about one block per compute
+// unit (256 on MI355X) over the n_diag values, at most one per sweep pass.
+int mirror_parts(int passes, int n_diag) {
+    const int want = n_diag > 0 ? (256 + n_diag - 1) / n_diag : 1;
+    return std::max(1, std::min(passes, want));
+}
+
 // The full-window single step has a mirror mode at N = 4, 9 (vector kernel)
 // and N = 16 (MFMA kernel, which needs R = 16), from L = 2.
 bool single_mirror_ok(int N, int L, const DigitSplit &main_split) {
@@ -316,10 +328,13 @@ Layout make_layout(const quapi_params &p, int n_panels) {
             if (h < hb) ++l.n_canon3;
             else if (h == hb) ++l.n_diag3;
         }
-        // mode 2: about four sweep rows per thread per block
+        // mode 2: run alone (below 2^28 entries), its blocks are latency
+        // bound, so each value's sweep is split into enough blocks for about
+        // one per compute unit; run concurrently with mode 1, fewer longer
+        // blocks (about four sweep rows per thread) cost less setup
         const int rows_per_pass = kBlock / s3.R;
         const int passes = (s3.Q + rows_per_pass - 1) / rows_per_pass;
-        l.parts3 = (passes + 3) / 4;
+        l.parts3 = step3_concurrent(entries) ? (passes + 3) / 4 : mirror_parts(passes, l.n_diag3);
         l.span3 = ((passes + l.parts3 - 1) / l.parts3) * rows_per_pass;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon3 + l.n_diag3 * (l.parts3 + 1));
     }
@@ -335,7 +350,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
         }
         const int rows_per_pass = N == 16 ? kBlock / 64 : kBlock / s1.R;
         const int passes = (s1.Q + rows_per_pass - 1) / rows_per_pass;
-        l.parts1 = (passes + 3) / 4;
+        l.parts1 = mirror_parts(passes, l.n_diag1);
         l.span1 = ((passes + l.parts1 - 1) / l.parts1) * rows_per_pass;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon1 + l.n_diag1 * (l.parts1 + 1));
     }
@@ -895,7 +910,7 @@ quapi_status prepare_step3(quapi_ctx *c, bool rho, Step3Args *out) {
     const size_t cap = c->lay.a_bytes / c->csize;
     const size_t lds = step3_lds_bytes(c->prec, rho, a.R, a.Q);
     if ((long long)a.grid * a.R * a.Q != a.m_count || (size_t)a.m_count * N * N * N > cap ||
-        a.grid > c->lay.partial_blocks || lds > (size_t)kLdsLimit || a.R > kBlock)
+        a.grid > c->lay.partial_blocks || lds > (size_t)kLdsLimitStep3 || a.R > kBlock)
         return fail(c, QUAPI_ERR_DEVICE, "internal three-step launch check failed");
     const size_t per = (size_t)N * (sp.R + sp.Q + sp.grid);
     for (int k = 0; k < 6; ++k) {
@@ -973,9 +988,21 @@ hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows, bo
     hipError_t e = hipSuccess;
     const bool fork = concurrent && l.n_diag3 > 0 && l.n_canon3 > 0;
     hipStream_t small = fork ? c->aux : c->stream;
+    auto mode1 = [&]() {
+        if (e == hipSuccess && l.n_canon3 > 0) {
+            a.mode = 1;
+            a.blk_hi = c->blk3;
+            a.n_blk = l.n_canon3;
+            a.parts = 1;
+            a.part_base = 0;
+            e = launch_step3(c->prec, rho, a, c->stream);
+        }
+    };
     if (fork) {
         e = hipEventRecord(c->ev_fork, c->stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+    } else {
+        mode1();                                  // one stream: the large launch first
     }
     if (e == hipSuccess && l.n_diag3 > 0) {
         a.mode = 2;
@@ -994,16 +1021,11 @@ hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows, bo
         a.part_base = l.n_canon3 + l.n_diag3 * l.parts3;
         e = launch_step3(c->prec, rho, a, small);
     }
-    if (e == hipSuccess && fork) e = hipEventRecord(c->ev_join, c->aux);
-    if (e == hipSuccess && l.n_canon3 > 0) {
-        a.mode = 1;
-        a.blk_hi = c->blk3;
-        a.n_blk = l.n_canon3;
-        a.parts = 1;
-        a.part_base = 0;
-        e = launch_step3(c->prec, rho, a, c->stream);
+    if (fork) {
+        if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->aux);
+        mode1();
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_join, 0);
     }
-    if (e == hipSuccess && fork) e = hipStreamWaitEvent(c->stream, c->ev_join, 0);
     *rows = l.n_canon3 + l.n_diag3 * (l.parts3 + 1);
     return e;
 }
@@ -1036,9 +1058,7 @@ quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
         e1 = take_event(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
-    // the fork and join cost ~10-20 us: worth it from L = 14 (M = 2) only
-    // (L = 15: 3.79 -> 3.71 ms per launch; L = 13: 0.37 -> 0.38 ms)
-    const bool concurrent = ipow_ll(c->N, c->L) >= (1LL << 28);
+    const bool concurrent = step3_concurrent((size_t)ipow_ll(c->N, c->L));
     int rows = 0;
     hipError_t e = launch_step3_modes(c, rho, a, &rows, concurrent);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "three-step launch: %s", hipGetErrorString(e));

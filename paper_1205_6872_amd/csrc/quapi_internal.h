@@ -13,6 +13,9 @@ constexpr int kMaxL = 30;
 constexpr int kBlock = 256;              // threads per block of every propagation kernel
 constexpr int kGL = 16;                  // Gauss-Legendre nodes per quadrature panel
 constexpr int kLdsLimit = 64 * 1024;     // LDS bytes a step block may use
+// gfx950 has 160 KB of LDS per compute unit; the three-step kernel with FP32
+// arithmetic keeps its rho sums there (about 73 KB per block, two blocks per CU)
+constexpr int kLdsLimitStep3 = 80 * 1024;
 
 // Tensor precision (values of quapi_dtype): storage / arithmetic.
 constexpr int kPrecC128 = 0;             // complex128 / FP64

@@ -16,8 +16,11 @@
 namespace quapi {
 namespace {
 
+// With FP32 arithmetic (csize 8) and rho, each thread's FP64 rho sums live
+// in LDS (acc: [3][N][kBlock]) instead of 48 registers, which lets the kernel
+// fit two waves per SIMD.
 struct Step3Lds {
-    unsigned tq, plo, phi, red, total;
+    unsigned tq, plo, phi, red, acc, total;
 };
 __host__ __device__ inline Step3Lds step3_lds_layout(int csize, bool rho, int R, int Q) {
     constexpr int N = 4;
@@ -28,6 +31,7 @@ __host__ __device__ inline Step3Lds step3_lds_layout(int csize, bool rho, int R,
     l.plo = lds_take(off, ns * N * R * csize);
     l.phi = lds_take(off, ns * N * 16);
     l.red = lds_take(off, rho ? 3 * (kBlock / 64) * N * 16 : 0);
+    l.acc = lds_take(off, rho && csize == 8 ? 3 * N * kBlock * 16 : 0);
     l.total = off;
     return l;
 }
@@ -119,8 +123,9 @@ __device__ __forceinline__ C cconj(C v) {
 }
 
 template <typename S, typename T, bool RHO, int MODE>
-__global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
+__global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 2 : 1) step3_kernel(const Step3Args a) {
     constexpr bool HALF = MODE != 0;
+    constexpr bool ACC_LDS = RHO && sizeof(T) == 4;
     constexpr int N = 4, NNN = 64;
     constexpr int NS = RHO ? 6 : 3;
     using C = typename Cx<T>::type;
@@ -132,6 +137,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
     C *s_plo = (C *)(smem + lay.plo);          // [NS][N][R]
     double2 *s_phi = (double2 *)(smem + lay.phi);
     double2 *s_red = (double2 *)(smem + lay.red);
+    double2 *s_acc = (double2 *)(smem + lay.acc);
     const T *coef = (const T *)a.coef;
 
     const int t = threadIdx.x;
@@ -155,29 +161,36 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
     }
     __syncthreads();
 
-    double2 acc[RHO ? 3 : 1][RHO ? N : 1];
+    double2 acc[(RHO && !ACC_LDS) ? 3 : 1][(RHO && !ACC_LDS) ? N : 1];
 #pragma unroll
-    for (int s = 0; s < (RHO ? 3 : 1); ++s)
+    for (int s = 0; s < 3; ++s)
 #pragma unroll
-        for (int o = 0; o < (RHO ? N : 1); ++o) acc[s][o] = make_double2(0.0, 0.0);
+        for (int o = 0; o < N; ++o) {
+            if (ACC_LDS) s_acc[(s * N + o) * kBlock + t] = make_double2(0.0, 0.0);
+            else if (RHO) acc[s][o] = make_double2(0.0, 0.0);
+        }
+    // this thread's rho sum of stage s and point o
+    auto acc_at = [&](int s, int o) -> double2 & {
+        return ACC_LDS ? s_acc[(s * N + o) * kBlock + t] : acc[ACC_LDS ? 0 : s][ACC_LDS ? 0 : o];
+    };
     auto factor = [&](int set, int o, int r, int qm) {
         return cmul(s_plo[(set * N + o) * R + r], s_tq[(set * N + o) * Q + qm]);
     };
     // rho terms v[o] of one item; in mirror mode the mirrored item adds
     // conj(v[mirror(o)]) (o = 0, 3 are their own mirrors, 1 and 2 swap)
-    auto add_rho = [&](double2 *ac, const double2 *v, bool both) {
+    auto add_rho = [&](int s, const double2 *v, bool both) {
         if (HALF && both) {
-            ac[0].x += 2.0 * v[0].x;
-            ac[1].x += v[1].x + v[2].x;
-            ac[1].y += v[1].y - v[2].y;
-            ac[2].x += v[2].x + v[1].x;
-            ac[2].y += v[2].y - v[1].y;
-            ac[3].x += 2.0 * v[3].x;
+            acc_at(s, 0).x += 2.0 * v[0].x;
+            acc_at(s, 1).x += v[1].x + v[2].x;
+            acc_at(s, 1).y += v[1].y - v[2].y;
+            acc_at(s, 2).x += v[2].x + v[1].x;
+            acc_at(s, 2).y += v[2].y - v[1].y;
+            acc_at(s, 3).x += 2.0 * v[3].x;
         } else {
 #pragma unroll
             for (int o = 0; o < N; ++o) {
-                ac[o].x += v[o].x;
-                ac[o].y += v[o].y;
+                acc_at(s, o).x += v[o].x;
+                acc_at(s, o).y += v[o].y;
             }
         }
     };
@@ -247,7 +260,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                     double2 v[N];
 #pragma unroll
                     for (int o = 0; o < N; ++o) v[o] = to_d2(cmul(factor(3, o, r, qm), tf[o == 3 ? 0 : o]));
-                    add_rho(acc[0], v, !selfm);
+                    add_rho(0, v, !selfm);
                 }
                 asm volatile("" ::: "memory");
                 const T *co = fresh(coef);
@@ -304,7 +317,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                     double2 v[N];
 #pragma unroll
                     for (int op = 0; op < N; ++op) v[op] = to_d2(cmul(factor(4, op, r, qm), tf[op]));
-                    add_rho(acc[1], v, !selfm);
+                    add_rho(1, v, !selfm);
                 }
                 asm volatile("" ::: "memory");
                 const T *co = fresh(coef);
@@ -366,7 +379,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
                     double2 v[N];
 #pragma unroll
                     for (int opp = 0; opp < N; ++opp) v[opp] = to_d2(cmul(factor(5, opp, r, qm), tf[opp]));
-                    add_rho(acc[2], v, !selfm);
+                    add_rho(2, v, !selfm);
                 }
                 asm volatile("" ::: "memory");
                 const T *co = fresh(coef);
@@ -412,7 +425,7 @@ __global__ void __launch_bounds__(kBlock) step3_kernel(const Step3Args a) {
         for (int s = 0; s < 3; ++s) {
 #pragma unroll
             for (int o = 0; o < N; ++o) {
-                double2 v = acc[s][o];
+                double2 v = acc_at(s, o);
                 for (int off = 32; off > 0; off >>= 1) {
                     v.x += __shfl_xor(v.x, off, 64);
                     v.y += __shfl_xor(v.y, off, 64);

@@ -103,7 +103,7 @@ def mirror_launches(R, Q, grid, block=256):
     diag = [h for h in range(grid) if h == mirror4(h)]
     rows_per_pass = block // R
     passes = (Q + rows_per_pass - 1) // rows_per_pass
-    parts = (passes + 3) // 4
+    parts = max(1, min(passes, -(-256 // max(len(diag), 1))))
     span = ((passes + parts - 1) // parts) * rows_per_pass
     dl, dm = int(round(np.log(R) / np.log(4))), int(round(np.log(Q) / np.log(4)))
     runs = []
@@ -266,7 +266,7 @@ def mfma_mirror_launches(Q, grid, waves=4):
     canon = [h for h in range(grid) if h < mirror16(h)]
     diag = [h for h in range(grid) if h == mirror16(h)]
     passes = (Q + waves - 1) // waves
-    parts = (passes + 3) // 4
+    parts = max(1, min(passes, -(-256 // max(len(diag), 1))))
     span = ((passes + parts - 1) // parts) * waves
     dm = int(round(np.log(Q) / np.log(16)))
     runs = []
@@ -354,7 +354,7 @@ def vector_mirror_launches(N, R, Q, grid, block=256):
     diag = [h for h in range(grid) if h == mir(h)]
     cR = block // R
     passes = (Q + cR - 1) // cR
-    parts = (passes + 3) // 4
+    parts = max(1, min(passes, -(-256 // max(len(diag), 1))))
     span = ((passes + parts - 1) // parts) * cR
     n_rows = 1
     q = Q
