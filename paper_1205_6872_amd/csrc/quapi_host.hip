@@ -288,10 +288,14 @@ struct Layout {
 
 constexpr int kSlots = 4;    // rho partial buffers: a fused launch takes two
 
-// The three-step mirror launches run modes 2, 3 concurrently with mode 1 from
-// 2^28 entries: the fork and join cost ~10-20 us, more than they hide below
-// (L = 15: 3.79 -> 3.71 ms per launch with rho; L = 13: 0.37 -> 0.38 ms).
-bool step3_concurrent(size_t entries) { return entries >= (size_t(1) << 28); }
+// The three-step mirror launches run modes 2, 3 concurrently with mode 1 with
+// FP32 arithmetic from 2^28 entries (measured on one GPU, the same build with
+// and without: L = 15 complex64 1.88 -> 1.84 ms per launch; complex128 no
+// gain, 3.62 -> 3.64 ms; below 2^28 entries the fork and join cost more than
+// they hide).
+bool step3_concurrent(size_t entries, int prec) {
+    return prec == kPrecC64 && entries >= (size_t(1) << 28);
+}
 
 // Blocks per high-digit value in mirror mode 2: about one block per compute
 // unit (256 on MI355X) over the n_diag values, at most one per sweep pass.
@@ -334,7 +338,8 @@ Layout make_layout(const quapi_params &p, int n_panels) {
         // blocks (about four sweep rows per thread) cost less setup
         const int rows_per_pass = kBlock / s3.R;
         const int passes = (s3.Q + rows_per_pass - 1) / rows_per_pass;
-        l.parts3 = step3_concurrent(entries) ? (passes + 3) / 4 : mirror_parts(passes, l.n_diag3);
+        l.parts3 = step3_concurrent(entries, p.dtype == QUAPI_C64 ? kPrecC64 : kPrecC128)
+                       ? (passes + 3) / 4 : mirror_parts(passes, l.n_diag3);
         l.span3 = ((passes + l.parts3 - 1) / l.parts3) * rows_per_pass;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon3 + l.n_diag3 * (l.parts3 + 1));
     }
@@ -1058,7 +1063,7 @@ quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
         e1 = take_event(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
-    const bool concurrent = step3_concurrent((size_t)ipow_ll(c->N, c->L));
+    const bool concurrent = step3_concurrent((size_t)ipow_ll(c->N, c->L), c->prec);
     int rows = 0;
     hipError_t e = launch_step3_modes(c, rho, a, &rows, concurrent);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "three-step launch: %s", hipGetErrorString(e));
