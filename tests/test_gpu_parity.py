@@ -309,6 +309,15 @@ def test_maximum_size_m2_l16_fused_group_c128():
     _sampled_fused_check(w, "c128", 1e-12)
 
 
+def test_maximum_size_m2_l17_fused_group_c64():
+    # 4^17 = 1.7e10 entries, complex64 (2 x 137 GB of the 288 GB HBM3E); one
+    # three-step launch in mirror mode, entry offsets past 2^34
+    w = W.spin_boson_l15("c64").with_(L=17, name="spin_boson_l17")
+    if not _fits(w, "c64"):
+        pytest.skip("footprint exceeds free device memory")
+    _sampled_fused_check(w, "c64", 3e-5)
+
+
 def test_maximum_size_m4_l8_single_steps_c64():
     # 16^8 = 4.3e9 entries, complex64 (2 x 34.4 GB); N = 16 runs single steps
     rng = np.random.default_rng(23)
