@@ -90,3 +90,33 @@ def test_pulse_area_sweep_final_point_only():
     # state; 0.8 pi lifts most of it (sin^2(0.4 pi) = 0.90 without phonons)
     pe = [r.rho[-1, 1, 1].real for r in res]
     assert abs(pe[0]) < 1e-12 and pe[1] > 0.5 and pe[2] < pe[1]
+
+
+def test_mirror_sized_requests_same_alone_and_in_the_mix():
+    """Requests large enough for mirror mode (M = 2, L = 12: three-step
+    passes; M = 3, L = 7 and M = 4, L = 6: single steps above 2^22 entries),
+    served in chunks that leave the tensor half-valid between calls, equal
+    the same requests run alone; one is also checked against the oracle."""
+    from oracle import run as orun
+    from paper_1205_6872_amd.serve import Server
+    rng = np.random.default_rng(31)
+    base = W.spin_boson_l7()
+    reqs = [
+        base.with_(name="m2_l12", L=12, n_steps=40, dtype="c128"),
+        base.with_(name="m2_l12_c64", L=12, n_steps=37, dtype="c64"),
+        W.three_site_l8().with_(name="m3_l7", L=7, n_steps=20, xi=0.3),
+        base.with_(name="m4_l6", M=4, s=np.linspace(-1, 1, 4), H=W.random_hermitian(rng, 4),
+                   rho0=np.diag([0.7, 0.1, 0.1, 0.1]).astype(complex), L=6, xi=0.3, n_steps=15),
+    ]
+    for k, w in enumerate(reqs):
+        w.meta["arrival_s"] = 0.0
+    for w in reqs:
+        with Q.create(Q.params_from(w)) as ctx:
+            assert ctx.mirror() == 1
+    res = Server(max_active=4, chunk_steps=7).run(reqs, realtime=False)
+    for w, r in zip(reqs, res):
+        alone = _alone(w)
+        assert np.array_equal(r.rho, alone), (w.name, np.abs(r.rho - alone).max())
+    o = orun.oracle_run(reqs[3], reqs[3].n_steps)
+    err = np.abs(res[3].rho - o).max() / np.abs(o).max()
+    assert err <= 1e-12, err
