@@ -26,8 +26,9 @@ thread_local std::string g_last_error;
 constexpr size_t kAlign = 256;
 constexpr int kRhoStage = 1024;          // rho slots of the blocking-call staging buffer
 constexpr double kOhmicCutoffFactor = 46.0;  // exp(-46) ~ 1e-20 of the integrand left out
-// Full-window steps of tensors up to this many entries are replayed from a
-// captured graph of two steps: they are launch-bound, not HBM-bound.
+// Full-window steps of tensors up to this many entries are replayed from
+// captured graphs (two single steps, or one fused launch): they are bound by
+// their launches, not by HBM.  The single step takes mirror mode only above it.
 constexpr size_t kGraphMaxEntries = size_t(1) << 22;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -280,7 +281,7 @@ struct Layout {
     size_t total;
     int n_panels, n_tables, partial_blocks;
     int n_canon3, n_diag3, parts3, span3;   // mirror mode of the three-step kernel (high-digit blocks)
-    int n_canon1, n_diag1, parts1, span1;   // mirror mode of the N = 9, 16 single step (main split)
+    int n_canon1, n_diag1, parts1, span1;   // mirror mode of the single step (main split)
     DigitSplit main_split;   // digit split of the full-window steps
     DigitSplit split2;       // digit split of the fused two-step kernel
     DigitSplit split3;       // digit split of the three-step kernel
@@ -1170,9 +1171,12 @@ quapi_status check_selection(quapi_ctx *c, int n_steps, const int *sel, int n_se
 // output of n_out slots (async), or NULL to stage and copy into host_out.
 //
 // Dispatch per step n: growth steps and the first full-window step run one
-// launch each; later full-window steps run in fused pairs when N = 4 (one pass
-// per two steps), else singly; small tensors replay captured graphs of two
-// steps.  A call that ends inside a pair runs its last step singly.
+// launch each; later full-window steps run in fused groups of F = c->fuse
+// steps when N = 4 (one pass per group, groups fixed by the global step
+// number), else singly; small tensors replay captured graphs.  A call that
+// ends inside a group runs that group's steps singly.  In mirror mode the
+// tensor may hold only its kept half between launches (c->half_cur); a
+// launch that reads every entry fills the other half first.
 quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel, double2 *dev_out,
                             double *host_out) {
     int n_out = 0;

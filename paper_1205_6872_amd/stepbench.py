@@ -7,10 +7,13 @@
 For each case (M levels, memory length L) and storage/arithmetic mode it runs
 the growth steps, then K full-window steps with rho at every step and K
 without, and prints one JSON line per case: the mean full-window launch time
-with and without rho, steps per launch (2 where two steps are fused), and the
-algorithmic HBM rate 2 * N^L * sizeof(complex) per step.  The system is a
-seeded random Hermitian H with evenly spaced coupling eigenvalues and an
-Ohmic bath (xi = 0.3, omega_c = 7.5, kT = 0.2, dt = 0.25).
+with and without rho (in mirror mode the launches of one step or group
+count as one), steps per launch (2 or 3 where steps are fused), the mirror
+mode, and the step-equivalent rate 2 * N^L * sizeof(complex) per step (the
+bytes of one full-tensor step).  --fused-steps pins the width, --mirror the
+mode (on: at every size).  The system is a seeded random Hermitian H with
+evenly spaced coupling eigenvalues and an Ohmic bath (xi = 0.3,
+omega_c = 7.5, kT = 0.2, dt = 0.25).
 """
 from __future__ import annotations
 
