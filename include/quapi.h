@@ -203,19 +203,20 @@ quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps);
 quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps);
 
 /* Mirror mode of the full-window kernels: the three-step kernel (M = 2,
- * L >= 4) and the single step (M = 2, 3, 4; L >= 2).  Swapping the forward and
+ * L >= 4), the two-step kernel (M = 2, L >= 3) and the single step (M = 2, 3,
+ * 4; L >= 2).  Swapping the forward and
  * backward path of every point maps the path sum of Sec. II to its complex
  * conjugate: K = U (x) U* and every influence factor go to their conjugates,
  * and so does rho(0) when it is Hermitian.  So the tensor entry of the
  * mirrored paths is the conjugate of the entry itself, and a pass reads and
  * writes only the entries not above their mirror (flat index, each digit
  * (a, b) -> (b, a)) -- about half the bytes.  rho at every step is unchanged
- * up to rounding.  On by default where available.  The single step uses it
- * for tensors above 2^22 entries only (smaller steps are bound by their
- * launches, and mirror mode takes three); the three-step kernel always.  The
- * entries above their mirror are filled in (one pass over the tensor)
- * before anything that reads the whole tensor: the two-step kernel, a single
- * step that does not take mirror mode, quapi_read_tensor.
+ * up to rounding.  On by default where available.  The single step and the
+ * two-step kernel use it for tensors above 2^22 entries only (smaller steps
+ * are bound by their launches, and mirror mode takes three); the three-step
+ * kernel always.  The entries above their mirror are filled in (one pass
+ * over the tensor) before anything that reads the whole tensor: a kernel
+ * that does not take mirror mode, quapi_read_tensor.
  *   quapi_mirror:      *enabled = the mode: 0 off, 1 on (default), 2 on at every size.
  *   quapi_set_mirror:  enable = 0, 1 or 2 as above.
  * Errors: QUAPI_ERR_INVALID for NULL arguments, enable outside 0..2, or enable > 0 where it is not

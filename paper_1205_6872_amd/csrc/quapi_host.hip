@@ -277,10 +277,11 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_Ht, off_Ut, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
-    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_blk1, off_pairs, off_sink;
+    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_blk2, off_blk1, off_pairs, off_sink;
     size_t total;
     int n_panels, n_tables, partial_blocks;
     int n_canon3, n_diag3, parts3, span3;   // mirror mode of the three-step kernel (high-digit blocks)
+    int n_canon2, n_diag2, parts2, span2;   // mirror mode of the two-step kernel
     int n_canon1, n_diag1, parts1, span1;   // mirror mode of the single step (main split)
     DigitSplit main_split;   // digit split of the full-window steps
     DigitSplit split2;       // digit split of the fused two-step kernel
@@ -344,6 +345,20 @@ Layout make_layout(const quapi_params &p, int n_panels) {
         l.span3 = ((passes + l.parts3 - 1) / l.parts3) * rows_per_pass;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon3 + l.n_diag3 * (l.parts3 + 1));
     }
+    if (fused_ok(N, L)) {
+        // the two-step kernel: the same partition over its block digits
+        const DigitSplit &s2 = l.split2;
+        for (int h = 0; h < s2.grid; ++h) {
+            const long long hb = mirror4(h);
+            if (h < hb) ++l.n_canon2;
+            else if (h == hb) ++l.n_diag2;
+        }
+        const int rows_per_pass = kBlock / s2.R;
+        const int passes = (s2.Q + rows_per_pass - 1) / rows_per_pass;
+        l.parts2 = mirror_parts(passes, l.n_diag2);
+        l.span2 = ((passes + l.parts2 - 1) / l.parts2) * rows_per_pass;
+        l.partial_blocks = std::max(l.partial_blocks, l.n_canon2 + l.n_diag2 * (l.parts2 + 1));
+    }
     if (single_mirror_ok(N, L, l.main_split)) {
         // the N = 9 step and the N = 16 MFMA step: the same partition over
         // their block digits; a block sweeps its rows with its 4 waves (MFMA)
@@ -403,6 +418,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_plan3 = take(triple ? (size_t)6 * N * (s3.R + s3.Q + s3.grid) * 16 : 0);
     l.off_coef3 = take(triple ? (size_t)kC3Count * 16 : 0);
     l.off_blk3 = take(triple ? (size_t)(l.n_canon3 + l.n_diag3) * sizeof(int) : 0);
+    l.off_blk2 = take((size_t)(l.n_canon2 + l.n_diag2) * sizeof(int));
     l.off_blk1 = take((size_t)(l.n_canon1 + l.n_diag1) * sizeof(int));
     l.total = off;
     return l;
@@ -467,7 +483,9 @@ struct quapi_ctx {
     bool half_cur = false;
     int *blk3 = nullptr;          // high-digit values: n_canon3 below their mirror, then n_diag3 equal
     std::vector<int> blk3_h;
-    int *blk1 = nullptr;          // the same for the N = 16 MFMA step (n_canon1, n_diag1)
+    int *blk2 = nullptr;          // the same for the two-step kernel (n_canon2, n_diag2)
+    std::vector<int> blk2_h;
+    int *blk1 = nullptr;          // the same for the single step (n_canon1, n_diag1)
     std::vector<int> blk1_h;
     double2 *plan3 = nullptr;
     void *coef3 = nullptr;
@@ -858,10 +876,60 @@ quapi_status prepare_step2(quapi_ctx *c, bool rho, Step2Args *out) {
     return QUAPI_OK;
 }
 
+// The two-step kernel runs in mirror mode above the graph size, as the
+// single step does (the same launch-count trade-off).
+bool pair_mirror_on(const quapi_ctx *c) {
+    return c->mirror != 0 && fused_ok(c->N, c->L) &&
+           (c->mirror == 2 || (size_t)ipow_ll(c->N, c->L) > kGraphMaxEntries);
+}
+
+// Launch the two-step kernel with the arguments of prepare_step2: every block
+// (mode 0), or in mirror mode the launches over the high-digit values below
+// their mirror (mode 1) and equal to it (modes 2, 3).  *rows: the rho
+// partial rows written.
+hipError_t launch_step2_modes(quapi_ctx *c, bool rho, Step2Args a, int *rows) {
+    if (!pair_mirror_on(c)) {
+        a.mode = 0;
+        *rows = a.grid;
+        return launch_step2(c->prec, rho, a, c->stream);
+    }
+    const Layout &l = c->lay;
+    hipError_t e = hipSuccess;
+    if (l.n_canon2 > 0) {
+        a.mode = 1;
+        a.blk_hi = c->blk2;
+        a.n_blk = l.n_canon2;
+        a.parts = 1;
+        a.part_base = 0;
+        e = launch_step2(c->prec, rho, a, c->stream);
+    }
+    if (e == hipSuccess && l.n_diag2 > 0) {
+        a.mode = 2;
+        a.blk_hi = c->blk2 + l.n_canon2;
+        a.n_blk = l.n_diag2 * l.parts2;
+        a.parts = l.parts2;
+        a.q_span = l.span2;
+        a.part_base = l.n_canon2;
+        e = launch_step2(c->prec, rho, a, c->stream);
+    }
+    if (e == hipSuccess && l.n_diag2 > 0) {
+        a.mode = 3;
+        a.blk_hi = c->blk2 + l.n_canon2;
+        a.n_blk = l.n_diag2;
+        a.parts = 1;
+        a.part_base = l.n_canon2 + l.n_diag2 * l.parts2;
+        e = launch_step2(c->prec, rho, a, c->stream);
+    }
+    *rows = l.n_canon2 + l.n_diag2 * (l.parts2 + 1);
+    return e;
+}
+
 // Enqueue the fused steps n, n+1 (n > L); rho of the selected ones goes to
 // the sink in step order.
 quapi_status enqueue_step2(quapi_ctx *c, int n, bool sel_n, bool sel_n1) {
-    if (quapi_status fs = ensure_full(c); fs != QUAPI_OK) return fs;
+    const bool half = pair_mirror_on(c);      // reads and writes the kept half only
+    if (!half)
+        if (quapi_status fs = ensure_full(c); fs != QUAPI_OK) return fs;
     const bool rho = sel_n || sel_n1;
     Step2Args a;
     quapi_status st = prepare_step2(c, rho, &a);
@@ -883,7 +951,8 @@ quapi_status enqueue_step2(quapi_ctx *c, int n, bool sel_n, bool sel_n1) {
         e1 = take_event(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
-    hipError_t e = launch_step2(c->prec, rho, a, c->stream);
+    int rows = 0;
+    hipError_t e = launch_step2_modes(c, rho, a, &rows);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "fused step launch: %s", hipGetErrorString(e));
     if (c->timing && e0 && e1) {
         (void)hipEventRecord(e1, c->stream);
@@ -893,10 +962,11 @@ quapi_status enqueue_step2(quapi_ctx *c, int n, bool sel_n, bool sel_n1) {
         int fin[2], nf = 0;
         if (sel_n) fin[nf++] = slots[0];
         if (sel_n1) fin[nf++] = slots[1];
-        st = finalize_side(c, fin, nf, a.grid);
+        st = finalize_side(c, fin, nf, rows);
         if (st != QUAPI_OK) return st;
     }
     c->cur = 1 - c->cur;
+    c->half_cur = half;
     c->step = n + 1;
     return QUAPI_OK;
 }
@@ -1115,9 +1185,10 @@ quapi_status build_graph(quapi_ctx *c, bool rho, int width, int par, hipGraphExe
         a2.a_out = c->A[1 - par];
         a2.partials[0] = c->partials[0];
         a2.partials[1] = c->partials[1];
-        e = launch_step2(c->prec, rho, a2, c->stream);
+        int rows = 0;
+        e = launch_step2_modes(c, rho, a2, &rows);
         for (int k = 0; k < 2 && rho && e == hipSuccess; ++k)
-            e = launch_rho_finalize(c->N, c->partials[k], a2.grid, c->pairs, c->sink, c->stream);
+            e = launch_rho_finalize(c->N, c->partials[k], rows, c->pairs, c->sink, c->stream);
     } else {
         for (int k = 0; k < 2 && e == hipSuccess; ++k) {
             StepArgs a = sp.args;
@@ -1271,7 +1342,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
                     c->graph_failed = true;   // stay on direct launches
                 } else {
                     st = join_side(c);        // the graph reuses partial buffers 0 and 1
-                    const bool half = !fused && single_mirror_on(c);
+                    const bool half = fused ? pair_mirror_on(c) : single_mirror_on(c);
                     if (st == QUAPI_OK && !half) st = ensure_full(c);
                     if (st != QUAPI_OK) return st;
                     HIP_TRY(c, hipGraphLaunch(gx, c->stream));
@@ -1472,6 +1543,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->plan3 = (double2 *)(w + lay.off_plan3);
     c->coef3 = w + lay.off_coef3;
     c->blk3 = (int *)(w + lay.off_blk3);
+    c->blk2 = (int *)(w + lay.off_blk2);
     c->blk1 = (int *)(w + lay.off_blk1);
     c->n_H = p->n_H;
     c->Ht_d = (const double2 *)(w + lay.off_Ht);
@@ -1498,6 +1570,11 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
                 for (int h = 0; h < lay.split3.grid; ++h)
                     if (pass == 0 ? h < mirror4(h) : h == mirror4(h)) c->blk3_h.push_back(h);
             c->mirror_ok = herm;
+        }
+        if (fused_ok(N, L)) {
+            for (int pass = 0; pass < 2; ++pass)
+                for (int h = 0; h < lay.split2.grid; ++h)
+                    if (pass == 0 ? h < mirror4(h) : h == mirror4(h)) c->blk2_h.push_back(h);
         }
         if (single_mirror_ok(N, L, lay.main_split)) {
             for (int pass = 0; pass < 2; ++pass)
@@ -1529,6 +1606,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     if (e == hipSuccess && c->n_H > 0) e = up(lay.off_Ht, c->Ht_h.data(), c->Ht_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_rho0, c->rho0_h.data(), (size_t)N * 16);
     if (e == hipSuccess && !c->blk3_h.empty()) e = up(lay.off_blk3, c->blk3_h.data(), c->blk3_h.size() * sizeof(int));
+    if (e == hipSuccess && !c->blk2_h.empty()) e = up(lay.off_blk2, c->blk2_h.data(), c->blk2_h.size() * sizeof(int));
     if (e == hipSuccess && !c->blk1_h.empty()) e = up(lay.off_blk1, c->blk1_h.data(), c->blk1_h.size() * sizeof(int));
     if (e == hipSuccess) e = up(lay.off_pa, c->pa_h.data(), c->pa_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_ph, c->ph_h.data(), c->ph_h.size() * 8);
@@ -1663,7 +1741,7 @@ quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable) {
     if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
     if (enable < 0 || enable > 2) return fail(ctx, QUAPI_ERR_INVALID, "enable must be 0, 1 or 2");
     if (enable == ctx->mirror) return QUAPI_OK;
-    // the captured three-step graphs hold the launches of the old mode
+    // the captured graphs hold the launches of the old mode
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     for (auto &row : ctx->graph3)
         for (auto &g : row) {
@@ -1674,6 +1752,11 @@ quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable) {
         if (g) (void)hipGraphExecDestroy(g);
         g = nullptr;
     }
+    for (auto &row : ctx->graph2)
+        for (auto &g : row) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
     ctx->mirror = enable;
     return QUAPI_OK;
 }

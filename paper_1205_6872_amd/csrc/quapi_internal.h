@@ -87,6 +87,10 @@ struct Step2Args {
     long long m_count;
     int R, Q, grid;
     const void *coef;           // kCoefCount complex entries in the compute precision
+    // Mirror mode, as for the three-step kernel (Step3Args): modes 1, 2, 3
+    // over the high-digit values blk_hi[..]; rho partials at part_base + block.
+    const int *blk_hi;
+    int n_blk, parts, q_span, part_base, mode;
 };
 
 // Coefficients of the fused step in the compute precision, grouped by the new

@@ -61,7 +61,27 @@ __global__ void step2_coef_kernel(const CoefArgs a) {
 // rho(t_{n+1}) from y with those of step n+1; both are reduced per block.
 // The coefficients that do not depend on m are read per use through scalar
 // loads; the m-dependent digit products come from LDS.
-template <typename S, typename T, bool RHO>
+//
+// MODE 1, 2, 3: mirror mode, as in the three-step kernel (an entry and its
+// mirror, every digit 2a + b -> 2b + a, are conjugates): mode 1 the blocks
+// whose high digits are below their mirror; mode 2 those equal to it, the
+// items below their mirror; mode 3 the items that are their own mirror,
+// whose input slots above the mirror are read from the mirrored slot,
+// conjugated.  Outputs above their mirror go, conjugated, to the mirrored
+// address; each block adds the mirrored items' rho terms as
+// S[o] + conj(S[mirror(o)]) (modes 1, 2).
+__device__ __forceinline__ constexpr int mirror_digit4(int d) { return d == 1 ? 2 : d == 2 ? 1 : d; }
+__device__ __forceinline__ int diagonal_digits4(unsigned x) {    // bit k -> digit k = 3
+    int out = 0;
+    for (int k = 0; x > 0; ++k, x >>= 1) out += (int)(x & 1u) * 3 << (2 * k);
+    return out;
+}
+__device__ __forceinline__ bool diagonal_digits_only4(int v) {
+    for (; v > 0; v >>= 2)
+        if ((v & 3) == 1 || (v & 3) == 2) return false;
+    return true;
+}
+template <typename S, typename T, bool RHO, int MODE>
 __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
     constexpr int N = 4, NN = 16;
     constexpr int NS = RHO ? 4 : 2;
@@ -78,7 +98,9 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
 
     const int t = threadIdx.x;
     const int cR = kBlock / R, active = cR * R;
-    const long long blk = blockIdx.x;
+    const long long blk = MODE == 0   ? (long long)blockIdx.x
+                          : MODE == 2 ? (long long)a.blk_hi[blockIdx.x / a.parts]
+                                      : (long long)a.blk_hi[blockIdx.x];     // high digits
     if (t < NS * N) {
         const int s = t / N, o = t % N;
         s_phi[t] = a.t_hi[s][(size_t)o * a.grid + blk];
@@ -103,12 +125,27 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
         const CS *__restrict__ ain = (const CS *)a.a_in;
         CS *__restrict__ aout = (CS *)a.a_out;
         const long long mc = a.m_count;
-        for (int qm = t / R; qm < Q; qm += cR) {
+        // sweep rows: all (mode 0, 1), a part (mode 2), or in mode 3 those whose
+        // digits are all diagonal, for threads whose low digits are
+        const int part = MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
+        const bool thread_runs = MODE != 3 || diagonal_digits_only4(r);
+        const int dm = (31 - __clz(Q)) >> 1;
+        const int i0 = (MODE == 2 ? part * a.q_span : 0) + t / R;
+        const int i1 = !thread_runs ? 0 : MODE == 3 ? (1 << dm) : MODE == 2 ? min(Q, (part + 1) * a.q_span) : Q;
+        for (int it = i0; it < i1; it += cR) {
             asm volatile("" ::: "memory");
+            const int qm = MODE == 3 ? diagonal_digits4((unsigned)it) : it;
             const long long m = m0 + (long long)qm * R + r;
+            const long long mb = MODE == 0 ? m : mirror4(m);
+            if (MODE == 2 && mb <= m) continue;   // own mirror (mode 3), or run by its mirror
+            constexpr bool selfm = MODE == 3;
             C x[NN];
 #pragma unroll
-            for (int k = 0; k < NN; ++k) x[k] = conv<C>(ain[(long long)NN * m + k]);
+            for (int k = 0; k < NN; ++k) {
+                const int kb = (int)mirror4(k);
+                x[k] = conv<C>(ain[(long long)NN * m + (selfm && kb < k ? kb : k)]);
+                if (selfm && kb < k) x[k].y = -x[k].y;
+            }
             C cn1[N], totf[RHO ? N : 1];
 #pragma unroll
             for (int op = 0; op < N; ++op) {
@@ -180,7 +217,15 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
 #pragma unroll
                         for (int ip = 0; ip < N; ++ip) cmac(sum, coef_ld(co, kCoefDO + op * N + ip), y[ip]);
                     }
-                    aout[m + mc * (o + N * op)] = conv<CS>(cmul(cn1[op], sum));
+                    const C v = cmul(cn1[op], sum);
+                    const int c2 = o + N * op, c2b = mirror_digit4(o) + N * mirror_digit4(op);
+                    if (MODE == 0 || c2b >= c2) {
+                        aout[m + mc * c2] = conv<CS>(v);
+                    } else if (!selfm) {
+                        C vc = v;
+                        vc.y = -vc.y;
+                        aout[mb + mc * c2b] = conv<CS>(vc);
+                    }
                     if (RHO) {
                         if (dgp) {
                             cmac(totf[op], coef_ld(co, kCoefV + op * N), ysum);
@@ -221,13 +266,19 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
         }
         __syncthreads();
         if (t < 2 * N) {
-            const int which = t / N, o = t % N;
+            const int which = t / N, o = t % N, ob = mirror_digit4(o);
             double2 s = make_double2(0.0, 0.0);
             for (int w = 0; w < kBlock / 64; ++w) {
                 s.x += s_red[(which * (kBlock / 64) + w) * N + o].x;
                 s.y += s_red[(which * (kBlock / 64) + w) * N + o].y;
             }
-            a.partials[which][blk * N + o] = s;
+            if (MODE == 1 || MODE == 2) {           // the mirrored items' terms
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    s.x += s_red[(which * (kBlock / 64) + w) * N + ob].x;
+                    s.y -= s_red[(which * (kBlock / 64) + w) * N + ob].y;
+                }
+            }
+            a.partials[which][((size_t)a.part_base + (MODE == 0 ? blk : (long long)blockIdx.x)) * N + o] = s;
         }
     }
 }
@@ -236,7 +287,14 @@ template <typename S, typename T, bool RHO>
 hipError_t launch_step2_t(const Step2Args &a, hipStream_t st) {
     using C = typename Cx<T>::type;
     const Step2Lds lay = step2_lds_layout((int)sizeof(C), RHO, a.R, a.Q);
-    hipLaunchKernelGGL((step2_kernel<S, T, RHO>), dim3(a.grid), dim3(kBlock), lay.total, st, a);
+    const dim3 b(kBlock);
+    switch (a.mode) {
+    case 0: hipLaunchKernelGGL((step2_kernel<S, T, RHO, 0>), dim3(a.grid), b, lay.total, st, a); break;
+    case 1: hipLaunchKernelGGL((step2_kernel<S, T, RHO, 1>), dim3(a.n_blk), b, lay.total, st, a); break;
+    case 2: hipLaunchKernelGGL((step2_kernel<S, T, RHO, 2>), dim3(a.n_blk), b, lay.total, st, a); break;
+    case 3: hipLaunchKernelGGL((step2_kernel<S, T, RHO, 3>), dim3(a.n_blk), b, lay.total, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 """GPU parity of mirror mode (half of the tensor's entries read and written
-per pass; the rest are their mirrors' conjugates): the three-step kernel at
-M = 2, the vector step at M = 3 and the MFMA step at M = 4.
+per pass; the rest are their mirrors' conjugates): the three- and two-step
+kernels and the vector step at M = 2, the vector step at M = 3 and the MFMA
+step at M = 4.
 
 Each run is compared with the oracle (complex128: per step
 max|drho| <= 1e-12 max|rho|; complex64 storage 1e-5 / 1e-6 absolute) and
@@ -41,10 +42,10 @@ def case(L, seed):
     return W.spin_boson_l7().with_(L=L, H=W.random_hermitian(rng, 2), rho0=hermitian_rho0(seed), xi=0.4)
 
 
-def run(w, n, mirror, dtype="c128", chunks=None):
+def run(w, n, mirror, dtype="c128", chunks=None, F=3):
     # mirror mode on at every size (2): the single steps at the call ends too
     with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
-        ctx.set_fused_steps(3)
+        ctx.set_fused_steps(F)
         ctx.set_mirror(2 if mirror else 0)
         assert ctx.mirror() == (2 if mirror else 0)
         if chunks is None:
@@ -82,11 +83,12 @@ def test_mirror_mode_against_oracle_and_full_mode(L, seed, n):
     assert np.abs(A_m[~pair].imag).max() <= 1e-13 * scale       # entries that are their own mirror are real
 
 
+@pytest.mark.parametrize("F", [2, 3])
 @pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c64f64", 1e-6)])
-def test_mirror_mode_complex64_tiers(dtype, tol):
+def test_mirror_mode_complex64_tiers(dtype, tol, F):
     w = case(7, 6)
     n = 90
-    rho_m, _ = run(w, n, True, dtype=dtype)
+    rho_m, _ = run(w, n, True, dtype=dtype, F=F)
     o = orun.oracle_run(w, n)
     assert np.abs(rho_m - o).max() <= tol
     tr = np.trace(rho_m, axis1=1, axis2=2)
@@ -104,6 +106,55 @@ def test_calls_ending_inside_groups_fill_the_mirrored_half_first():
     assert rel_err_per_step(rho_m, o).max() <= TOL_C128
     assert rel_err_per_step(rho_m, rho_f).max() <= 1e-13
     assert np.abs(A_m - A_f).max() <= 1e-13 * np.abs(A_f).max()
+
+
+# ------------------------------------------------ M = 2: the two-step kernel
+@pytest.mark.parametrize("L,seed,n", [(3, 21, 31), (4, 22, 30), (5, 23, 33), (6, 24, 26), (9, 25, 21),
+                                      (10, 26, 19)])
+def test_pair_mirror_mode_against_oracle_and_full_mode(L, seed, n):
+    w = case(L, seed)
+    print(f"pairs L={L} seed={seed} steps={n}", flush=True)
+    rho_m, A_m = run(w, n, True, F=2)
+    rho_f, A_f = run(w, n, False, F=2)
+    o = orun.oracle_run(w, n)
+    assert rel_err_per_step(rho_m, o).max() <= TOL_C128
+    assert rel_err_per_step(rho_m, rho_f).max() <= 1e-13
+    scale = np.abs(A_f).max()
+    assert np.abs(A_m - A_f).max() <= 1e-13 * scale
+    x = np.arange(len(A_m))
+    mirror = ((x & 0x5555555555555555) << 1) | ((x >> 1) & 0x5555555555555555)
+    pair = mirror != x
+    if (n - L) % 2 == 0:
+        # the last launch was a mirror pair: the filled-in half is exactly the conjugate
+        assert np.array_equal(A_m[mirror[pair]], np.conj(A_m[pair]))
+    assert np.abs(A_m[~pair].imag).max() <= 1e-13 * scale
+
+
+def test_pair_calls_ending_inside_pairs_fill_the_mirrored_half_first():
+    w = case(6, 27)
+    chunks = [7, 3, 5, 1, 8, 2, 11, 4]
+    n = sum(chunks)
+    rho_m, A_m = run(w, n, True, chunks=chunks, F=2)
+    rho_f, A_f = run(w, n, False, chunks=chunks, F=2)
+    assert rel_err_per_step(rho_m, orun.oracle_run(w, n)).max() <= TOL_C128
+    assert rel_err_per_step(rho_m, rho_f).max() <= 1e-13
+    assert np.abs(A_m - A_f).max() <= 1e-13 * np.abs(A_f).max()
+
+
+def test_pair_mirror_mode_by_default_above_the_graph_size():
+    # L = 12 complex64 (4^12 entries): two steps per launch by default, in
+    # mirror mode (mode 1), against the same run with mirror mode off
+    w = case(12, 28)
+    n = 16
+    out = []
+    for mirror in (1, 0):
+        with Q.create(Q.params_from(w, dtype="c64")) as ctx:
+            assert ctx.fused_steps() == 2
+            ctx.set_mirror(mirror)
+            out.append(ctx.propagate(n, list(range(n + 1))))
+    rho_m, rho_f = out
+    assert np.abs(rho_m - rho_f).max() <= 1e-6
+    assert np.abs(rho_m - orun.oracle_run(w, n)).max() <= 1e-5
 
 
 def test_switching_mirror_mode_mid_run():

@@ -138,9 +138,61 @@ def test_mirror_launches_run_each_kept_item_once(R, Q, grid):
     assert max(row for _, row, _ in runs) < n_rows <= max(grid, 1) + (2 ** int(round(np.log(grid) / np.log(4)))) * 64
 
 
+def pair_mirror_launches(R, Q, grid, block=256):
+    """The items each mirror-mode launch of the two-step kernel runs, thread
+    by thread as the kernel maps them: mode 1 every row of a block whose high
+    digits are below their mirror; mode 2 the sweep rows of its part, items
+    below their mirror; mode 3 the threads whose low digits are all diagonal,
+    sweeping the diagonal middle digits.  Returns [(mode, partial row, item)]
+    and the number of partial rows."""
+    canon = [h for h in range(grid) if h < mirror4(h)]
+    diag = [h for h in range(grid) if h == mirror4(h)]
+    cols = block // R
+    passes = (Q + cols - 1) // cols
+    parts = max(1, min(passes, -(-256 // max(len(diag), 1))))
+    span = ((passes + parts - 1) // parts) * cols
+    dm = int(round(np.log(Q) / np.log(4)))
+    runs = []
+    for b, h in enumerate(canon):
+        for t in range(cols * R):
+            for q in range(t // R, Q, cols):
+                runs.append((1, b, h * R * Q + q * R + t % R))
+    for b in range(len(diag) * parts):
+        h, part = diag[b // parts], b % parts
+        for t in range(cols * R):
+            for q in range(part * span + t // R, min(Q, (part + 1) * span), cols):
+                m = h * R * Q + q * R + t % R
+                if mirror4(m) > m:
+                    runs.append((2, len(canon) + b, m))
+    for b, h in enumerate(diag):
+        for t in range(cols * R):
+            r = t % R
+            if mirror4(r) != r:                    # a low digit off the diagonal
+                continue
+            for it in range(t // R, 1 << dm, cols):
+                runs.append((3, len(canon) + len(diag) * parts + b, h * R * Q + diagonal_digits(it) * R + r))
+    return runs, len(canon) + len(diag) * (parts + 1)
+
+
+@pytest.mark.parametrize("R,Q,grid", [(4, 1, 1), (16, 1, 1), (64, 1, 1), (64, 4, 1), (64, 16, 1), (64, 64, 1),
+                                      (64, 64, 4), (64, 64, 64), (64, 16, 16)])
+def test_pair_mirror_launches_run_each_kept_item_once(R, Q, grid):
+    """The two-step kernel's split: R = 4^min(3, digits) low digits per
+    thread, Q = 4^(0..3) middle digits swept, the rest per block."""
+    runs, n_rows = pair_mirror_launches(R, Q, grid)
+    items = [m for _, _, m in runs]
+    assert len(items) == len(set(items))
+    assert set(items) == {m for m in range(R * Q * grid) if m <= mirror4(m)}
+    assert all(mode == 3 for mode, _, m in runs if mirror4(m) == m)
+    assert all(mode != 3 for mode, _, m in runs if mirror4(m) != m)
+    assert max(row for _, row, _ in runs) < n_rows
+
+
+@pytest.mark.parametrize("width", [2, 3])
 @pytest.mark.parametrize("nd", [0, 1, 3, 4, 5, 6])
-def test_mirror_pass_index_rules(nd):
-    """Items are m (nd digits) with 64 entries each.  Mode 1 runs the blocks
+def test_mirror_pass_index_rules(nd, width):
+    """Items are m (nd digits) with E = 4^width entries each (the two- and
+    three-step kernels).  Mode 1 runs the blocks
     whose high digits are below their mirror, with no per-item test; mode 2
     the blocks equal to their mirror, skipping items above their mirror.
     Input: only entries not above their mirror are valid.  Output: each item
@@ -149,7 +201,8 @@ def test_mirror_pass_index_rules(nd):
     rng = np.random.default_rng(nd)
     R, Q, grid = _split(nd)
     n_items = 4 ** nd
-    entries = 64 * n_items
+    E = 4 ** width
+    entries = E * n_items
     x = np.arange(entries)
     keep = x <= mirror4(x)
 
@@ -163,16 +216,16 @@ def test_mirror_pass_index_rules(nd):
     Y = symmetric(rng.normal(size=entries) + 1j * rng.normal(size=entries))   # what a full step would write
     Xh = np.where(keep, X, np.nan)                                           # half-valid input
     # output layout: entry (m, c) at m + n_items * c
-    out_index = (np.arange(n_items)[:, None] + n_items * np.arange(64)[None, :])
+    out_index = (np.arange(n_items)[:, None] + n_items * np.arange(E)[None, :])
     Yc = Y[out_index]                                                        # Yc[m, c]
-    assert np.array_equal(mirror4(out_index), out_index[mirror4(np.arange(n_items))][:, mirror4(np.arange(64))])
+    assert np.array_equal(mirror4(out_index), out_index[mirror4(np.arange(n_items))][:, mirror4(np.arange(E))])
 
     out = np.full(entries, np.nan + 0j)
     writes = np.zeros(entries, dtype=int)
     # rho-like linear functional with mirror-covariant weights: W[mirror(o), mirror(c)] = conj(W[o, c])
-    Wt = rng.normal(size=(4, 64)) + 1j * rng.normal(size=(4, 64))
+    Wt = rng.normal(size=(4, E)) + 1j * rng.normal(size=(4, E))
     for o in range(4):
-        for c in range(64):
+        for c in range(E):
             if (int(mirror4(o)), int(mirror4(c))) < (o, c):
                 Wt[o, c] = np.conj(Wt[int(mirror4(o)), int(mirror4(c))])
             elif (int(mirror4(o)), int(mirror4(c))) == (o, c):
@@ -194,18 +247,18 @@ def test_mirror_pass_index_rules(nd):
                     continue
                 ran.add(m)
                 self_m = m == mb
-                w = Xh[64 * m:64 * m + 64].copy()
+                w = Xh[E * m:E * m + E].copy()
                 if self_m:
-                    for k in range(64):
+                    for k in range(E):
                         if mirror4(k) < k:
                             w[k] = np.conj(w[mirror4(k)])
-                assert np.array_equal(w, X[64 * m:64 * m + 64])   # every value the item uses is valid
+                assert np.array_equal(w, X[E * m:E * m + E])      # every value the item uses is valid
                 v = Wt @ Yc[m]
                 if self_m:
                     rho_half += v
                 else:
                     rho_half += v + np.conj(v[[0, 2, 1, 3]])
-                for c in range(64):
+                for c in range(E):
                     cb = int(mirror4(c))
                     if cb >= c:
                         out[m + n_items * c] = Yc[m, c]
