@@ -6,12 +6,16 @@ default, rho(t_n) extracted at every step ('allPoints').  Inputs are
 synthetic (seeded parameters, no dataset).
 
 A timed "step" is one full-window propagation step.  For M = 2 the library
-fuses consecutive steps into one kernel launch (three at L = 15 in every
-precision mode): it reads the tensor once, keeps the intermediate tensors
-in registers, writes the tensor of the group's last step once, and produces
-per-block partial sums of rho at every step of the group in the same pass; a
-small finalize kernel on a side stream sums them.  So one launch moves
-2 * N^L * sizeof(complex) bytes and covers two or three steps.  The growth steps (n < L) and the device setup run first and
+fuses consecutive steps into one kernel launch (at L = 15 three with
+complex128 and complex64, two with complex64 storage and FP64 arithmetic):
+it reads the tensor once, keeps the intermediate tensors in registers,
+writes the tensor of the group's last step once, and produces per-block
+partial sums of rho at every step of the group in the same pass; a small
+finalize kernel on a side stream sums them.  So one launch moves
+2 * N^L * sizeof(complex) bytes and covers two or three steps; in mirror
+mode (on by default: rho0 is Hermitian) it reads and writes only the
+(N^L + M^L) / 2 entries not above their mirror, the rest being their
+conjugates.  The growth steps (n < L) and the device setup run first and
 are reported separately.  Three precisions run on the same workload:
 complex128 (the reported `value`), the complex64 tier with FP32 arithmetic
 (`fp32_tier`), and complex64 storage with FP64 arithmetic
@@ -29,7 +33,7 @@ arrivals) so the run stays within minutes; --serve-requests 512 serves all.
 Metric: Gelem/s = N^L * steps / seconds / 1e9, with the tensor resident in
 HBM.  `roofline` prices the step kernel against the HBM peak: algorithmic
 bytes per launch = 2 * N^L * sizeof(complex) (one read, one write of the
-tensor), divided by the kernel's average duration per launch from HIP events
+tensor; (N^L + M^L) * sizeof(complex) in mirror mode), divided by the kernel's average duration per launch from HIP events
 on the library's stream (`steps_per_launch` says how many steps a launch covers).
 `step_equivalent_gbs` divides the same bytes by the measured time per step:
 the rate an unfused step would need to match it.
@@ -93,7 +97,10 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         tm = ctx.get_timing()
-        mirror = ctx.mirror() and ctx.fused_steps() == 3     # only the three-step kernel has a mirror mode
+        # the fused kernels' mirror mode: the three-step kernel always, the
+        # two-step kernel above 2^22 entries (or at every size in mode 2)
+        F = ctx.fused_steps()
+        mirror = bool(ctx.mirror()) and (F == 3 or (F == 2 and (ctx.mirror() == 2 or N ** L > 2 ** 22)))
     finally:
         ctx.destroy()
         del ctx
@@ -119,18 +126,16 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
 
 def kernel_name(tier: str, steps_per_launch: float, mirror: bool = False) -> str:
     st = {"c128": "double, double", "c64": "float, float", "c64f64": "float, double"}[tier]
-    if steps_per_launch > 2.5 and mirror:
-        return (f"step3_kernel<{st}, rho, mirror> (three steps fused per launch, the entries not above "
-                f"their mirror only)")
+    half = ", the entries not above their mirror only" if mirror else ""
     if steps_per_launch > 2.5:
-        return f"step3_kernel<{st}, rho> (three steps fused per launch)"
+        return f"step3_kernel<{st}, rho{', mirror' if mirror else ''}> (three steps fused per launch{half})"
     if steps_per_launch > 1.5:
-        return f"step2_kernel<{st}, rho> (two steps fused per launch)"
+        return f"step2_kernel<{st}, rho{', mirror' if mirror else ''}> (two steps fused per launch{half})"
     return f"step_kernel<4, {st}, rho, full-window>"
 
 
 # The dominant kernel of each tier at M = 2, L = 15 and the sources it is built from.
-TIER_KERNEL = {"c128": "step3", "c64": "step3", "c64f64": "step3"}
+TIER_KERNEL = {"c128": "step3", "c64": "step3", "c64f64": "step2"}
 KERNEL_SOURCES = {"step2": ("quapi_step2.hip", "quapi_device.h", "quapi_internal.h"),
                   "step3": ("quapi_step3.hip", "quapi_device.h", "quapi_internal.h")}
 

@@ -192,10 +192,8 @@ quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries);
 quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps);
 
 /* Choose the full-window steps per launch: 1, 2 (N = 4, L >= 3), 3 (N = 4,
- * L >= 4), or 0 for the default: 3 at complex128 and QUAPI_C64 from L = 13
- * (where mirror mode is available, from L = 12 at complex128 and from L = 14
- * at QUAPI_C64_F64), else 2 where available, else 1; always 1 for a driven
- * context.  Every choice gives the same results to within rounding (the
+ * L >= 4), or 0 for the default: 3 at complex128 and QUAPI_C64 from L = 13,
+ * else 2 where available, else 1; always 1 for a driven context.  Every choice gives the same results to within rounding (the
  * fused kernels apply the same factors in another order); use it to pin the
  * kernel, e.g. in tests.  It takes effect from the next call.
  * Errors: QUAPI_ERR_INVALID for an unavailable width; QUAPI_ERR_STATE while

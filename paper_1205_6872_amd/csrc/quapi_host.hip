@@ -105,15 +105,14 @@ bool triple_ok(int N, int L) { return N == 4 && L >= 4; }
 // Full-window steps per launch chosen by default: three from L = 13 at
 // complex128 and at complex64 with FP32 arithmetic (4^10 items and more; the
 // step is HBM bound there, and a third step in registers saves a third of
-// the traffic); where the three-step kernel runs in mirror mode (half the
-// entries, and half the arithmetic) from L = 12 at complex128 and from L = 14
-// with complex64 storage and FP64 arithmetic; two otherwise.  A three-step
-// item runs one wave per SIMD through three dependent stages, so with fewer
-// items than that the two-step kernel finishes first; with complex64 storage
-// and FP64 arithmetic the full-tensor three-step kernel is bound by its
-// arithmetic.
-int fusion_width(int N, int L, int prec, bool mirror) {
-    const int from = prec == kPrecC128 ? (mirror ? 12 : 13) : prec == kPrecC64 ? 13 : (mirror ? 14 : 1 << 20);
+// the traffic); two otherwise.  A three-step item runs one wave per SIMD
+// through three dependent stages, so with fewer items than that the two-step
+// kernel finishes first; with complex64 storage and FP64 arithmetic the
+// three-step kernel is bound by its arithmetic (measured on one GPU with rho
+// every step, both kernels in mirror mode: L = 15 1.14 ms per step with three
+// steps per launch, 1.00 with two; L = 12 complex128 0.061 and 0.048).
+int fusion_width(int N, int L, int prec) {
+    const int from = prec == kPrecC64F64 ? 1 << 20 : 13;
     if (triple_ok(N, L) && L >= from) return 3;
     return fused_ok(N, L) ? 2 : 1;
 }
@@ -476,9 +475,9 @@ struct quapi_ctx {
     bool plan2_ready = false;     // fused-step factor tables computed
     bool plan3_ready = false;     // three-step factor tables computed
     int fuse = 1;                 // full-window steps per launch (fusion_width)
-    // Mirror mode of the three-step kernel: it reads and writes only the
+    // Mirror mode of the full-window kernels: they read and write only the
     // entries not above their mirror; half_cur says A[cur] holds only those.
-    bool mirror_ok = false;       // N = 4, three-step width available, rho0 exactly Hermitian
+    bool mirror_ok = false;       // M = 2, 3, 4, L >= 2, rho0 exactly Hermitian
     int mirror = 0;               // 0 off, 1 where it pays, 2 at every size (quapi_set_mirror)
     bool half_cur = false;
     int *blk3 = nullptr;          // high-digit values: n_canon3 below their mirror, then n_diag3 equal
@@ -1584,7 +1583,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
         }
         c->mirror = c->mirror_ok ? 1 : 0;
     }
-    c->fuse = c->n_H > 0 ? 1 : fusion_width(N, L, c->prec, c->mirror_ok);
+    c->fuse = c->n_H > 0 ? 1 : fusion_width(N, L, c->prec);
     c->pa_h = std::move(pa);
     c->ph_h = std::move(ph);
     c->pseg_h = std::move(pseg);
@@ -1716,7 +1715,7 @@ quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps) {
 quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
     if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
     const int N = ctx->N, L = ctx->L;
-    if (steps == 0) steps = ctx->n_H > 0 ? 1 : fusion_width(N, L, ctx->prec, ctx->mirror_ok);
+    if (steps == 0) steps = ctx->n_H > 0 ? 1 : fusion_width(N, L, ctx->prec);
     if (ctx->n_H > 0 && steps != 1)
         return fail(ctx, QUAPI_ERR_INVALID, "a driven context runs one step per launch");
     const bool ok = steps == 1 || (steps == 2 && fused_ok(N, L)) || (steps == 3 && triple_ok(N, L));

@@ -180,7 +180,7 @@ def _sampled_fused_check(w, dtype, tol, F=None):
     with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
         if F is None:
             F = ctx.fused_steps()
-            assert F == (3 if (dtype in ("c128", "c64") and L >= 13) or L >= 14 else 2), F
+            assert F == (3 if dtype in ("c128", "c64") and L >= 13 else 2), F
         else:
             ctx.set_fused_steps(F)
         mr = N ** (L - F)                   # items: digits of points n-L+F .. n-1
