@@ -183,6 +183,23 @@ quapi_status quapi_get_setup(const quapi_ctx *ctx, int what, double *out, size_t
  * INVALID when the range exceeds the tensor. */
 quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count, double *out);
 
+/* Resume from a checkpoint.  The state a context carries from one call to
+ * the next is its step count c and its tensor (the factor tables depend only
+ * on the parameters); quapi_step_count and quapi_read_tensor (first = 0,
+ * count = quapi_tensor_size) read it out.  quapi_restore puts such a state
+ * into a context created from the same parameters: step = c >= 0, tensor =
+ * N^min(c+1, L) complex values interleaved (re, im) in the layout of
+ * quapi_read_tensor, host memory, read only during the call (for complex64
+ * storage each value is rounded to complex64, so a state read from a
+ * complex64 context goes back unchanged).  The next quapi_propagate continues
+ * with step c+1 and gives the same results, bit for bit, as the context the
+ * state was read from would have given (the fused groups are fixed by the
+ * global step number).  The call waits for the context's queued work first.
+ * Errors: QUAPI_ERR_INVALID for NULL arguments, step < 0 or a count other
+ * than N^min(step+1, L); QUAPI_ERR_STATE while another call runs on the
+ * context; QUAPI_ERR_DEVICE when the copy fails. */
+quapi_status quapi_restore(quapi_ctx *ctx, int step, const double *tensor, size_t count);
+
 /* Number of entries in the current tensor (N^min(c+1, L)). */
 quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries);
 

@@ -1806,6 +1806,32 @@ quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count,
     return QUAPI_OK;
 }
 
+quapi_status quapi_restore(quapi_ctx *ctx, int step, const double *tensor, size_t count) {
+    if (!ctx || !tensor) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    quapi_ctx *c = ctx;
+    if (step < 0) return fail(c, QUAPI_ERR_INVALID, "step must be >= 0");
+    const size_t want = (size_t)ipow_ll(c->N, std::min(step + 1, c->L));
+    if (count != want)
+        return fail(c, QUAPI_ERR_INVALID, "count %zu is not N^min(step+1, L) = %zu", count, want);
+    BusyGuard g(c);
+    if (!g.ok) return fail(c, QUAPI_ERR_STATE, "context in use by another call");
+    if (quapi_status js = join_side(c); js != QUAPI_OK) return js;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // on the context's stream, so that its next kernels see the copy
+    std::vector<float> tmp;
+    if (c->prec == kPrecC128) {
+        HIP_TRY(c, hipMemcpyAsync(c->A[c->cur], tensor, count * 16, hipMemcpyHostToDevice, c->stream));
+    } else {
+        tmp.resize(2 * count);
+        for (size_t i = 0; i < 2 * count; ++i) tmp[i] = (float)tensor[i];
+        HIP_TRY(c, hipMemcpyAsync(c->A[c->cur], tmp.data(), count * 8, hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->step = step;
+    c->half_cur = false;
+    return QUAPI_OK;
+}
+
 quapi_status quapi_set_timing(quapi_ctx *ctx, int enable) {
     if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
     ctx->timing = enable != 0;

@@ -31,7 +31,7 @@ EXPORTED_SYMBOLS = (
     "quapi_footprint", "quapi_paper_pmc_bytes", "quapi_create", "quapi_propagate",
     "quapi_propagate_async", "quapi_step_count", "quapi_fused_steps", "quapi_set_fused_steps",
     "quapi_mirror", "quapi_set_mirror",
-    "quapi_get_setup", "quapi_read_tensor",
+    "quapi_get_setup", "quapi_read_tensor", "quapi_restore",
     "quapi_tensor_size", "quapi_set_timing", "quapi_get_timing", "quapi_destroy",
     "quapi_last_error",
 )
@@ -82,6 +82,7 @@ def load_library() -> ctypes.CDLL:
     lib.quapi_set_mirror.argtypes = [vp, ctypes.c_int]
     lib.quapi_get_setup.argtypes = [vp, ctypes.c_int, _DP, sz]
     lib.quapi_read_tensor.argtypes = [vp, sz, sz, _DP]
+    lib.quapi_restore.argtypes = [vp, ctypes.c_int, _DP, sz]
     lib.quapi_tensor_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.quapi_set_timing.argtypes = [vp, ctypes.c_int]
     lib.quapi_get_timing.argtypes = [vp, ctypes.POINTER(Timing)]
@@ -265,6 +266,16 @@ class Context:
         h = self._live()
         _check(lib().quapi_read_tensor(h, int(first), int(count), _ptr(out)), h)
         return out.view(np.complex128)[:count].copy()
+
+    def checkpoint(self) -> tuple:
+        """(step, tensor): the state quapi_restore takes back."""
+        return self.step_count(), self.read_tensor(0, self.tensor_size())
+
+    def restore(self, step: int, tensor) -> None:
+        t = np.ascontiguousarray(np.asarray(tensor, dtype=np.complex128).reshape(-1))
+        buf = t.view(np.float64)
+        h = self._live()
+        _check(lib().quapi_restore(h, int(step), _ptr(buf), t.size), h)
 
     def set_timing(self, enable: bool = True) -> None:
         _check(lib().quapi_set_timing(self._live(), int(bool(enable))))

@@ -3,6 +3,7 @@ every function include/quapi.h declares; the paper's primary memory cost
 column (Table 1) is reproduced; parameters are validated; the footprint
 follows the two-buffer layout; the memory cap yields NOMEM before any device
 call; create without a device fails cleanly."""
+import ctypes
 import os
 import re
 from pathlib import Path
@@ -148,3 +149,5 @@ def test_null_context_calls_are_invalid():
     lib = Q.lib()
     assert lib.quapi_destroy(None) == Q.ERR_INVALID
     assert b"NULL" in lib.quapi_last_error(None)
+    buf = (ctypes.c_double * 8)()
+    assert lib.quapi_restore(None, 0, buf, 4) == Q.ERR_INVALID
