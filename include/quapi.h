@@ -175,12 +175,14 @@ quapi_status quapi_step_count(const quapi_ctx *ctx, int *step);
 enum { QUAPI_SETUP_G = 0, QUAPI_SETUP_ETA = 1, QUAPI_SETUP_U = 2, QUAPI_SETUP_K = 3 };
 quapi_status quapi_get_setup(const quapi_ctx *ctx, int what, double *out, size_t out_len);
 
-/* Test hook: copy entries [first, first + count) of the current augmented
- * tensor to host as complex128.
+/* Copy entries [first, first + count) of the current augmented tensor to
+ * host as complex128 (a test hook; the whole tensor is the checkpoint that
+ * quapi_restore takes back).
  * Layout after global step c >= 1: the tensor holds path points
  * max(0, c-L+1) .. c, flat index sum_j o_{p0 + j} N^j (oldest point fastest),
  * N^min(c+1, L) entries (complex64 storage is widened to complex128).
- * INVALID when the range exceeds the tensor. */
+ * INVALID when the range exceeds the tensor; QUAPI_ERR_STATE while another
+ * call runs on the context. */
 quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count, double *out);
 
 /* Resume from a checkpoint.  The state a context carries from one call to

@@ -1794,6 +1794,8 @@ quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count,
         return fail(c, QUAPI_ERR_INVALID, "range [%zu, %zu) exceeds the tensor of %zu entries", first,
                     first + count, entries);
     if (!count) return QUAPI_OK;
+    BusyGuard g(c);                        // the completion pass changes the tensor
+    if (!g.ok) return fail(c, QUAPI_ERR_STATE, "context in use by another call");
     if (quapi_status fs = ensure_full(c); fs != QUAPI_OK) return fs;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->prec == kPrecC128) {
