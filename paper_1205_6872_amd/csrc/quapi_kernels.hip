@@ -865,12 +865,17 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
     const int part = MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
     const int i0 = (MODE == 2 ? part * a.q_span : 0) + wave;
     const int i1 = MODE == 3 ? (1 << (2 * dm)) : MODE == 2 ? min(Q, (part + 1) * a.q_span) : Q;
-    for (int it = i0; it < i1; it += kBlock / 64) {
+    // the item of sweep index it: its index m, its mirror, and whether it runs
+    auto item = [&](int it, long long &m, long long &mb) {
         const int qm = MODE == 3 ? diagonal_digits16(it, dm) : it;
-        const long long m = m0 + 16LL * qm + j;
-        const long long mb = MODE == 0 ? m : mirror16(m);
-        const bool run = MODE == 0 || MODE == 1 || (MODE == 2 ? m < mb : j % 5 == 0);
-        T xw[8];
+        m = m0 + 16LL * qm + j;
+        mb = MODE == 0 ? m : mirror16(m);
+        return MODE == 0 || MODE == 1 || (MODE == 2 ? m < mb : j % 5 == 0);
+    };
+    // a lane's 8 input words of the item of sweep index it
+    auto load = [&](int it, T *xw) {
+        long long m, mb;
+        const bool run = item(it, m, mb);
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             if (MODE == 3) {
@@ -884,6 +889,18 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
                 xw[s] = (MODE != 2 || run) ? (T)ain[32 * m + 8 * g + s] : T(0);
             }
         }
+    };
+    // the next item's inputs are loaded before this item's products, so
+    // that their latency overlaps the MFMAs
+    T xw[8];
+    if (i0 < i1) load(i0, xw);
+    for (int it = i0; it < i1; it += kBlock / 64) {
+        const bool more = it + kBlock / 64 < i1;
+        T xn[8];
+        if (more) load(it + kBlock / 64, xn);
+        const int qm = MODE == 3 ? diagonal_digits16(it, dm) : it;
+        long long m, mb;
+        const bool run = item(it, m, mb);
         V4 d[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) d[b] = V4{0, 0, 0, 0};
@@ -911,6 +928,10 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
                 acc[q].x += v.x;
                 acc[q].y += v.y;
             }
+        }
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) xw[s] = xn[s];
         }
     }
     if (RHO) {
