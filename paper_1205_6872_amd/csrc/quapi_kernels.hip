@@ -772,7 +772,7 @@ __device__ __forceinline__ int diagonal_digits16(int x, int nd) {
     return out;
 }
 struct Step16Lds {
-    unsigned tq, tqf, red, total;
+    unsigned tq, tqf, red, afr, total;
 };
 __host__ __device__ inline Step16Lds step16_lds_layout(int csize, bool rho, int Q) {
     Step16Lds l;
@@ -780,6 +780,7 @@ __host__ __device__ inline Step16Lds step16_lds_layout(int csize, bool rho, int 
     l.tq = lds_take(off, 16 * Q * csize);
     l.tqf = lds_take(off, rho ? 16 * Q * csize : 0);
     l.red = lds_take(off, rho ? (kBlock / 64) * 16 * 16 : 0);
+    l.afr = lds_take(off, rho ? 4 * 8 * 64 * (csize / 2) : 0);     // A fragments [4][8][lane]
     l.total = off;
     return l;
 }
@@ -801,7 +802,7 @@ template <> struct Mfma16<double> {
 };
 
 template <typename S, typename T, bool RHO, int MODE>
-__global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
+__global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfma_kernel(const StepArgs a) {
     constexpr int N = 16, NB = RHO ? 4 : 2;
     using C = typename Cx<T>::type;
     using CS = typename Cx<S>::type;
@@ -812,6 +813,7 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
     C *s_tq = (C *)(smem + lay.tq);                      // [N][Q] mid x high products
     C *s_tqf = (C *)(smem + lay.tqf);
     double2 *s_red = (double2 *)(smem + lay.red);        // [waves][N]
+    T *s_afr = (T *)(smem + lay.afr);
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int j = lane & 15, g = lane >> 4;
     const long long blk = MODE == 0   ? (long long)blockIdx.x
@@ -823,8 +825,10 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
         s_tq[idx] = from_d2<C>(cmul(a.t_hi[(size_t)o * a.grid + blk], a.t_mid[idx]));
         if (RHO) s_tqf[idx] = from_d2<C>(cmul(a.t_hif[(size_t)o * a.grid + blk], a.t_midf[idx]));
     }
-    // A fragments: row 16b + j, word 8g + s
-    T afr[NB][8];
+    // A fragments: row 16b + j, word 8g + s; those of the final-point table
+    // (blocks 2, 3) in LDS, read per use, to keep the registers of the rho
+    // form down
+    T afr[RHO ? 1 : 2][8];
     {
         const C *bc = (const C *)a.bank_c;
 #pragma unroll
@@ -839,7 +843,9 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
                 const int w = 8 * g + s, i = w / 2, im_word = w & 1;
                 const C c = bc[(size_t)tb * (N * N) + o * N + i];
                 // Re z = cr xr - ci xi ; Im z = ci xr + cr xi
-                afr[b][s] = im_row ? (im_word ? c.x : c.y) : (im_word ? -c.y : c.x);
+                const T v = im_row ? (im_word ? c.x : c.y) : (im_word ? -c.y : c.x);
+                if (!RHO) afr[b][s] = v;
+                else if (wave == 0) s_afr[(b * 8 + s) * 64 + lane] = v;
             }
         }
     }
@@ -904,10 +910,12 @@ __global__ void __launch_bounds__(kBlock) step16_mfma_kernel(const StepArgs a) {
         V4 d[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) d[b] = V4{0, 0, 0, 0};
+        if (RHO) asm volatile("" ::: "memory");   // the LDS fragments are read here, per item group
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) d[b] = Mfma16<T>::run(afr[b][s], xw[s], d[b]);
+            for (int b = 0; b < NB; ++b)
+                d[b] = Mfma16<T>::run(RHO ? s_afr[(b * 8 + s) * 64 + lane] : afr[b][s], xw[s], d[b]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
