@@ -627,6 +627,38 @@ __global__ void __launch_bounds__(kBlock) rho_slice_kernel(const double2 *__rest
     const int t = threadIdx.x;
     const int b = blockIdx.x;
     const long long r0 = (long long)rows * b / kSlices, r1 = (long long)rows * (b + 1) / kSlices;
+    if constexpr (N >= 9) {
+        // one point o per thread and kBlock / N row lanes: a row's N values
+        // are read by N neighbouring threads, and each thread keeps one pair
+        // of compensated sums; the lanes of a point are then combined in
+        // lane order by one thread
+        constexpr int RL = kBlock / N;
+        __shared__ double s_p[4][kBlock];
+        const int o = t % N, lane_r = t / N;
+        double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+        if (lane_r < RL) {
+            for (long long r = r0 + lane_r; r < r1; r += RL) {
+                const double2 v = partials[(size_t)r * N + o];
+                neumaier(sr, cr, v.x);
+                neumaier(si, ci, v.y);
+            }
+        }
+        s_p[0][t] = sr;
+        s_p[1][t] = cr;
+        s_p[2][t] = si;
+        s_p[3][t] = ci;
+        __syncthreads();
+        if (t < N) {
+            for (int k = 1; k < RL; ++k) {
+                const int u = k * N + t;
+                two_sum_combine(sr, cr, s_p[0][u], s_p[1][u]);
+                two_sum_combine(si, ci, s_p[2][u], s_p[3][u]);
+            }
+            pairs[((size_t)b * N + t) * 2] = make_double2(sr, si);
+            pairs[((size_t)b * N + t) * 2 + 1] = make_double2(cr, ci);
+        }
+        return;
+    }
     constexpr int U = N >= 16 ? 1 : 16 / N;   // rows in flight per thread
     double sr[N], cr[N], si[N], ci[N];
 #pragma unroll
