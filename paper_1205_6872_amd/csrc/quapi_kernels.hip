@@ -765,7 +765,8 @@ __global__ void __launch_bounds__(kBlock) plan_tables_kernel(const PlanArgs a) {
 // tables), K = 32 (the item's 32 real words in memory order) and one column per
 // item.  A wave runs it on 16 items at a time with 16x16x4 MFMAs (FP32 for the
 // complex64 tier, FP64 otherwise): the coefficients are per-lane A fragments
-// kept in registers for the whole block, the inputs are B fragments loaded
+// kept in registers for the whole block (in LDS, read per item group, in the
+// rho form, which has twice as many), the inputs are B fragments loaded
 // straight from HBM, and each lane's accumulators hold 4 outputs of one item.
 //
 // MFMA 16x16x4 lane layout (wave64): A[i][k] in lane i + 16k, B[k][j] in lane
