@@ -306,7 +306,7 @@ def mirror9_array(x):
     return out
 
 
-@pytest.mark.parametrize("L,seed,n", [(2, 1, 20), (3, 2, 20), (4, 3, 16), (6, 4, 12), (8, 5, 8)])
+@pytest.mark.parametrize("L,seed,n", [(2, 1, 20), (3, 2, 20), (4, 3, 16), (6, 4, 12), (7, 6, 10), (8, 5, 8)])
 def test_m3_mirror_mode_against_oracle_and_full_mode(L, seed, n):
     w = case_m3(L, seed)
     print(f"M=3 L={L} seed={seed} steps={n}", flush=True)
