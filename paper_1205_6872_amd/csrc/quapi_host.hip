@@ -70,10 +70,13 @@ DigitSplit split_digits(int N, int n_digits) {
     s.d_mid = std::min(d_mid_target, avail);
     // keep at least ~1024 blocks in flight when the tensor allows it
     while (s.d_mid > 0 && ipow_ll(N, avail - s.d_mid) < 1024) --s.d_mid;
-    // N = 9 with one sweep row leaves 81 of a block's threads with an item:
-    // one middle digit (nine rows over three thread columns) pays from 512
-    // blocks (M = 3, L = 7, rho every step: 0.081 -> 0.062 ms per step)
+    // One sweep row leaves threads without an item: at N = 9 all but 81 of
+    // a block's 256, at N = 16 (MFMA, a row per wave) three of its four
+    // waves.  One middle digit pays from 512 blocks at N = 9 (M = 3, L = 7,
+    // rho every step: 0.081 -> 0.062 ms per step) and from 256 at N = 16
+    // (M = 4, L = 5: 0.034 -> 0.021 ms).
     if (N == 9 && s.d_mid == 0 && avail >= 1 && ipow_ll(N, avail - 1) >= 512) s.d_mid = 1;
+    if (N == 16 && s.d_mid == 0 && avail >= 1 && ipow_ll(N, avail - 1) >= 256) s.d_mid = 1;
     s.R = (int)ipow_ll(N, s.d_lo);
     s.Q = (int)ipow_ll(N, s.d_mid);
     s.grid = (int)ipow_ll(N, avail - s.d_mid);
