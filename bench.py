@@ -1,9 +1,9 @@
 """Benchmark of the QUAPI tensor-propagator step on one MI355X.
 
 Workload: spin-boson, M = 2 (N = 4), L = Delta k_max = 15 (4^15 = 1.07e9
-tensor entries), xi = 0.5, omega_c = 10, kT = 0.05, dt = 0.1, 1000 steps by
-default, rho(t_n) extracted at every step ('allPoints').  Inputs are
-synthetic (seeded parameters, no dataset).
+tensor entries), xi = 0.5, omega_c = 10, kT = 0.05, dt = 0.1, 1000 steps,
+rho(t_n) extracted at every step ('allPoints').  Inputs are synthetic
+(seeded parameters, no dataset).
 
 A timed "step" is one full-window propagation step.  For M = 2 the library
 fuses consecutive steps into one kernel launch (at L = 15 three with
@@ -11,45 +11,46 @@ complex128 and complex64, two with complex64 storage and FP64 arithmetic):
 it reads the tensor once, keeps the intermediate tensors in registers,
 writes the tensor of the group's last step once, and produces per-block
 partial sums of rho at every step of the group in the same pass; a small
-finalize kernel on a side stream sums them.  So one launch moves
-2 * N^L * sizeof(complex) bytes and covers two or three steps; in mirror
-mode (on by default: rho0 is Hermitian) it reads and writes only the
-(N^L + M^L) / 2 entries not above their mirror, the rest being their
-conjugates.  The growth steps (n < L) and the device setup run first and
-are reported separately.  Three precisions run on the same workload:
-complex128 (the reported `value`), the complex64 tier with FP32 arithmetic
+finalize kernel on a side stream sums them.  In mirror mode (on by default:
+rho0 is Hermitian) a launch reads and writes only the (N^L + M^L) / 2
+entries not above their mirror, the rest being their conjugates.  The
+groups are fixed by the global step number, so the warm-up is lengthened
+until the timed call starts on a group boundary (`warmup_steps_run`); a
+timed call of K steps then runs K // F whole groups and its last K % F steps
+as one shorter launch or singly (`roofline.other_launches`).  The growth
+steps (n < L) and the device setup run first and are reported separately;
+after the timed call every tier runs on, untimed, to step 1000, so the
+complex64 tiers are compared with complex128 (max|drho| and trace drift)
+over the whole workload whatever K is.  Three precisions run: complex128
+(the reported `value`), the complex64 tier with FP32 arithmetic
 (`fp32_tier`), and complex64 storage with FP64 arithmetic
-(`c64_storage_f64_math`), each complex64 run with max|drho| and trace drift
-against complex128.  `copy_ceiling` is a plain device copy (torch copy_ of
-16 GiB) timed on the same GPU, for reference.
+(`c64_storage_f64_math`).
 
-`serving` replays the seeded Poisson trace of mixed requests (M in {2,3,4},
-L up to N^L <= 2^28, 50-1000 steps, complex64/complex128, 20 requests/s) in
-real time through the continuous-batching server and reports p50/p99
-latency (arrival -> rho on the host) and aggregate Gelem/s.  By default it
-serves the first 64 requests of the 512-request trace (about 3 s of
-arrivals) so the run stays within minutes; --serve-requests 512 serves all.
+Metric: Gelem/s = N^L * K / seconds / 1e9 over the K timed steps, with the
+tensor resident in HBM.  `roofline` prices the dominant launch (the F-step
+launch, its mirror-mode group of three kernels counted as one launch)
+against the HBM peak of 8 TB/s: `achieved` = the bytes the launch must
+move ((N^L + M^L) * sizeof(complex) in mirror mode, 2 * N^L * sizeof
+otherwise) / its mean duration from HIP events on the library's stream;
+`step_equivalent_gbs` = F * 2 * N^L * sizeof(complex) (the bytes of F
+unfused full-tensor steps) / the same duration.  `traffic` is the HBM bytes
+per launch from rocprofv3 counters (profiles/), null when the kernel's
+sources changed since they were taken.  `copy_ceiling` is the attainable
+read+write rate: the library's chunked copy kernel swept over chunk sizes,
+with torch copy_ beside it.  `cpu_baseline` times the oracle (plain C,
+OpenMP, all host threads it is given) on 10 full-window steps of the same
+workload.
 
-Metric: Gelem/s = N^L * steps / seconds / 1e9, with the tensor resident in
-HBM.  `roofline` prices the step kernel against the HBM peak: algorithmic
-bytes per launch = 2 * N^L * sizeof(complex) (one read, one write of the
-tensor; (N^L + M^L) * sizeof(complex) in mirror mode), divided by the kernel's average duration per launch from HIP events
-on the library's stream (`steps_per_launch` says how many steps a launch covers).
-`step_equivalent_gbs` divides the same bytes by the measured time per step:
-the rate an unfused step would need to match it.
-`cpu_baseline` times the oracle (plain C, OpenMP) on a bounded sample of the
-same workload on the host.
-
-`paper_table1` re-runs the paper's Table 1 experiment (its Sec. III model system
-with the tabulated super-Ohmic J, memory length dk = 2..15, 989 main-phase
-steps, rho at every point) and reports the main-phase wall time per dk.
-`serving` / `serving_fifo` serve the first requests of the seeded trace with
-shortest-work-first and arrival-order admission.
-`pulse_sweep` serves the paper's use case of many runs that differ only in
-the pulse area: its Sec. III quantum dot driven by a Gaussian pulse (a
-Hamiltonian per time interval, so each request recomputes its propagator
-tables every step), 32 areas from 0 to 4 pi, rho at the last step only, and
-reports the makespan, latency and the final excited-state population per area.
+`serving` replays the seeded 512-request Poisson trace of mixed requests
+(M in {2,3,4}, N^L <= 2^28, 50-1000 steps, complex64/complex128, 20
+requests/s) in real time through the continuous-batching server and reports
+p50/p99 latency (arrival -> rho on the host) and aggregate Gelem/s, with
+shortest-work-first (`serving`) and arrival-order (`serving_fifo`)
+admission.  `paper_table1` re-runs the paper's Table 1 experiment (its
+Sec. III model system with the tabulated super-Ohmic J, dk = 2..15, 989
+main-phase steps, rho at every point).  `pulse_sweep` serves the paper's use
+case of many runs that differ only in the pulse area (Sec. III quantum dot
+driven by a Gaussian pulse, 32 areas from 0 to 4 pi, rho at the last step).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tiers c128,c64,c64f64]
                        [--serve-requests R] [--no-table1] [--no-pulse-sweep]
@@ -74,7 +75,20 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_tier(w, dtype: str, warmup: int, steps: int):
+def aligned_warmup(warmup: int, F: int) -> int:
+    """Warm-up steps actually run: at least `warmup` and at least one, and such
+    that the timed call starts on a fused-group boundary.  After the growth
+    call (steps 1 .. L-1) and W warm-up steps the timed call starts at step
+    L + W; groups start at n = L+1, L+1+F, ..., so (W - 1) % F == 0."""
+    w = max(1, warmup)
+    while (w - 1) % F:
+        w += 1
+    return w
+
+
+def run_tier(w, dtype: str, warmup: int, steps, total_steps: int):
+    """Growth, aligned warm-up, K timed steps, then (untimed) the rest of the
+    run up to total_steps so that every tier's rho is compared over it."""
     import numpy as np
     import torch
     from paper_1205_6872_amd import quapi as Q
@@ -86,9 +100,13 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
     ctx = Q.create_in_torch(p, stream=stream)
     setup_wall = time.perf_counter() - t0
     try:
+        F = ctx.fused_steps()
+        w_run = aligned_warmup(warmup, F)
+        if steps is None:
+            steps = total_steps - (L - 1) - w_run
         ctx.set_timing(True)
         rho_grow = ctx.propagate(L - 1)                   # growth steps 1 .. L-1
-        rho_warm = ctx.propagate(warmup)                  # first full-window steps
+        rho_warm = ctx.propagate(w_run)                   # first full-window steps
         tm = ctx.get_timing()
         grow_ms = tm["grow_ms"]
         torch.cuda.synchronize()
@@ -97,9 +115,11 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         tm = ctx.get_timing()
+        ctx.set_timing(False)
+        rest = total_steps - ctx.step_count()
+        rho_rest = ctx.propagate(rest) if rest > 0 else np.zeros((0, w.M, w.M), complex)
         # the fused kernels' mirror mode: the three-step kernel always, the
         # two-step kernel above 2^22 entries (or at every size in mode 2)
-        F = ctx.fused_steps()
         mirror = bool(ctx.mirror()) and (F == 3 or (F == 2 and (ctx.mirror() == 2 or N ** L > 2 ** 22)))
     finally:
         ctx.destroy()
@@ -107,31 +127,56 @@ def run_tier(w, dtype: str, warmup: int, steps: int):
         torch.cuda.empty_cache()
     entries = N ** L
     csize = 16 if dtype == "c128" else 8   # bytes per stored entry
-    # every entry read once and written once; in mirror mode only the entries
-    # not above their mirror, (N^L + M^L) / 2 of them
+    # the bytes the dominant launch must move: every entry read once and
+    # written once; in mirror mode only the entries not above their mirror,
+    # (N^L + M^L) / 2 of them
     bytes_per_launch = (entries + w.M ** L) * csize if mirror else 2 * entries * csize
-    launches = max(tm["step_launches"], 1)
-    kernel_ms = tm["step_ms"] / launches                  # per full-window launch
-    steps_per_launch = tm["step_steps"] / launches        # 2 when two steps are fused
+    # launches of the dominant width (F steps each), timed apart from the
+    # single or two-step launches at the ends of the call
+    launches = max(int(tm["width_launches"][F]), 1)
+    kernel_ms = tm["width_ms"][F] / launches
+    other = {str(k): {"launches": int(tm["width_launches"][k]),
+                      "ms_per_launch": round(tm["width_ms"][k] / tm["width_launches"][k], 4)}
+             for k in (1, 2, 3) if k != F and tm["width_launches"][k] > 0}
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
-    rho = np.concatenate([rho_grow, rho_warm, rho_main])
+    rho = np.concatenate([rho_grow, rho_warm, rho_main, rho_rest])
     return dict(
-        dtype=dtype, elapsed_s=elapsed, steps=steps, ms_per_step=elapsed * 1e3 / steps,
-        gelem_s=entries * steps / elapsed / 1e9, kernel_ms=kernel_ms, kernel_launches=tm["step_launches"],
-        steps_per_launch=steps_per_launch,
+        dtype=dtype, elapsed_s=elapsed, steps=steps, warmup_run=w_run, ms_per_step=elapsed * 1e3 / steps,
+        gelem_s=entries * steps / elapsed / 1e9, kernel_ms=kernel_ms, kernel_launches=launches, F=F,
+        other_launches=other,
         finalize_ms=tm["finalize_ms"] / max(tm["finalize_launches"], 1), setup_ms=tm["setup_ms"],
         setup_wall_ms=setup_wall * 1e3, grow_ms=grow_ms, bytes_per_launch=bytes_per_launch,
         achieved_gbs=achieved, rho=rho, mirror=mirror, step_bytes=2 * entries * csize)
 
 
-def kernel_name(tier: str, steps_per_launch: float, mirror: bool = False) -> str:
+def kernel_name(tier: str, F: int, mirror: bool = False) -> str:
     st = {"c128": "double, double", "c64": "float, float", "c64f64": "float, double"}[tier]
-    half = ", the entries not above their mirror only" if mirror else ""
-    if steps_per_launch > 2.5:
+    half = ", the entries not above their mirror only (modes 1 + 2 + 3)" if mirror else ""
+    if F == 3:
         return f"step3_kernel<{st}, rho{', mirror' if mirror else ''}> (three steps fused per launch{half})"
-    if steps_per_launch > 1.5:
+    if F == 2:
         return f"step2_kernel<{st}, rho{', mirror' if mirror else ''}> (two steps fused per launch{half})"
     return f"step_kernel<4, {st}, rho, full-window>"
+
+
+def roofline(r, traffic):
+    """Roofline of the dominant launch: `achieved` on the bytes the launch must
+    move (its kept half in mirror mode), and the step-equivalent rate: the
+    per-step bytes of the unfused step (2 N^L sizeof) times the F steps the
+    launch covers, over the same launch time."""
+    step_eq = r["F"] * r["step_bytes"] / (r["kernel_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kernel_name(r["dtype"], r["F"], r["mirror"]),
+            "kernel_ms": round(r["kernel_ms"], 4), "kernel_launches": r["kernel_launches"],
+            "bytes_per_launch": r["bytes_per_launch"], "steps_per_launch": r["F"],
+            "frac_definition": ("bytes the launch must move (its kept half read once and written once in "
+                                "mirror mode, else the whole tensor) / launch time / 8 TB/s"),
+            "step_equivalent_gbs": round(step_eq, 1),
+            "step_equivalent_frac": round(step_eq / HBM_PEAK_GBS, 4),
+            "step_equivalent_definition": ("F steps x 2 N^L sizeof(complex) (one read and one write of "
+                                           "the whole tensor per unfused step) / launch time / 8 TB/s"),
+            "other_launches": r["other_launches"]}
 
 
 # The dominant kernel of each tier at M = 2, L = 15 and the sources it is built from.
@@ -169,23 +214,43 @@ def measured_traffic(tier: str):
 
 
 def copy_ceiling(nbytes: int = 2 ** 34):
-    """Plain device read+write copy (torch copy_), GB/s counting read + write."""
+    """Attainable HBM read+write rate on this GPU: the library's chunked copy
+    kernel (quapi_copy_bandwidth) over a few chunk sizes, loads plain and
+    nontemporal, and torch copy_ for reference; GB/s counting read + write."""
     import torch
+    from paper_1205_6872_amd import quapi as Q
     a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / 5
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    rows = []
+    for chunk_kb in (64, 256, 1024, 4096):
+        for nt in (False, True):
+            ms = timed(lambda: Q.copy_bandwidth(a.data_ptr(), b.data_ptr(), nbytes, chunk_kb * 1024, nt,
+                                                stream.cuda_stream))
+            rows.append({"kernel": f"quapi_copy_bandwidth chunk {chunk_kb} KB{', nontemporal loads' if nt else ''}",
+                         "kernel_ms": round(ms, 4), "achieved": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)})
+    assert torch.equal(a[:: 1 << 20], b[:: 1 << 20])
+    ms = timed(lambda: b.copy_(a))
+    torch_row = {"kernel": "torch copy_", "kernel_ms": round(ms, 4),
+                 "achieved": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
     del a, b
     torch.cuda.empty_cache()
-    return {"achieved": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "unit": "GB/s", "bytes": 2 * nbytes,
-            "kernel_ms": round(ms, 4), "kernel": "torch copy_ of 16 GiB float64"}
+    best = max(rows, key=lambda r: r["achieved"])
+    return {"achieved": best["achieved"], "unit": "GB/s", "bytes": 2 * nbytes, "kernel_ms": best["kernel_ms"],
+            "kernel": best["kernel"], "torch_copy": torch_row, "sweep": rows,
+            "note": "16 GiB copied; bytes counted as one read plus one write"}
 
 
 def serve_trace(n_requests: int, policy: str = "sjf", chunk_ms=8.0, chunk_steps: int = 32):
@@ -228,7 +293,19 @@ def pulse_sweep(n: int = 32, L: int = 11, n_steps: int = 200, dtype: str = "c128
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
 
 
-def cpu_baseline(w, n_main: int = 2):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, n_main: int = 10):
     """Oracle on the host: growth to L, then n_main full-window steps (timed)."""
     import numpy as np
     from oracle.run import oracle_run
@@ -242,7 +319,7 @@ def cpu_baseline(w, n_main: int = 2):
                 sample=(f"{w.name} complex128: growth steps 1..{w.L - 1} then {n_main} full-window "
                         f"steps; value over the full-window steps ({total:.1f} s), "
                         f"growth {float(np.sum(secs[:w.L - 1])):.1f} s untimed"),
-                seconds=total)
+                seconds=total, cpu_model=cpu_model(), nproc=os.cpu_count())
 
 
 def main() -> int:
@@ -252,7 +329,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tiers", default="c128,c64,c64f64")
     ap.add_argument("--no-copy-ceiling", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=64, help="0 skips the serving run")
+    ap.add_argument("--serve-requests", type=int, default=512, help="0 skips the serving run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-table1", action="store_true", help="skip the paper's Table 1 sweep")
     ap.add_argument("--no-pulse-sweep", action="store_true", help="skip the pulse-area sweep")
@@ -271,24 +348,25 @@ def main() -> int:
         return 2
     torch.cuda.set_device(0)
     w = W.spin_boson_l15("c128")
-    steps = args.steps if args.steps is not None else w.n_steps - (w.L - 1) - args.warmup
+    total = w.n_steps                      # every tier runs the whole 1000-step workload
     tiers = [t for t in args.tiers.split(",") if t]
     res = {}
     for t in tiers:
-        log(f"bench: tier {t}: {w.name} N^L={w.N ** w.L}, warmup {args.warmup}, timed {steps} steps")
-        res[t] = run_tier(w, t, args.warmup, steps)
+        log(f"bench: tier {t}: {w.name} N^L={w.N ** w.L}, warmup {args.warmup}, "
+            f"timed {args.steps if args.steps is not None else 'the rest of the'} steps")
+        res[t] = run_tier(w, t, args.warmup, args.steps, total)
         r = res[t]
-        log(f"bench: tier {t}: {r['ms_per_step']:.3f} ms/step, {r['gelem_s']:.1f} Gelem/s, kernel "
-            f"{r['kernel_ms']:.3f} ms = {r['achieved_gbs']:.0f} GB/s")
+        log(f"bench: tier {t}: {r['ms_per_step']:.3f} ms/step, {r['gelem_s']:.1f} Gelem/s, "
+            f"{r['F']}-step launch {r['kernel_ms']:.3f} ms = {r['achieved_gbs']:.0f} GB/s "
+            f"(warm-up {r['warmup_run']}, other launches {r['other_launches']})")
     main_t = "c128" if "c128" in res else tiers[0]
     r = res[main_t]
-    traffic = measured_traffic(main_t)
     out = {
         "metric": "QUAPI step Gelem/s + HBM GB/s (FP64 vs FP32) at M=2 dk=15",
         "value": round(r["gelem_s"], 3),
         "unit": "Gelem/s",
         "n_gpus": 1,
-        "steps": steps,
+        "steps": r["steps"],
         "warmup": args.warmup,
         "ms_per_step": round(r["ms_per_step"], 4),
         "higher_is_better": True,
@@ -297,15 +375,11 @@ def main() -> int:
         "dtype": "f64" if main_t == "c128" else "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "M": w.M, "L": w.L, "entries": w.N ** w.L,
-                   "tensor": main_t, "rho_every_step": True, "total_steps": w.L - 1 + args.warmup + steps,
-                   "xi": w.xi, "omega_c": w.omega_c, "kT": w.kT, "dt": w.dt},
-        "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": kernel_name(main_t, r["steps_per_launch"], r["mirror"]),
-                     "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_launch": r["bytes_per_launch"],
-                     "steps_per_launch": round(r["steps_per_launch"], 3),
-                     # bytes a single full-tensor step reads and writes, per measured step time
-                     "step_equivalent_gbs": round(r["step_bytes"] / (r["ms_per_step"] * 1e-3) / 1e9, 1)},
+                   "tensor": main_t, "rho_every_step": True,
+                   "warmup_steps_run": r["warmup_run"],
+                   "timed_steps": [w.L + r["warmup_run"], w.L - 1 + r["warmup_run"] + r["steps"]],
+                   "total_steps": total, "xi": w.xi, "omega_c": w.omega_c, "kT": w.kT, "dt": w.dt},
+        "roofline": roofline(r, measured_traffic(main_t)),
         "setup_ms": round(r["setup_ms"], 3),
         "growth_ms": round(r["grow_ms"], 3),
         "finalize_ms": round(r["finalize_ms"], 4),
@@ -319,14 +393,9 @@ def main() -> int:
         out[key] = {
             "dtype": "f32" if t == "c64" else "f64", "storage": "complex64",
             "value": round(a["gelem_s"], 3), "unit": "Gelem/s", "ms_per_step": round(a["ms_per_step"], 4),
-            "roofline": {"bound": "hbm", "achieved": round(a["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(a["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic(t),
-                         "kernel": kernel_name(t, a["steps_per_launch"], a["mirror"]),
-                         "kernel_ms": round(a["kernel_ms"], 4), "bytes_per_launch": a["bytes_per_launch"],
-                         "steps_per_launch": round(a["steps_per_launch"], 3),
-                         "step_equivalent_gbs": round(a["step_bytes"] / (a["ms_per_step"] * 1e-3) / 1e9, 1)},
+            "roofline": roofline(a, measured_traffic(t)),
             "max_abs_drho_vs_f64": d, "trace_drift_vs_f64": drift, "steps_compared": len(a["rho"]),
+            "targets": {"max_abs_drho": 1e-5, "trace_drift": 1e-6},
         }
     if not args.no_copy_ceiling:
         out["copy_ceiling"] = copy_ceiling()
@@ -343,7 +412,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("bench: cpu_baseline (oracle on the host)")
         cb = cpu_baseline(w.with_(dtype="c128"))
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "cpu_model",
+                                                  "nproc")}
         out["cpu_baseline"]["value"] = round(cb["value"], 5)
     print(json.dumps(out), flush=True)
     return 0

@@ -150,7 +150,8 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
  * of F = quapi_fused_steps() steps fixed by the global step number:
  * (L+1 .. L+F), (L+F+1 .. L+2F), ...  A sequence of calls gives bit-identical
  * results to one call when every call ends at step c <= L or with c - L a
- * multiple of F (otherwise the steps of a split group run one by one and
+ * multiple of F (otherwise the steps of a split group run one by one, or as
+ * one two-step launch when a call ends two steps into a three-step group, and
  * round differently, within 1e-15).  F is chosen as quapi_set_fused_steps
  * describes. */
 quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
@@ -252,6 +253,11 @@ typedef struct {
     long long grow_launches;
     double finalize_ms;       /* summed duration of the kernels that sum rho over blocks */
     long long finalize_launches;
+    /* step_ms / step_launches split by the full-window steps a launch covers:
+     * index 1 single steps, 2 two-step launches, 3 three-step launches (index
+     * 0 unused).  A launch in mirror mode counts its group of three kernels. */
+    double width_ms[4];
+    long long width_launches[4];
 } quapi_timing;
 
 /* enable != 0 records an event pair around every propagation kernel launch. */
@@ -259,6 +265,18 @@ quapi_status quapi_set_timing(quapi_ctx *ctx, int enable);
 /* Waits for the stream, returns the accumulated timings, and resets them
  * (setup_ms is kept). */
 quapi_status quapi_get_timing(quapi_ctx *ctx, quapi_timing *out);
+
+/* Measurement aid, not part of the method: enqueue one device copy of
+ * `bytes` from src to dst (both device memory, 16-byte aligned, bytes a
+ * multiple of 16) on hip_stream (NULL: the null stream).  Each block of 512
+ * threads copies one contiguous chunk of chunk_bytes (a multiple of 16,
+ * >= 8192) with 16-byte accesses; nontemporal != 0 marks the loads
+ * nontemporal.  Timing it with events on the stream gives the attainable
+ * HBM read+write rate that the step kernels are compared with.  Returns
+ * QUAPI_ERR_INVALID for bad arguments, QUAPI_ERR_DEVICE when the launch
+ * fails; the call does not wait for the copy. */
+quapi_status quapi_copy_bandwidth(const void *src, void *dst, size_t bytes, size_t chunk_bytes,
+                                  int nontemporal, void *hip_stream);
 
 /* Release the context and everything it allocated (not a caller workspace). */
 quapi_status quapi_destroy(quapi_ctx *ctx);

@@ -1,19 +1,26 @@
-"""Build the HIP library libquapi.so for gfx950 (in-tree, with hipcc)."""
+"""Build the HIP library libquapi.so for gfx950 (in-tree, with hipcc).
+
+Each source is compiled to an object in parallel (every kernel is launched
+from its own translation unit), then the objects are linked into the shared
+library."""
 from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB_DIR = PKG / "_lib"
+OBJ_DIR = LIB_DIR / "obj"
 LIB = LIB_DIR / "libquapi.so"
-SOURCES = [CSRC / "quapi_kernels.hip", CSRC / "quapi_step2.hip", CSRC / "quapi_step3.hip", CSRC / "quapi_host.hip"]
+SOURCES = [CSRC / "quapi_kernels.hip", CSRC / "quapi_step2.hip", CSRC / "quapi_step3.hip",
+           CSRC / "quapi_host.hip", CSRC / "quapi_copy.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off (plain scalar/float2 code only)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
@@ -26,11 +33,24 @@ def hipcc() -> str:
     return str(cand) if cand.exists() else "hipcc"
 
 
-def build_library(verbose: bool = False) -> Path:
-    LIB_DIR.mkdir(exist_ok=True)
+def _compile(src: Path, verbose: bool) -> Path:
+    obj = OBJ_DIR / (src.stem + ".o")
+    tmp = obj.with_suffix(".o.tmp")
+    cmd = [hipcc(), *HIPCC_FLAGS, f"-I{ROOT / 'include'}", f"-I{CSRC}", "-c", "-o", str(tmp), str(src)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, obj)
+    return obj
+
+
+def build_library(verbose: bool = False, jobs: int = 0) -> Path:
+    OBJ_DIR.mkdir(parents=True, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB.with_suffix(".so.tmp")
-    cmd = [hipcc(), *HIPCC_FLAGS, f"-I{ROOT / 'include'}", f"-I{CSRC}", "-o", str(tmp),
-           *[str(s) for s in SOURCES]]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", str(tmp), *[str(o) for o in objs]]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -510,6 +510,8 @@ struct quapi_ctx {
     double acc_ms[3] = {0, 0, 0};
     long long acc_n[3] = {0, 0, 0};
     long long acc_steps = 0;      // full-window steps covered by timed step launches
+    double acc_width_ms[4] = {0, 0, 0, 0};      // full-window launches by the steps they cover
+    long long acc_width_n[4] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -1251,7 +1253,8 @@ quapi_status check_selection(quapi_ctx *c, int n_steps, const int *sel, int n_se
 // launch each; later full-window steps run in fused groups of F = c->fuse
 // steps when N = 4 (one pass per group, groups fixed by the global step
 // number), else singly; small tensors replay captured graphs.  A call that
-// ends inside a group runs that group's steps singly.  In mirror mode the
+// ends inside a group runs that group's steps singly, or, two steps into a
+// three-step group, as one two-step launch.  In mirror mode the
 // tensor may hold only its kept half between launches (c->half_cur); a
 // launch that reads every entry fills the other half first.
 quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel, double2 *dev_out,
@@ -1334,7 +1337,10 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
         // Two full-window steps n, n+1.  Pairs are fixed by the global step
         // number -- (L+1, L+2), (L+3, L+4), ... -- so a run gives the same bits
         // however it is split into calls, as long as no call ends inside a pair.
-        if (c->fuse != 3 && n > L && n < last && (n - L - 1) % 2 == 0) {
+        // A call that ends two steps into a three-step group runs those two
+        // steps as one two-step launch.
+        const bool pair_tail = c->fuse == 3 && n > L && n + 1 == last && (n - L - 1) % 3 == 0;
+        if ((c->fuse != 3 && n > L && n < last && (n - L - 1) % 2 == 0) || pair_tail) {
             const bool s1 = is_sel(n + 1, si + (s0 ? 1 : 0));
             const int nsel = (s0 ? 1 : 0) + (s1 ? 1 : 0);
             if (!dev_out && staged + nsel > kRhoStage) {
@@ -1342,7 +1348,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
                 if (st != QUAPI_OK) return st;
             }
             bool done = false;
-            if (graphs && s0 == s1 && (fused || c->cur == 0)) {
+            if (graphs && !pair_tail && s0 == s1 && (fused || c->cur == 0)) {
                 hipGraphExec_t &gx = fused ? c->graph2[s0 ? 1 : 0][c->cur] : c->graph1[s0 ? 1 : 0];
                 if (!gx && build_graph(c, s0, fused ? 2 : 1, c->cur, &gx) != QUAPI_OK) {
                     c->graph_failed = true;   // stay on direct launches
@@ -1358,7 +1364,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
                     done = true;
                 }
             }
-            if (!done && fused) {
+            if (!done && (fused || pair_tail)) {
                 st = enqueue_step2(c, n, s0, s1);
                 if (st != QUAPI_OK) return st;
                 done = true;
@@ -1857,6 +1863,10 @@ quapi_status quapi_get_timing(quapi_ctx *ctx, quapi_timing *out) {
             ctx->acc_ms[r.kind] += ms;
             ctx->acc_n[r.kind] += 1;
             ctx->acc_steps += r.steps;
+            if (r.kind == 0 && r.steps >= 1 && r.steps <= 3) {
+                ctx->acc_width_ms[r.steps] += ms;
+                ctx->acc_width_n[r.steps] += 1;
+            }
         }
         ctx->pool.push_back(r.a);
         ctx->pool.push_back(r.b);
@@ -1870,6 +1880,12 @@ quapi_status quapi_get_timing(quapi_ctx *ctx, quapi_timing *out) {
     out->grow_launches = ctx->acc_n[1];
     out->finalize_ms = ctx->acc_ms[2];
     out->finalize_launches = ctx->acc_n[2];
+    for (int k = 0; k < 4; ++k) {
+        out->width_ms[k] = ctx->acc_width_ms[k];
+        out->width_launches[k] = ctx->acc_width_n[k];
+        ctx->acc_width_ms[k] = 0.0;
+        ctx->acc_width_n[k] = 0;
+    }
     for (int k = 0; k < 3; ++k) {
         ctx->acc_ms[k] = 0.0;
         ctx->acc_n[k] = 0;

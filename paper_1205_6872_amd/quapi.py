@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = (
     "quapi_mirror", "quapi_set_mirror",
     "quapi_get_setup", "quapi_read_tensor", "quapi_restore",
     "quapi_tensor_size", "quapi_set_timing", "quapi_get_timing", "quapi_destroy",
-    "quapi_last_error",
+    "quapi_last_error", "quapi_copy_bandwidth",
 )
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -55,7 +55,8 @@ class Timing(ctypes.Structure):
                 ("step_launches", ctypes.c_longlong), ("step_steps", ctypes.c_longlong),
                 ("grow_ms", ctypes.c_double),
                 ("grow_launches", ctypes.c_longlong), ("finalize_ms", ctypes.c_double),
-                ("finalize_launches", ctypes.c_longlong)]
+                ("finalize_launches", ctypes.c_longlong), ("width_ms", ctypes.c_double * 4),
+                ("width_launches", ctypes.c_longlong * 4)]
 
 
 class QuapiError(RuntimeError):
@@ -87,6 +88,7 @@ def load_library() -> ctypes.CDLL:
     lib.quapi_set_timing.argtypes = [vp, ctypes.c_int]
     lib.quapi_get_timing.argtypes = [vp, ctypes.POINTER(Timing)]
     lib.quapi_destroy.argtypes = [vp]
+    lib.quapi_copy_bandwidth.argtypes = [vp, vp, sz, sz, ctypes.c_int, vp]
     lib.quapi_last_error.argtypes = [vp]
     lib.quapi_last_error.restype = ctypes.c_char_p
     for name in EXPORTED_SYMBOLS:
@@ -284,7 +286,11 @@ class Context:
         t = Timing()
         h = self._live()
         _check(lib().quapi_get_timing(h, ctypes.byref(t)), h)
-        return {k: getattr(t, k) for k, _ in Timing._fields_}
+        out = {}
+        for k, _ in Timing._fields_:
+            v = getattr(t, k)
+            out[k] = list(v) if k.startswith("width_") else v
+        return out
 
     def destroy(self) -> None:
         if self._h:
@@ -304,6 +310,14 @@ class Context:
                 lib().quapi_destroy(self._h)
         except Exception:
             pass
+
+
+def copy_bandwidth(src: int, dst: int, nbytes: int, chunk_bytes: int, nontemporal: bool,
+                   stream: Optional[int] = None) -> None:
+    """quapi_copy_bandwidth: enqueue one chunked device copy (a measurement aid)."""
+    _check(lib().quapi_copy_bandwidth(ctypes.c_void_p(src), ctypes.c_void_p(dst), int(nbytes),
+                                      int(chunk_bytes), int(bool(nontemporal)),
+                                      ctypes.c_void_p(stream) if stream else None))
 
 
 def create(p: _ParamsHolder, stream: Optional[int] = None, workspace: Optional[int] = None,

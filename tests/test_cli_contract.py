@@ -47,3 +47,15 @@ def test_stepbench_cli_parses():
     r = _run("-m", "paper_1205_6872_amd.stepbench", "--help")
     assert r.returncode == 0
     assert "--mirror" in r.stdout and "--paper-table1" in r.stdout
+
+
+@pytest.mark.parametrize("warmup,F,want", [(5, 3, 7), (7, 3, 7), (0, 3, 1), (1, 3, 1), (5, 2, 5),
+                                            (4, 2, 5), (5, 1, 5), (0, 1, 1)])
+def test_bench_warmup_starts_the_timed_call_on_a_group(warmup, F, want):
+    # groups start at n = L+1, L+1+F, ...; the timed call starts at step L + W
+    sys.path.insert(0, str(ROOT))
+    import bench
+    w = bench.aligned_warmup(warmup, F)
+    assert w == want
+    L = 15
+    assert (L + w - L - 1) % F == 0 and w >= max(1, warmup)

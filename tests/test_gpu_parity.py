@@ -2,16 +2,16 @@
 
 Tolerances (per step n, on rho(t_n) as an M x M matrix):
   complex128   max|rho_gpu - rho_oracle| <= 1e-12 * max|rho_oracle|
-  complex64    max|rho_c64 - rho_ref| <= 1e-5 (absolute); trace drift <= 1e-6 with
-               FP64 arithmetic (c64f64), <= 1e-5 with FP32 arithmetic (c64)
+  complex64    max|rho_c64 - rho_ref| <= 1e-5 (absolute) and trace drift <= 1e-6
+               (FP64 arithmetic: max|drho| <= 1e-6 at L = 15)
 Setup values (G, eta, U, K) agree with the oracle to 1e-13 of their scale.
 
 Small cases run the whole propagation through both sides.  The L = 12
-spin-boson (500 steps) is compared at every step, the M = 3, L = 8 chain over
-its first 150 steps, both with the trace and Hermiticity invariants at every
-step.  At L = 15 and 16 (1e9 and 4e9 entries) the oracle cannot hold the
-tensor, so full-window steps are checked entry by entry on sampled outputs
-(oracle.entry).
+spin-boson (500 steps) and the M = 3, L = 8 chain (300 steps) are compared at
+every step, with the trace and Hermiticity invariants at every step.  The
+L = 15 spin-boson (1e9 entries) is compared with the oracle at every step of
+its growth and its first 8 full-window steps; full-window steps at L = 15,
+16 and 17 are also checked entry by entry on sampled outputs (oracle.entry).
 """
 import numpy as np
 import pytest
@@ -126,11 +126,12 @@ def test_bitwise_deterministic():
     assert np.array_equal(a, b)
 
 
-# The oracle takes ~50 s for the 500 steps at L = 12 and ~25 s for 150 steps of
-# the M = 3, L = 8 chain on 16 host cores.
+# The oracle takes ~50 s for the 500 steps at L = 12 and ~50 s for the 300
+# steps of the M = 3, L = 8 chain on 16 host cores.
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("wf,n_total,n_oracle", [
     (W.spin_boson_l12, 500, 500),
-    (W.three_site_l8, 300, 150),
+    (W.three_site_l8, 300, 300),
 ])
 def test_workload_sizes_against_oracle_and_invariants(wf, n_total, n_oracle):
     w = wf()
@@ -142,6 +143,54 @@ def test_workload_sizes_against_oracle_and_invariants(wf, n_total, n_oracle):
     tr = np.trace(g, axis1=1, axis2=2)
     assert np.abs(tr - 1.0).max() <= 1e-12
     assert np.abs(g - np.conj(np.swapaxes(g, 1, 2))).max() <= 1e-12
+
+
+# The L = 15 workload (4^15 entries) end to end against the oracle: growth
+# steps 1..14, the first full-window step 15 (single), whole fused groups in
+# mirror mode (three steps per launch at complex128 and complex64/FP32: 16-18,
+# 19-21; two at complex64/FP64: 16-17, 18-19, 20-21) and a single step 22 at
+# the end of the call.  With complex64 storage the tensor is above 2^28
+# entries, so complex64/FP32 runs mirror modes 2 and 3 on the concurrent
+# stream.  The oracle holds two complex128 tensors of 4^15 entries (34 GB of
+# host memory) and takes ~3 s per full-window step on 16 cores.
+L15_STEPS = 22
+
+
+@pytest.fixture(scope="module")
+def l15_oracle_rho():
+    w = W.spin_boson_l15("c128")
+    print(f"oracle: {w.name}, {L15_STEPS} steps", flush=True)
+    return orun.oracle_run(w, L15_STEPS)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", ["c128", "c64", "c64f64"])
+def test_headline_l15_rho_every_step_against_oracle(l15_oracle_rho, dtype):
+    w = W.spin_boson_l15(dtype)
+    n = L15_STEPS
+    print(f"case {w.name} {dtype}: {n} steps", flush=True)
+    with Q.create(Q.params_from(w, dtype=dtype)) as ctx:
+        F = ctx.fused_steps()
+        assert F == (2 if dtype == "c64f64" else 3) and ctx.mirror() == 1
+        ctx.set_timing(True)
+        g = ctx.propagate(n, sel=list(range(n + 1)))
+        t = ctx.get_timing()
+    # the launches that ran: steps L and L+7 single, the rest in groups of F
+    groups = (n - w.L - 1) // F
+    assert t["width_launches"][F] == groups and t["width_launches"][1] == 2, t
+    o = l15_oracle_rho
+    if dtype == "c128":
+        err = rel_err_per_step(g, o)
+        print(f"max relative |drho| per step: {err.max():.3e}", flush=True)
+        assert err.max() <= TOL_C128, (err.argmax(), err.max())
+    else:
+        tol = {"c64": 1e-5, "c64f64": 1e-6}[dtype]
+        d = np.abs(g - o).max()
+        print(f"max |drho|: {d:.3e}", flush=True)
+        assert d <= tol
+    tr = np.trace(g, axis1=1, axis2=2)
+    assert np.abs(tr - 1).max() <= (1e-12 if dtype == "c128" else 1e-6)
+    assert np.abs(g - np.conj(np.swapaxes(g, 1, 2))).max() <= (1e-12 if dtype == "c128" else 1e-6)
 
 
 def _sampled_entry_check(w, dtype, tol):
@@ -364,20 +413,26 @@ def test_m3_m4_against_oracle_every_tier(name, w, n, dtype, tol):
     assert np.abs(tr - 1).max() <= (1e-12 if dtype == "c128" else 1e-6)
 
 
-# max|drho| and trace drift against complex128 over 150 steps at L = 15.  With
-# the trace-exact FP32 rounding of K the FP32-arithmetic tier stays within
-# ~3e-7 of the complex128 trace over these steps (its remaining ~1e-6 offset
-# from the FP32 sums appears only between steps 200 and 260); with FP64
-# arithmetic only the storage rounding of 1e9 entries remains.
-@pytest.mark.parametrize("dtype,max_drho,max_drift", [("c64", 1e-5, 1e-6), ("c64f64", 1e-5, 1e-6)])
-def test_c64_tiers_against_c128_at_l15(dtype, max_drho, max_drift):
+# max|drho| and trace drift against complex128 over the whole 1000-step L = 15
+# workload.  With FP64 arithmetic (c64f64) only the storage rounding of 1e9
+# entries remains.  With FP32 arithmetic the trace difference stays below
+# ~4e-7 for 200 steps, then rises to 1.1e-6..1.9e-6 between steps 200 and 260
+# (depending on the launch width and mirror mode) and stays there.
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dtype,max_drho,max_drift", [
+    pytest.param("c64", 1e-5, 1e-6, marks=pytest.mark.xfail(
+        strict=True, reason="FP32-arithmetic tier: trace drift 1.5e-6..1.9e-6 at 1000 steps, above 1e-6")),
+    ("c64f64", 1e-5, 1e-6)])
+def test_c64_tiers_against_c128_at_l15_all_1000_steps(dtype, max_drho, max_drift):
     w = W.spin_boson_l15(dtype)
-    n = 150
+    n = w.n_steps
     r64 = gpu_rho(w, n, dtype=dtype)
     r128 = gpu_rho(w, n, dtype="c128")
     d = np.abs(r64 - r128).max()
-    drift = np.abs(np.trace(r64, axis1=1, axis2=2) - np.trace(r128, axis1=1, axis2=2)).max()
-    print(f"{dtype} vs c128 over {n} steps: max|drho| = {d:.3e}, trace drift = {drift:.3e}", flush=True)
+    tr_d = np.abs(np.trace(r64, axis1=1, axis2=2) - np.trace(r128, axis1=1, axis2=2))
+    drift = tr_d.max()
+    print(f"{dtype} vs c128 over {n} steps: max|drho| = {d:.3e}, trace drift = {drift:.3e} "
+          f"(first above 1e-6 at step {int(np.argmax(tr_d > 1e-6)) + 1 if drift > 1e-6 else None})", flush=True)
     assert d <= max_drho
     assert drift <= max_drift
 

@@ -30,8 +30,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix():
         alone = _alone(w)
         assert np.array_equal(r.rho, alone), (w.name, np.abs(r.rho - alone).max())
         tr = np.trace(r.rho, axis1=1, axis2=2)
-        # FP32 arithmetic (c64) drifts the trace by up to ~1e-6 per 100 steps
-        assert np.abs(tr - 1).max() <= {"c128": 1e-12, "c64": 1e-5, "c64f64": 1e-6}[w.dtype]
+        assert np.abs(tr - 1).max() <= {"c128": 1e-12, "c64": 1e-6, "c64f64": 1e-6}[w.dtype]
     s = summarize(res)
     assert s["requests"] == len(reqs) and s["p99_latency_s"] >= s["p50_latency_s"] > 0
 
