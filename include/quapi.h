@@ -63,7 +63,9 @@ typedef enum {
     QUAPI_C64 = 1,           /* stored in complex64, FP32 products with FP32 accumulation; the
                                 K entries of the diagonal rows (a, a) are rounded to FP32 values
                                 whose column sums are exactly delta_cd, so the rounding of K
-                                does not change the trace of rho from step to step */
+                                does not change the trace of rho from step to step, and the
+                                rows of the diagonal points, which carry the trace, sum their
+                                FP32 values exactly and round each product once */
     QUAPI_C64_F64 = 2        /* stored in complex64; each loaded value is widened and every
                                 product and sum is FP64, rounded to complex64 on store */
 } quapi_dtype;

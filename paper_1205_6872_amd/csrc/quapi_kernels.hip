@@ -413,6 +413,8 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
     using C = typename Cx<T>::type;
     using CS = typename Cx<S>::type;
     constexpr int I = GROW ? 1 : N;
+    // FP32 arithmetic, full-window N = 4, 9: the diagonal rows' sums compensated
+    constexpr bool TRACE_ROWS = sizeof(T) == 4 && !GROW && (N == 4 || N == 9);
     constexpr bool PLO_REG = (N <= 4);
     constexpr bool OLD_REG = (N <= 4);
     constexpr int ILP = (N <= 4) ? 2 : 1;
@@ -553,11 +555,24 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 #pragma unroll
                 for (int o = 0; o < N; ++o) {
                     if (!OLD_REG) asm volatile("" ::: "memory");   // table reads of this o only
-                    C s = {};
-#pragma unroll
-                    for (int i = 0; i < I; ++i) cmac(s, OLD_REG ? old_r[o * I + i] : coef_ld(old_c, o * N + i), x[u][i]);
                     const C p = cmul(PLO_REG ? plo[o] : s_plo[o * R + r], s_tq[o * Q + qm]);
-                    const C v = cmul(s, p);
+                    C v;
+                    if (TRACE_ROWS && o % (MD::M + 1) == 0 && a.n_digits > 0) {
+                        // a diagonal point with L >= 2: its oldest-point row is
+                        // ones and p is K[o, m_last]; the sum stays unrounded
+                        // until the product (these rows carry the trace)
+                        TraceSum<C> ts;
+                        ts.init(x[u][0]);
+#pragma unroll
+                        for (int i = 1; i < I; ++i) ts.add(x[u][i]);
+                        v = ts.times_right(p);
+                    } else {
+                        C s = {};
+#pragma unroll
+                        for (int i = 0; i < I; ++i)
+                            cmac(s, OLD_REG ? old_r[o * I + i] : coef_ld(old_c, o * N + i), x[u][i]);
+                        v = cmul(s, p);
+                    }
                     if (MODE == 0 || MD::digit(o) >= o) {
                         aout[m + mc * o] = conv<CS>(v);
                     } else if (MODE != 3) {

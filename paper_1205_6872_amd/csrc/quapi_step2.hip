@@ -136,6 +136,10 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
             asm volatile("" ::: "memory");
             const int qm = MODE == 3 ? diagonal_digits4((unsigned)it) : it;
             const long long m = m0 + (long long)qm * R + r;
+            // opaque per item: the factor reads from LDS stay in the loop
+            // instead of being hoisted into registers for the whole block
+            int rl = r;
+            asm volatile("" : "+v"(rl));
             const long long mb = MODE == 0 ? m : mirror4(m);
             if (MODE == 2 && mb <= m) continue;   // own mirror (mode 3), or run by its mirror
             constexpr bool selfm = MODE == 3;
@@ -149,7 +153,7 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
             C cn1[N], totf[RHO ? N : 1];
 #pragma unroll
             for (int op = 0; op < N; ++op) {
-                cn1[op] = cmul(s_plo[(1 * N + op) * R + r], s_tq[(1 * N + op) * Q + qm]);
+                cn1[op] = cmul(s_plo[(1 * N + op) * R + rl], s_tq[(1 * N + op) * Q + qm]);
                 if (RHO) totf[op] = C{};
             }
             // Diagonal points o = (a, a) (o = 0 and 3) carry no influence: every
@@ -158,12 +162,15 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
             // factor, no K) are ones in the rows o = 0, 3, and DO, V (K folded
             // in) do not depend on i' in the rows o' = 0, 3: those rows reduce
             // to plain sums over the summed point, shared by both diagonal rows.
-            C sx[N], totd = {};
+            // (With FP32 arithmetic these shared sums stay unrounded until their
+            // products, TraceSum: the diagonal rows carry the trace.)
+            TraceSum<C> sx[N];
+            C totd = {};
 #pragma unroll
             for (int ip = 0; ip < N; ++ip) {
-                sx[ip] = x[N * ip];
+                sx[ip].init(x[N * ip]);
 #pragma unroll
-                for (int i = 1; i < N; ++i) sx[ip] = cadd(sx[ip], x[i + N * ip]);
+                for (int i = 1; i < N; ++i) sx[ip].add(x[i + N * ip]);
             }
             if (RHO) {
                 totd = x[0];
@@ -179,17 +186,18 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
                 asm volatile("" ::: "memory");  // coefficient reads of this o only
                 const T *co = coef + 2 * kCoefPerO * o;
                 const bool dg = o == 0 || o == 3;
-                const C bn = cmul(s_plo[(0 * N + o) * R + r], s_tq[(0 * N + o) * Q + qm]);
+                const C bn = cmul(s_plo[(0 * N + o) * R + rl], s_tq[(0 * N + o) * Q + qm]);
                 C y[N];
 #pragma unroll
                 for (int ip = 0; ip < N; ++ip) {
-                    C sum = sx[ip];
-                    if (!dg) {
-                        sum = C{};
+                    if (dg) {
+                        y[ip] = sx[ip].times(bn);
+                    } else {
+                        C sum = {};
 #pragma unroll
                         for (int i = 0; i < N; ++i) cmac(sum, coef_ld(co, kCoefOA + ip * N + i), x[i + N * ip]);
+                        y[ip] = cmul(bn, sum);
                     }
-                    y[ip] = cmul(bn, sum);
                 }
                 if (RHO) {
                     C tot = totd;
@@ -198,21 +206,22 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
 #pragma unroll
                         for (int k = 0; k < NN; ++k) cmac(tot, coef_ld(co, kCoefW + k), x[k]);
                     }
-                    const C bnf = cmul(s_plo[(2 * N + o) * R + r], s_tq[(2 * N + o) * Q + qm]);
+                    const C bnf = cmul(s_plo[(2 * N + o) * R + rl], s_tq[(2 * N + o) * Q + qm]);
                     const double2 v = to_d2(cmul(bnf, tot));
                     accn[o].x += v.x;
                     accn[o].y += v.y;
                 }
-                C ysum = y[0];
+                TraceSum<C> ysum;
+                ysum.init(y[0]);
 #pragma unroll
-                for (int ip = 1; ip < N; ++ip) ysum = cadd(ysum, y[ip]);
+                for (int ip = 1; ip < N; ++ip) ysum.add(y[ip]);
 #pragma unroll
                 for (int op = 0; op < N; ++op) {
                     asm volatile("" ::: "memory");
                     const bool dgp = op == 0 || op == 3;
                     C sum = {};
                     if (dgp) {
-                        sum = cmul(coef_ld(co, kCoefDO + op * N), ysum);
+                        sum = ysum.times(coef_ld(co, kCoefDO + op * N));
                     } else {
 #pragma unroll
                         for (int ip = 0; ip < N; ++ip) cmac(sum, coef_ld(co, kCoefDO + op * N + ip), y[ip]);
@@ -228,7 +237,7 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
                     }
                     if (RHO) {
                         if (dgp) {
-                            cmac(totf[op], coef_ld(co, kCoefV + op * N), ysum);
+                            cmac(totf[op], coef_ld(co, kCoefV + op * N), ysum.rounded());
                         } else {
 #pragma unroll
                             for (int ip = 0; ip < N; ++ip) cmac(totf[op], coef_ld(co, kCoefV + op * N + ip), y[ip]);
@@ -240,7 +249,7 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
                 asm volatile("" ::: "memory");
 #pragma unroll
                 for (int op = 0; op < N; ++op) {
-                    const C cf1 = cmul(s_plo[(3 * N + op) * R + r], s_tq[(3 * N + op) * Q + qm]);
+                    const C cf1 = cmul(s_plo[(3 * N + op) * R + rl], s_tq[(3 * N + op) * Q + qm]);
                     const double2 v = to_d2(cmul(cf1, totf[op]));
                     accn1[op].x += v.x;
                     accn1[op].y += v.y;

@@ -209,7 +209,10 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 2 : 1) step3_kernel(c
         const int istep = MODE == 3 ? kBlock : cR;
         for (int it = i0; it < i1; it += istep) {
             asm volatile("" ::: "memory");
-            const int r = MODE == 3 ? diagonal_digits((unsigned)it & ((1u << dl) - 1)) : t % R;
+            int r = MODE == 3 ? diagonal_digits((unsigned)it & ((1u << dl) - 1)) : t % R;
+            // opaque per item: the factor reads from LDS below stay in the loop
+            // instead of being hoisted (and, short of registers, spilled)
+            asm volatile("" : "+v"(r));
             const int qm = MODE == 3 ? diagonal_digits((unsigned)it >> dl) : it;
             const long long m = m0 + (long long)qm * R + r;
             const long long mb = HALF ? mirror4(m) : m;
@@ -236,7 +239,9 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 2 : 1) step3_kernel(c
             // there.  So the old / old_f rows of o = 0, 3 and the step-n group
             // factors AF of o = 0, 3 (lags L-1 and L-2 >= 2, no K) are ones, and
             // their sums over the summed point are one plain sum shared by both
-            // rows -- the same additions in the same order as the general form.
+            // rows -- the same additions in the same order as the general form
+            // (with FP32 arithmetic kept unrounded until their products,
+            // TraceSum: these rows carry the trace).
             // ---- step n: groups g = i' + N i'', slots 4g .. 4g+3
             {
                 if (RHO) {
@@ -273,9 +278,14 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 2 : 1) step3_kernel(c
                     C xs[N];
 #pragma unroll
                     for (int i = 0; i < N; ++i) xs[i] = w[N * g + i];
-                    C sd = xs[0];
+                    {
+                        TraceSum<C> sd;
+                        sd.init(xs[0]);
 #pragma unroll
-                    for (int i = 1; i < N; ++i) sd = cadd(sd, xs[i]);
+                        for (int i = 1; i < N; ++i) sd.add(xs[i]);
+                        w[N * g] = sd.times(bn[0]);
+                        w[N * g + 3] = sd.times(bn[3]);
+                    }
 #pragma unroll
                     for (int o = 1; o <= 2; ++o) {
                         C s = {};
@@ -283,8 +293,6 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 2 : 1) step3_kernel(c
                         for (int i = 0; i < N; ++i) cmac(s, coef_ld(co, kC3Old + o * N + i), xs[i]);
                         w[N * g + o] = cmul(bn[o], cmul(coef_ld(cg, kC3AF + g * N + o), s));
                     }
-                    w[N * g] = cmul(bn[0], sd);
-                    w[N * g + 3] = cmul(bn[3], sd);
                 }
             }
             // ---- step n+1: groups (o, i''), slots o + N i' + N^2 i'' over i'
@@ -332,17 +340,21 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 2 : 1) step3_kernel(c
                         C ys[N];
 #pragma unroll
                         for (int ip = 0; ip < N; ++ip) ys[ip] = w[o + N * ip + N * N * ipp];
-                        C sd = ys[0];
+                        {
+                            TraceSum<C> sd;
+                            sd.init(ys[0]);
 #pragma unroll
-                        for (int ip = 1; ip < N; ++ip) sd = cadd(sd, ys[ip]);
+                            for (int ip = 1; ip < N; ++ip) sd.add(ys[ip]);
 #pragma unroll
-                        for (int op = 0; op < N; ++op) {
-                            C s = sd;
-                            if (op == 1 || op == 2) {
-                                s = C{};
+                            for (int op = 0; op < N; op += 3)
+                                w[o + N * op + N * N * ipp] =
+                                    cmul(cn[op], sd.times(coef_ld(cg, kC3GH + (ipp * N + o) * N + op)));
+                        }
 #pragma unroll
-                                for (int ip = 0; ip < N; ++ip) cmac(s, coef_ld(co, kC3Old + op * N + ip), ys[ip]);
-                            }
+                        for (int op = 1; op <= 2; ++op) {
+                            C s = {};
+#pragma unroll
+                            for (int ip = 0; ip < N; ++ip) cmac(s, coef_ld(co, kC3Old + op * N + ip), ys[ip]);
                             w[o + N * op + N * N * ipp] =
                                 cmul(cn[op], cmul(coef_ld(cg, kC3GH + (ipp * N + o) * N + op), s));
                         }
@@ -397,22 +409,27 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 2 : 1) step3_kernel(c
                         C zs[N];
 #pragma unroll
                         for (int ipp = 0; ipp < N; ++ipp) zs[ipp] = w[o + N * op + N * N * ipp];
-                        C sd = zs[0];
-#pragma unroll
-                        for (int ipp = 1; ipp < N; ++ipp) sd = cadd(sd, zs[ipp]);
-#pragma unroll
-                        for (int opp = 0; opp < N; ++opp) {
-                            C s = sd;
-                            if (opp == 1 || opp == 2) {
-                                s = C{};
-#pragma unroll
-                                for (int ipp = 0; ipp < N; ++ipp)
-                                    cmac(s, coef_ld(co, kC3Old + opp * N + ipp), zs[ipp]);
-                            }
-                            const C v = cmul(dn[opp], cmul(coef_ld(cg, kC3PQ + (op * N + o) * N + opp), s));
+                        auto store = [&](int opp, C u) {
+                            const C v = cmul(dn[opp], u);
                             const int c3 = o + N * op + N * N * opp;
                             if (!HALF || (int)mirror4(c3) >= c3) po[st * N * N * opp] = conv<CS>(v);
                             else if (!selfm) pb[st * N * N * mirror_digit(opp)] = conv<CS>(cconj(v));
+                        };
+                        {
+                            TraceSum<C> sd;
+                            sd.init(zs[0]);
+#pragma unroll
+                            for (int ipp = 1; ipp < N; ++ipp) sd.add(zs[ipp]);
+#pragma unroll
+                            for (int opp = 0; opp < N; opp += 3)
+                                store(opp, sd.times(coef_ld(cg, kC3PQ + (op * N + o) * N + opp)));
+                        }
+#pragma unroll
+                        for (int opp = 1; opp <= 2; ++opp) {
+                            C s = {};
+#pragma unroll
+                            for (int ipp = 0; ipp < N; ++ipp) cmac(s, coef_ld(co, kC3Old + opp * N + ipp), zs[ipp]);
+                            store(opp, cmul(coef_ld(cg, kC3PQ + (op * N + o) * N + opp), s));
                         }
                     }
                 }
