@@ -165,6 +165,33 @@ quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_
 quapi_status quapi_propagate_async(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
                                    void *rho_out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * propagation -- the setup of quapi_create, n_steps steps from step 0 and
+ * rho at the selected steps, as quapi_propagate_async -- with its entire
+ * working set (both tensors, the factor tables and the rho reduction
+ * buffers) in a static device array of 64 MiB that the library holds on each
+ * GPU until the process ends.  It calls no hipMalloc or hipFree and creates
+ * no streams or events: every kernel runs on hip_stream (NULL: the null
+ * stream).
+ *   p, n_steps, sel, n_sel   as quapi_create / quapi_propagate (global steps
+ *                            0 < k <= n_steps, or k = 0 for rho0)
+ *   rho_out_dev              device memory of n_out * M*M complex128,
+ *                            caller-owned, written in selection order
+ * Blocks until the work has finished on hip_stream, then returns; the result
+ * equals quapi_create + quapi_propagate_async on the same parameters, bit for
+ * bit (the same kernels run in the same order; no captured graphs).
+ * Every call on one GPU uses that GPU's one array, which keeps the last call's
+ * contents: calls from different threads of a process on one GPU are
+ * serialized by the library, and a call must not overlap other work that
+ * reads or writes it (there is none outside this call).
+ * Errors: QUAPI_ERR_INVALID for malformed parameters or selection, NULL
+ * rho_out_dev with outputs selected, or a working set (quapi_footprint)
+ * above 64 MiB (e.g. M = 2 beyond dk_max = 10 at complex128); QUAPI_ERR_DEVICE
+ * for runtime or launch failures. */
+quapi_status quapi_propagate_static(const quapi_params *p, int n_steps, const int *sel, int n_sel,
+                                    void *rho_out_dev, void *hip_stream);
+
 /* Global step index the context has reached (0 after create). */
 quapi_status quapi_step_count(const quapi_ctx *ctx, int *step);
 

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -447,6 +448,9 @@ struct quapi_ctx {
     double dt = 0.0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // one stream only (quapi_propagate_static): no side or aux streams, no
+    // events, the rho finalize on the context's stream, no graphs
+    bool one_stream = false;
     // rho finalize kernels run on a side stream, overlapped with the next
     // step; the block partials rotate over kSlots buffers between the streams
     hipStream_t side = nullptr;
@@ -699,6 +703,13 @@ quapi_status ensure_full(quapi_ctx *c) {
 // Finalize the rho partials of `slots` (in order) on the side stream, after
 // the step kernel that wrote them.
 quapi_status finalize_side(quapi_ctx *c, const int *slots, int n, int grid) {
+    if (c->one_stream) {
+        for (int k = 0; k < n; ++k) {
+            hipError_t e = launch_rho_finalize(c->N, c->partials[slots[k]], grid, c->pairs, c->sink, c->stream);
+            if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "rho finalize launch: %s", hipGetErrorString(e));
+        }
+        return QUAPI_OK;
+    }
     HIP_TRY(c, hipEventRecord(c->ev_step[slots[0]], c->stream));
     HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_step[slots[0]], 0));
     for (int k = 0; k < n; ++k) {
@@ -1142,7 +1153,7 @@ quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
         e1 = take_event(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
-    const bool concurrent = step3_concurrent((size_t)ipow_ll(c->N, c->L), c->prec);
+    const bool concurrent = step3_concurrent((size_t)ipow_ll(c->N, c->L), c->prec) && c->aux != nullptr;
     int rows = 0;
     hipError_t e = launch_step3_modes(c, rho, a, &rows, concurrent);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "three-step launch: %s", hipGetErrorString(e));
@@ -1442,29 +1453,11 @@ void release(quapi_ctx *c) {
     delete c;
 }
 
-}  // namespace
-
-// ===================================================================== ABI
-extern "C" {
-
-size_t quapi_paper_pmc_bytes(int M, int dk_max) {
-    if (M < 1 || dk_max < 0) return 0;
-    size_t e;
-    if (!checked_pow((size_t)M, 2 * (dk_max + 1), &e)) return 0;
-    if (e > std::numeric_limits<size_t>::max() / 64) return 0;
-    return 64 * e;
-}
-
-quapi_status quapi_footprint(const quapi_params *p, size_t *device_bytes) {
-    const std::string msg = validate(p);
-    if (!msg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", msg.c_str());
-    if (!device_bytes) return fail(nullptr, QUAPI_ERR_INVALID, "device_bytes is NULL");
-    *device_bytes = make_layout(*p, count_panels(*p)).total;
-    return QUAPI_OK;
-}
-
-quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspace, size_t ws_bytes,
-                          quapi_ctx **out) {
+// quapi_create, and with one_stream the context of quapi_propagate_static:
+// the caller's stream only (no side or aux streams, no events, no graphs) and
+// the given workspace (never a device allocation).
+quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace, size_t ws_bytes, bool one_stream,
+                        quapi_ctx **out) {
     if (!out) return fail(nullptr, QUAPI_ERR_INVALID, "out is NULL");
     *out = nullptr;
     const std::string msg = validate(p);
@@ -1499,7 +1492,9 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->csize = p->dtype == QUAPI_C128 ? 16 : 8;
     c->dt = p->dt;
     c->lay = lay;
-    if (hip_stream) {
+    c->one_stream = one_stream;
+    c->graph_failed = one_stream;
+    if (hip_stream || one_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
         if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -1508,11 +1503,12 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
         }
         c->own_stream = true;
     }
-    bool side_ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
-                   hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess &&
-                   hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
-                   hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
-    for (int k = 0; k < kSlots && side_ok; ++k)
+    bool side_ok = one_stream ||
+                   (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
+                    hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess &&
+                    hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
+                    hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess);
+    for (int k = 0; k < kSlots && side_ok && !one_stream; ++k)
         side_ok = hipEventCreateWithFlags(&c->ev_step[k], hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&c->ev_fin[k], hipEventDisableTiming) == hipSuccess;
     if (!side_ok) {
@@ -1633,8 +1629,10 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     }
 
     hipEvent_t s0 = nullptr, s1 = nullptr;
-    (void)hipEventCreate(&s0);
-    (void)hipEventCreate(&s1);
+    if (!one_stream) {
+        (void)hipEventCreate(&s0);
+        (void)hipEventCreate(&s1);
+    }
     if (s0) (void)hipEventRecord(s0, c->stream);
     QuadArgs qa{};
     qa.kind = p->bath.kind;
@@ -1692,6 +1690,83 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
     c->step = 0;
     *out = c;
     return QUAPI_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ static scratch
+// The whole working set of quapi_propagate_static (both tensors, the factor
+// tables, the rho reduction buffers): a file-scope device array, one copy on
+// every GPU the library runs on, held until the process ends.  In host code
+// the array's name is not a device address: kernels and copies get the
+// address hipGetSymbolAddress returns on the current device.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu[kMaxStaticDevices];        // one static call at a time per device
+void *g_static_ptr[kMaxStaticDevices] = {};       // the device address of `scratch`, per device
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+size_t quapi_paper_pmc_bytes(int M, int dk_max) {
+    if (M < 1 || dk_max < 0) return 0;
+    size_t e;
+    if (!checked_pow((size_t)M, 2 * (dk_max + 1), &e)) return 0;
+    if (e > std::numeric_limits<size_t>::max() / 64) return 0;
+    return 64 * e;
+}
+
+quapi_status quapi_footprint(const quapi_params *p, size_t *device_bytes) {
+    const std::string msg = validate(p);
+    if (!msg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", msg.c_str());
+    if (!device_bytes) return fail(nullptr, QUAPI_ERR_INVALID, "device_bytes is NULL");
+    *device_bytes = make_layout(*p, count_panels(*p)).total;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspace, size_t ws_bytes,
+                          quapi_ctx **out) {
+    return create_ctx(p, hip_stream, workspace, ws_bytes, false, out);
+}
+
+quapi_status quapi_propagate_static(const quapi_params *p, int n_steps, const int *sel, int n_sel,
+                                    void *rho_out_dev, void *hip_stream) {
+    const std::string msg = validate(p);
+    if (!msg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", msg.c_str());
+    if (n_steps < 0) return fail(nullptr, QUAPI_ERR_INVALID, "n_steps must be >= 0");
+    const size_t need = make_layout(*p, count_panels(*p)).total;
+    if (need > kStaticScratchBytes)
+        return fail(nullptr, QUAPI_ERR_INVALID,
+                    "the working set needs %zu bytes; the static scratch holds %zu (use quapi_create)", need,
+                    kStaticScratchBytes);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0) return fail(nullptr, QUAPI_ERR_DEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev >= kMaxStaticDevices) return fail(nullptr, QUAPI_ERR_DEVICE, "device %d beyond the static scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_static_mu[dev]);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(nullptr, QUAPI_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_static_ptr[dev] = ptr;
+    }
+    quapi_ctx *c = nullptr;
+    quapi_status st = create_ctx(p, hip_stream, g_static_ptr[dev], kStaticScratchBytes, true, &c);
+    if (st != QUAPI_OK) return st;
+    int n_out = 0;
+    st = check_selection(c, n_steps, sel, n_sel, &n_out);
+    if (st == QUAPI_OK && n_out > 0 && !rho_out_dev) st = fail(c, QUAPI_ERR_INVALID, "rho_out_dev is NULL");
+    if (st == QUAPI_OK) st = propagate_impl(c, n_steps, sel, n_sel, (double2 *)rho_out_dev, nullptr);
+    e = hipStreamSynchronize(c->stream);
+    if (st == QUAPI_OK && e != hipSuccess)
+        st = fail(c, QUAPI_ERR_DEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+    release(c);
+    return st;
 }
 
 quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel, double *rho_out) {

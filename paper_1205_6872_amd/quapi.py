@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = (
     "quapi_mirror", "quapi_set_mirror",
     "quapi_get_setup", "quapi_read_tensor", "quapi_restore",
     "quapi_tensor_size", "quapi_set_timing", "quapi_get_timing", "quapi_destroy",
-    "quapi_last_error", "quapi_copy_bandwidth",
+    "quapi_last_error", "quapi_copy_bandwidth", "quapi_propagate_static",
 )
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -89,6 +89,7 @@ def load_library() -> ctypes.CDLL:
     lib.quapi_get_timing.argtypes = [vp, ctypes.POINTER(Timing)]
     lib.quapi_destroy.argtypes = [vp]
     lib.quapi_copy_bandwidth.argtypes = [vp, vp, sz, sz, ctypes.c_int, vp]
+    lib.quapi_propagate_static.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ip, ctypes.c_int, vp, vp]
     lib.quapi_last_error.argtypes = [vp]
     lib.quapi_last_error.restype = ctypes.c_char_p
     for name in EXPORTED_SYMBOLS:
@@ -318,6 +319,21 @@ def copy_bandwidth(src: int, dst: int, nbytes: int, chunk_bytes: int, nontempora
     _check(lib().quapi_copy_bandwidth(ctypes.c_void_p(src), ctypes.c_void_p(dst), int(nbytes),
                                       int(chunk_bytes), int(bool(nontemporal)),
                                       ctypes.c_void_p(stream) if stream else None))
+
+
+def propagate_static(p: _ParamsHolder, n_steps: int, sel: Optional[Sequence[int]], rho_out_dev: int,
+                     stream: Optional[int] = None) -> None:
+    """quapi_propagate_static: setup + n_steps steps in the library's static
+    scratch (no device allocation); rho at the selected steps (None: every
+    step 1..n_steps) goes to device memory at rho_out_dev."""
+    if sel is None:
+        psel, n_sel = None, 0
+    else:
+        sel_arr, n_sel = _sel_array(sel)
+        psel = sel_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    _check(lib().quapi_propagate_static(ctypes.byref(p.p), int(n_steps), psel, n_sel,
+                                        ctypes.c_void_p(rho_out_dev) if rho_out_dev else None,
+                                        ctypes.c_void_p(stream) if stream else None))
 
 
 def create(p: _ParamsHolder, stream: Optional[int] = None, workspace: Optional[int] = None,

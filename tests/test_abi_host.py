@@ -151,3 +151,13 @@ def test_null_context_calls_are_invalid():
     assert b"NULL" in lib.quapi_last_error(None)
     buf = (ctypes.c_double * 8)()
     assert lib.quapi_restore(None, 0, buf, 4) == Q.ERR_INVALID
+
+
+def test_static_entry_point_refuses_a_working_set_above_its_scratch_without_a_device():
+    # the size check comes before any device call
+    from paper_1205_6872_amd import workloads as W
+    big = W.spin_boson_l7().with_(L=11)
+    assert Q.footprint(Q.params_from(big)) > 64 << 20
+    with pytest.raises(Q.QuapiError) as ei:
+        Q.propagate_static(Q.params_from(big), 3, None, 0)
+    assert ei.value.status == Q.ERR_INVALID and "static scratch" in str(ei.value)
