@@ -260,9 +260,10 @@ def serve_trace(n_requests: int, policy: str = "sjf", chunk_ms=8.0, chunk_steps:
     reqs = W.serving_requests()[:n_requests]
     log(f"bench: serving {len(reqs)} requests ({reqs[-1].meta['arrival_s']:.1f} s of arrivals), "
         f"policy {policy}")
-    res = Server(max_active=8, chunk_steps=chunk_steps, chunk_ms=chunk_ms, policy=policy,
-                 progress=True).run(reqs, realtime=True)
+    srv = Server(max_active=8, chunk_steps=chunk_steps, chunk_ms=chunk_ms, policy=policy, progress=True)
+    res = srv.run(reqs, realtime=True)
     s = summarize(res)
+    s.update({"batched_requests": srv.batched, "batch_calls": srv.batch_calls})
     s.update({"trace": "seeded Poisson, 20 requests/s, seed 2026", "sample": f"first {len(reqs)} of 512",
               "max_active": 8, "policy": policy,
               "chunk": f"{chunk_ms} ms of estimated device time" if chunk_ms else f"{chunk_steps} steps",

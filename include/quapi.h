@@ -192,6 +192,41 @@ quapi_status quapi_propagate_async(quapi_ctx *ctx, int n_steps, const int *sel, 
 quapi_status quapi_propagate_static(const quapi_params *p, int n_steps, const int *sel, int n_sel,
                                     void *rho_out_dev, void *hip_stream);
 
+/* The persistent path.  A context whose tensor has at most 2^14 entries
+ * (N^L; M = 2 up to dk_max = 7, M = 3 up to 4, M = 4 up to 3) runs every
+ * step of a call in one launch, one workgroup per context: the tensor stays
+ * in LDS when both of its buffers fit there (M = 2 up to dk_max = 6),
+ * otherwise in the context's two buffers in HBM, which stay in the L2 cache
+ * at these sizes; a step costs a workgroup barrier instead of kernel
+ * launches.  Not for driven contexts, contexts whose launch width is pinned
+ * (quapi_set_fused_steps != 0) or mirror mode 2.  Results do not depend on
+ * how a run is split into calls or batched.
+ *   quapi_persistent:  *mode = 0 (multi-block kernels), 1 (persistent, tensor
+ *                      in LDS) or 2 (persistent, tensor in HBM).
+ * Errors: QUAPI_ERR_INVALID for NULL arguments. */
+quapi_status quapi_persistent(const quapi_ctx *ctx, int *mode);
+
+/* Advance n_ctx contexts in as few launches as possible: the serving loop's
+ * batched form of quapi_propagate_async (the paper's many runs that differ
+ * in a parameter, Sec. IV).  Every context must be on the persistent path
+ * (quapi_persistent != 0), and all must have the same M and dtype (their
+ * memory lengths, baths, Hamiltonians and step counts may differ); one
+ * workgroup runs one context, up to 32 contexts per launch.  Context k
+ * advances n_steps[k] >= 0 steps and writes rho to device memory
+ * rho_out_dev[k] (caller-owned, complex128, N values per output):
+ *   rho_mode[k] = 0 none, 1 every step (n_steps[k] outputs, 'allPoints'),
+ *                 2 the last step only (one output, 'justFinalPoint').
+ * Enqueued on the first context's stream, after the work already queued on
+ * every context's stream; later work on any of the contexts' streams runs
+ * after it.  Returns at once.  Each context's results equal those of its
+ * own quapi_propagate calls over the same steps, bit for bit.
+ * Errors: QUAPI_ERR_INVALID for NULL arguments, a repeated or unsuitable
+ * context, mixed M or dtype, negative steps, rho_mode outside 0..2 or a NULL
+ * output buffer with outputs; QUAPI_ERR_STATE when a context is in use;
+ * QUAPI_ERR_DEVICE on launch failure. */
+quapi_status quapi_propagate_batch(quapi_ctx *const *ctxs, int n_ctx, const int *n_steps, const int *rho_mode,
+                                   void *const *rho_out_dev);
+
 /* Global step index the context has reached (0 after create). */
 quapi_status quapi_step_count(const quapi_ctx *ctx, int *step);
 

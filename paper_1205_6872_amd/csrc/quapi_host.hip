@@ -486,6 +486,10 @@ struct quapi_ctx {
     bool plan2_ready = false;     // fused-step factor tables computed
     bool plan3_ready = false;     // three-step factor tables computed
     int fuse = 1;                 // full-window steps per launch (fusion_width)
+    bool fuse_pinned = false;     // quapi_set_fused_steps chose a width
+    // persistent path (small tensors, quapi_small.hip): 0 off, 1 tensor in
+    // LDS, 2 tensor in the context's global buffers
+    int small = 0;
     // Mirror mode of the full-window kernels: they read and write only the
     // entries not above their mirror; half_cur says A[cur] holds only those.
     bool mirror_ok = false;       // M = 2, 3, 4, L >= 2, rho0 exactly Hermitian
@@ -508,7 +512,9 @@ struct quapi_ctx {
     // timing
     bool timing = false;
     double setup_ms = 0.0;
-    struct Rec { int kind; hipEvent_t a, b; int steps; };   // steps: full-window steps covered
+    // steps: full-window steps covered; width: steps per launch of a fused or
+    // single step (1..3), 0 for a persistent launch
+    struct Rec { int kind; hipEvent_t a, b; int steps; int width; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     double acc_ms[3] = {0, 0, 0};
@@ -724,7 +730,7 @@ quapi_status finalize_side(quapi_ctx *c, const int *slots, int n, int grid) {
         if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "rho finalize launch: %s", hipGetErrorString(e));
         if (c->timing && f0 && f1) {
             (void)hipEventRecord(f1, c->side);
-            c->recs.push_back({2, f0, f1, 0});
+            c->recs.push_back({2, f0, f1, 0, 0});
         }
         HIP_TRY(c, hipEventRecord(c->ev_fin[sl], c->side));
         c->fin_pending[sl] = true;
@@ -812,7 +818,7 @@ quapi_status enqueue_step(quapi_ctx *c, int n, bool rho) {
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "step kernel launch: %s", hipGetErrorString(e));
     if (c->timing && e0 && e1) {
         (void)hipEventRecord(e1, c->stream);
-        c->recs.push_back({sp.grow ? 1 : 0, e0, e1, sp.grow ? 0 : 1});
+        c->recs.push_back({sp.grow ? 1 : 0, e0, e1, sp.grow ? 0 : 1, sp.grow ? 0 : 1});
     }
     if (rho) {
         st = finalize_side(c, &slot, 1, rows);
@@ -975,7 +981,7 @@ quapi_status enqueue_step2(quapi_ctx *c, int n, bool sel_n, bool sel_n1) {
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "fused step launch: %s", hipGetErrorString(e));
     if (c->timing && e0 && e1) {
         (void)hipEventRecord(e1, c->stream);
-        c->recs.push_back({0, e0, e1, 2});
+        c->recs.push_back({0, e0, e1, 2, 2});
     }
     if (rho) {
         int fin[2], nf = 0;
@@ -1159,7 +1165,7 @@ quapi_status enqueue_step3(quapi_ctx *c, int n, const bool *selk) {
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "three-step launch: %s", hipGetErrorString(e));
     if (c->timing && e0 && e1) {
         (void)hipEventRecord(e1, c->stream);
-        c->recs.push_back({0, e0, e1, 3});
+        c->recs.push_back({0, e0, e1, 3, 3});
     }
     if (rho) {
         int fin[3], nf = 0;
@@ -1257,6 +1263,115 @@ quapi_status check_selection(quapi_ctx *c, int n_steps, const int *sel, int n_se
     return QUAPI_OK;
 }
 
+// ---------------------------------------------------------- persistent path
+// Small tensors (N^L <= 2^14) run every step of a call in one launch of the
+// persistent kernel, one block per context: a step costs a block barrier
+// instead of three launches.  Contexts that pin a launch width, force mirror
+// mode at every size, or are driven use the multi-block kernels.
+bool small_on(const quapi_ctx *c) {
+    return c->small != 0 && c->n_H == 0 && !c->fuse_pinned && c->mirror != 2;
+}
+
+SmallCtxArgs small_args(const quapi_ctx *c, int n_steps, int rho_mode, double2 *rho_out) {
+    SmallCtxArgs s{};
+    s.bank = c->bank;
+    s.a0 = c->A[c->cur];
+    s.a1 = c->A[1 - c->cur];
+    s.rho_out = rho_out;
+    s.L = c->L;
+    s.step0 = c->step;
+    s.n_steps = n_steps;
+    s.rho_mode = rho_mode;
+    return s;
+}
+
+// After a persistent launch of n steps: the tensor is in A[cur] after an
+// even number of steps, in the other buffer after an odd one.
+void small_advance(quapi_ctx *c, int n) {
+    c->step += n;
+    if (n & 1) c->cur = 1 - c->cur;
+}
+
+// The persistent path of propagate_impl: one launch per run of consecutive
+// selected steps and per stretch of steps up to an isolated selected step
+// (one launch for 'allPoints', 'justFinalPoint' or no selection); the
+// blocking call also cuts runs at the staging buffer's size.
+quapi_status propagate_small(quapi_ctx *c, int n_steps, const int *sel, int n_sel, double2 *dev_out,
+                             double *host_out) {
+    const int N = c->N;
+    int si = 0, written = 0, staged = 0;
+    if (sel && si < n_sel && sel[si] == 0) {  // rho(t_0) = rho0
+        if (dev_out)
+            HIP_TRY(c, hipMemcpyAsync(dev_out, c->rho0_d, (size_t)N * 16, hipMemcpyDeviceToDevice, c->stream));
+        else
+            std::memcpy(host_out, c->rho0_h.data(), (size_t)N * 16);
+        ++si;
+        ++written;
+    }
+    quapi_status st = join_side(c);
+    if (st == QUAPI_OK) st = ensure_full(c);
+    if (st != QUAPI_OK) return st;
+    auto flush = [&]() -> quapi_status {
+        if (!staged) return QUAPI_OK;
+        HIP_TRY(c, hipMemcpyAsync(host_out + (size_t)2 * N * (written - staged), c->stage,
+                                  (size_t)staged * N * 16, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        staged = 0;
+        return QUAPI_OK;
+    };
+    const int last = c->step + n_steps;
+    while (c->step < last) {
+        int k, mode;
+        if (!sel) {
+            k = last - c->step;
+            mode = 1;
+        } else if (si < n_sel && sel[si] == c->step + 1) {
+            // a run of consecutive selected steps: rho at every one
+            k = 1;
+            while (si + k < n_sel && sel[si + k] == c->step + 1 + k) ++k;
+            mode = 1;
+        } else if (si < n_sel) {
+            k = sel[si] - c->step;    // up to the next selected step
+            mode = 2;
+        } else {
+            k = last - c->step;
+            mode = 0;
+        }
+        if (!dev_out && mode != 0) {
+            if (staged == kRhoStage && (st = flush()) != QUAPI_OK) return st;
+            if (mode == 1) k = std::min(k, kRhoStage - staged);
+        }
+        double2 *out = dev_out ? dev_out + (size_t)written * N : c->stage + (size_t)staged * N;
+        SmallBatchArgs b;
+        b.c[0] = small_args(c, k, mode, out);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) {
+            e0 = take_event(c);
+            e1 = take_event(c);
+            if (e0) (void)hipEventRecord(e0, c->stream);
+        }
+        hipError_t e = launch_small(N, c->prec, c->small == 1, b, 1, c->L, c->stream);
+        if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "persistent step launch: %s", hipGetErrorString(e));
+        if (c->timing && e0 && e1) {
+            (void)hipEventRecord(e1, c->stream);
+            // full-window steps of the launch (n >= L); a launch of growth steps only counts as growth
+            const int full = std::max(0, c->step + k - std::max(c->step, c->L - 1));
+            c->recs.push_back({full > 0 ? 0 : 1, e0, e1, full, 0});
+        }
+        const int outs = mode == 1 ? k : mode == 2 ? 1 : 0;
+        small_advance(c, k);
+        written += outs;
+        if (!dev_out) staged += outs;
+        if (sel) si += outs;
+    }
+    if (!dev_out) {
+        st = flush();
+        if (st != QUAPI_OK) return st;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return QUAPI_OK;
+}
+
 // Shared driver of the blocking and asynchronous calls.  dev_out: device
 // output of n_out slots (async), or NULL to stage and copy into host_out.
 //
@@ -1274,6 +1389,7 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
     quapi_status st = check_selection(c, n_steps, sel, n_sel, &n_out);
     if (st != QUAPI_OK) return st;
     if (n_out > 0 && !dev_out && !host_out) return fail(c, QUAPI_ERR_INVALID, "rho_out is NULL");
+    if (small_on(c)) return propagate_small(c, n_steps, sel, n_sel, dev_out, host_out);
     const int N = c->N, L = c->L;
     int si = 0;          // next selection entry
     int written = 0;     // outputs delivered so far
@@ -1593,6 +1709,20 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
         c->mirror = c->mirror_ok ? 1 : 0;
     }
     c->fuse = c->n_H > 0 ? 1 : fusion_width(N, L, c->prec);
+    {
+        // the persistent path: the tensor in LDS when both buffers fit a
+        // block's LDS, else in the global buffers (still L2 resident)
+        size_t ent = 1;
+        checked_pow((size_t)N, L, &ent);
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            lds_max = 64 * 1024;
+        if (ent <= (size_t)kSmallMaxEntries) {
+            c->small = small_lds_bytes(N, c->prec, L, true) <= (size_t)lds_max ? 1
+                       : small_lds_bytes(N, c->prec, L, false) <= (size_t)lds_max ? 2 : 0;
+        }
+    }
     c->pa_h = std::move(pa);
     c->ph_h = std::move(ph);
     c->pseg_h = std::move(pseg);
@@ -1788,6 +1918,94 @@ quapi_status quapi_propagate_async(quapi_ctx *ctx, int n_steps, const int *sel, 
     return propagate_impl(ctx, n_steps, sel, n_sel, (double2 *)rho_out_dev, nullptr);
 }
 
+quapi_status quapi_persistent(const quapi_ctx *ctx, int *mode) {
+    if (!ctx || !mode) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    *mode = small_on(ctx) ? ctx->small : 0;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_propagate_batch(quapi_ctx *const *ctxs, int n_ctx, const int *n_steps, const int *rho_mode,
+                                   void *const *rho_out_dev) {
+    if (n_ctx < 0 || (n_ctx > 0 && (!ctxs || !n_steps || !rho_mode || !rho_out_dev)))
+        return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument or n_ctx < 0");
+    if (n_ctx == 0) return QUAPI_OK;
+    for (int k = 0; k < n_ctx; ++k) {
+        const quapi_ctx *c = ctxs[k];
+        if (!c) return fail(nullptr, QUAPI_ERR_INVALID, "ctxs[%d] is NULL", k);
+        for (int j = 0; j < k; ++j)
+            if (ctxs[j] == c) return fail(nullptr, QUAPI_ERR_INVALID, "ctxs[%d] repeats ctxs[%d]", k, j);
+        if (!small_on(c))
+            return fail(nullptr, QUAPI_ERR_INVALID,
+                        "ctxs[%d] is not on the persistent path (N^L above 2^14, a driven system, a pinned "
+                        "launch width or mirror mode 2)", k);
+        if (c->N != ctxs[0]->N || c->prec != ctxs[0]->prec)
+            return fail(nullptr, QUAPI_ERR_INVALID, "ctxs[%d] differs from ctxs[0] in M or dtype", k);
+        if (n_steps[k] < 0 || (long long)c->step + n_steps[k] > std::numeric_limits<int>::max())
+            return fail(nullptr, QUAPI_ERR_INVALID, "n_steps[%d] = %d is negative or overflows the step counter", k,
+                        n_steps[k]);
+        if (rho_mode[k] < 0 || rho_mode[k] > 2)
+            return fail(nullptr, QUAPI_ERR_INVALID, "rho_mode[%d] must be 0, 1 or 2", k);
+        if (rho_mode[k] != 0 && n_steps[k] > 0 && !rho_out_dev[k])
+            return fail(nullptr, QUAPI_ERR_INVALID, "rho_out_dev[%d] is NULL", k);
+    }
+    // hold every context for the call
+    int held = 0;
+    for (; held < n_ctx; ++held) {
+        int z = 0;
+        if (!ctxs[held]->busy.compare_exchange_strong(z, 1)) break;
+    }
+    struct Release {
+        quapi_ctx *const *cs;
+        int n;
+        ~Release() {
+            for (int k = 0; k < n; ++k) cs[k]->busy.store(0);
+        }
+    } release_all{ctxs, held};
+    if (held < n_ctx) return fail(nullptr, QUAPI_ERR_STATE, "ctxs[%d] is in use by another call", held);
+    quapi_ctx *c0 = ctxs[0];
+    hipStream_t bs = c0->stream;
+    // each context's earlier work (its stream, its side stream, a mirror half)
+    // comes first; the launches run on the first context's stream
+    for (int k = 0; k < n_ctx; ++k) {
+        quapi_ctx *c = ctxs[k];
+        quapi_status st = join_side(c);
+        if (st == QUAPI_OK) st = ensure_full(c);
+        if (st != QUAPI_OK) return st;
+        if (k > 0) {
+            HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
+            HIP_TRY(c0, hipStreamWaitEvent(bs, c->ev_fork, 0));
+        }
+    }
+    for (int mode = 1; mode <= 2; ++mode) {
+        SmallBatchArgs b;
+        int nb = 0, L_max = 1;
+        auto launch = [&]() -> quapi_status {
+            if (!nb) return QUAPI_OK;
+            hipError_t e = launch_small(c0->N, c0->prec, mode == 1, b, nb, L_max, bs);
+            if (e != hipSuccess) return fail(c0, QUAPI_ERR_DEVICE, "persistent batch launch: %s", hipGetErrorString(e));
+            nb = 0;
+            L_max = 1;
+            return QUAPI_OK;
+        };
+        for (int k = 0; k < n_ctx; ++k) {
+            quapi_ctx *c = ctxs[k];
+            if (c->small != mode || n_steps[k] == 0) continue;
+            b.c[nb++] = small_args(c, n_steps[k], rho_mode[k], (double2 *)rho_out_dev[k]);
+            L_max = std::max(L_max, c->L);
+            if (nb == kMaxSmallBatch)
+                if (quapi_status st = launch(); st != QUAPI_OK) return st;
+        }
+        if (quapi_status st = launch(); st != QUAPI_OK) return st;
+    }
+    for (int k = 0; k < n_ctx; ++k) small_advance(ctxs[k], n_steps[k]);
+    // later work on every other context's stream waits for the launches
+    if (n_ctx > 1) {
+        HIP_TRY(c0, hipEventRecord(c0->ev_join, bs));
+        for (int k = 1; k < n_ctx; ++k) HIP_TRY(ctxs[k], hipStreamWaitEvent(ctxs[k]->stream, c0->ev_join, 0));
+    }
+    return QUAPI_OK;
+}
+
 quapi_status quapi_step_count(const quapi_ctx *ctx, int *step) {
     if (!ctx || !step) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
     *step = ctx->step;
@@ -1803,6 +2021,7 @@ quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps) {
 quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
     if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
     const int N = ctx->N, L = ctx->L;
+    const bool pinned = steps != 0;
     if (steps == 0) steps = ctx->n_H > 0 ? 1 : fusion_width(N, L, ctx->prec);
     if (ctx->n_H > 0 && steps != 1)
         return fail(ctx, QUAPI_ERR_INVALID, "a driven context runs one step per launch");
@@ -1812,6 +2031,7 @@ quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
                     "3: N = 4, L >= 4)", steps, N, L);
     if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
     ctx->fuse = steps;
+    ctx->fuse_pinned = pinned;
     return QUAPI_OK;
 }
 
@@ -1938,9 +2158,9 @@ quapi_status quapi_get_timing(quapi_ctx *ctx, quapi_timing *out) {
             ctx->acc_ms[r.kind] += ms;
             ctx->acc_n[r.kind] += 1;
             ctx->acc_steps += r.steps;
-            if (r.kind == 0 && r.steps >= 1 && r.steps <= 3) {
-                ctx->acc_width_ms[r.steps] += ms;
-                ctx->acc_width_n[r.steps] += 1;
+            if (r.kind == 0) {
+                ctx->acc_width_ms[r.width] += ms;
+                ctx->acc_width_n[r.width] += 1;
             }
         }
         ctx->pool.push_back(r.a);

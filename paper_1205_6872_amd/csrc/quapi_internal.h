@@ -243,6 +243,32 @@ size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q);
 hipError_t launch_step2(int prec, bool with_rho, const Step2Args &a, hipStream_t st);
 hipError_t launch_step2_coef(const CoefArgs &a, hipStream_t st);
 hipError_t launch_step3(int prec, bool with_rho, const Step3Args &a, hipStream_t st);
+// Persistent propagation of small tensors (quapi_small.hip): one block per
+// context runs every step of a call.  The tensor is in a0 at entry and ends
+// in a0 after an even number of steps, a1 after an odd one.
+constexpr int kSmallBlock = 256;
+constexpr int kMaxSmallBatch = 32;                   // contexts per launch (kernel-argument size)
+// N^L of a context on the persistent path: up to here one workgroup per
+// step beats the multi-block kernels (M = 2, L = 7: 13 against 23 us per
+// step with rho; at 2^16 entries it is slower, 40 against 23 us)
+constexpr long long kSmallMaxEntries = 1LL << 14;
+struct SmallCtxArgs {
+    const double2 *bank;
+    void *a0, *a1;              // the context's two tensor buffers
+    double2 *rho_out;           // rho of the selected steps, N complex each, in step order
+    int L;
+    int step0;                  // global step reached before the launch
+    int n_steps;
+    int rho_mode;               // 0 none, 1 every step, 2 the last step of the launch
+};
+struct SmallBatchArgs {
+    SmallCtxArgs c[kMaxSmallBatch];
+};
+// LDS bytes of a block (in_lds: the two tensor buffers in LDS too).
+size_t small_lds_bytes(int N, int prec, int L, bool in_lds);
+// n_ctx blocks, block k running b.c[k]; L_max sizes the dynamic LDS.
+hipError_t launch_small(int N, int prec, bool in_lds, const SmallBatchArgs &b, int n_ctx, int L_max,
+                        hipStream_t st);
 // Fill every entry above its mirror (N = 4, 9 or 16) with the conjugate of the mirror.
 hipError_t launch_mirror_complete(int N, int prec, void *a, long long entries, hipStream_t st);
 hipError_t launch_step3_coef(const Coef3Args &a, hipStream_t st);

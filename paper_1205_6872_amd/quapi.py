@@ -34,6 +34,7 @@ EXPORTED_SYMBOLS = (
     "quapi_get_setup", "quapi_read_tensor", "quapi_restore",
     "quapi_tensor_size", "quapi_set_timing", "quapi_get_timing", "quapi_destroy",
     "quapi_last_error", "quapi_copy_bandwidth", "quapi_propagate_static",
+    "quapi_persistent", "quapi_propagate_batch",
 )
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -90,6 +91,8 @@ def load_library() -> ctypes.CDLL:
     lib.quapi_destroy.argtypes = [vp]
     lib.quapi_copy_bandwidth.argtypes = [vp, vp, sz, sz, ctypes.c_int, vp]
     lib.quapi_propagate_static.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ip, ctypes.c_int, vp, vp]
+    lib.quapi_persistent.argtypes = [vp, ip]
+    lib.quapi_propagate_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ip, ip, ctypes.POINTER(vp)]
     lib.quapi_last_error.argtypes = [vp]
     lib.quapi_last_error.restype = ctypes.c_char_p
     for name in EXPORTED_SYMBOLS:
@@ -246,6 +249,12 @@ class Context:
         h = self._live()
         _check(lib().quapi_set_mirror(h, int(enable)), h)
 
+    def persistent(self) -> int:
+        """0: multi-block kernels; 1: persistent path, tensor in LDS; 2: persistent, tensor in HBM."""
+        v = ctypes.c_int(0)
+        _check(lib().quapi_persistent(self._live(), ctypes.byref(v)))
+        return int(v.value)
+
     def step_count(self) -> int:
         v = ctypes.c_int(0)
         _check(lib().quapi_step_count(self._live(), ctypes.byref(v)))
@@ -334,6 +343,20 @@ def propagate_static(p: _ParamsHolder, n_steps: int, sel: Optional[Sequence[int]
     _check(lib().quapi_propagate_static(ctypes.byref(p.p), int(n_steps), psel, n_sel,
                                         ctypes.c_void_p(rho_out_dev) if rho_out_dev else None,
                                         ctypes.c_void_p(stream) if stream else None))
+
+
+def propagate_batch(ctxs: Sequence["Context"], n_steps: Sequence[int], rho_mode: Sequence[int],
+                    rho_out_dev: Sequence[int]) -> None:
+    """quapi_propagate_batch: advance persistent-path contexts (same M, dtype)
+    together; rho_mode 0 none, 1 every step, 2 the last step; enqueued on the
+    first context's stream."""
+    n = len(ctxs)
+    hs = (ctypes.c_void_p * max(n, 1))(*[c._live() for c in ctxs])
+    ns = np.ascontiguousarray(np.asarray(list(n_steps) or [0], dtype=np.int32))
+    ms = np.ascontiguousarray(np.asarray(list(rho_mode) or [0], dtype=np.int32))
+    outs = (ctypes.c_void_p * max(n, 1))(*[ctypes.c_void_p(int(p)) if p else None for p in rho_out_dev])
+    ip = ctypes.POINTER(ctypes.c_int)
+    _check(lib().quapi_propagate_batch(hs, n, ns.ctypes.data_as(ip), ms.ctypes.data_as(ip), outs))
 
 
 def create(p: _ParamsHolder, stream: Optional[int] = None, workspace: Optional[int] = None,

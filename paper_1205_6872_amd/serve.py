@@ -11,11 +11,17 @@ time.  The server:
 * keeps every admitted request's tensor resident in its own workspace (a
   torch uint8 tensor) and runs it on its own HIP stream, so the work of
   different requests overlaps on the device;
-* enqueues each request's steps in chunks through ``propagate_async``,
-  round-robin over the active requests, at most two chunks in flight per
-  request.  A chunk is sized to about ``chunk_ms`` of estimated device time,
-  so the streams that share a hardware queue interleave finely and a long
-  request's steps do not hold a short one's for long;
+* batches the requests small enough for the library's persistent path
+  (N^L <= 2^14: one workgroup per request runs all of its steps): every
+  loop iteration, the newly admitted ones of the same M and precision go to
+  the GPU together in one ``propagate_batch`` call, which advances each of
+  them through all of its steps in one launch;
+* enqueues every other request's steps in chunks through
+  ``propagate_async``, round-robin over the active requests, at most two
+  chunks in flight per request.  A chunk is sized to about ``chunk_ms`` of
+  estimated device time, so the streams that share a hardware queue
+  interleave finely and a long request's steps do not hold a short one's
+  for long;
 * records arrival, admission and completion times and reports p50/p99
   latency (arrival -> rho on the host) and aggregate throughput.
 
@@ -97,6 +103,7 @@ class _Active:
     admit_s: float
     fuse: int = 1
     final_only: bool = False
+    persistent: bool = False       # batched through propagate_batch
     enqueued: int = 0
     events: deque = field(default_factory=deque)
 
@@ -124,6 +131,8 @@ class Server:
             free, _ = torch.cuda.mem_get_info(device)
             hbm_budget = int(free * 0.85)
         self.budget = int(hbm_budget)
+        self.batched = 0               # requests run through propagate_batch
+        self.batch_calls = 0
 
     def _admit(self, w, index: int, slot: int, now: float) -> _Active:
         torch = self.torch
@@ -135,7 +144,33 @@ class Server:
         rho_dev = torch.empty((rows, w.N, 2), dtype=torch.float64, device=self.device)
         ctx.propagate_async(0, [0], rho_dev.data_ptr())          # rho(t_0)
         return _Active(w=w, index=index, ctx=ctx, stream=stream, rho_dev=rho_dev, slot=slot,
-                       fp=Q.footprint(p), admit_s=now, fuse=ctx.fused_steps(), final_only=final_only)
+                       fp=Q.footprint(p), admit_s=now, fuse=ctx.fused_steps(), final_only=final_only,
+                       persistent=ctx.persistent() != 0)
+
+    def _launch_batches(self, active) -> int:
+        """One propagate_batch call per (M, precision) over the admitted
+        persistent-path requests that have not started: each runs all of its
+        steps.  Returns the number of requests launched."""
+        torch = self.torch
+        groups: dict = {}
+        for a in active.values():
+            if a.persistent and a.enqueued == 0 and a.w.n_steps > 0:
+                groups.setdefault((a.w.M, a.w.dtype), []).append(a)
+        launched = 0
+        for grp in groups.values():
+            n = [a.w.n_steps for a in grp]
+            modes = [2 if a.final_only else 1 for a in grp]
+            outs = [a.rho_dev.data_ptr() + a.w.N * 16 for a in grp]
+            Q.propagate_batch([a.ctx for a in grp], n, modes, outs)
+            ev = torch.cuda.Event()
+            ev.record(grp[0].stream)                # the batch runs on its first request's stream
+            for a in grp:
+                a.enqueued = a.w.n_steps
+                a.events.append(ev)
+            self.batch_calls += 1
+            launched += len(grp)
+        self.batched += launched
+        return launched
 
     def run(self, requests, realtime: bool = True) -> list[RequestResult]:
         """Serve the requests (each with meta['arrival_s']); returns results in index order."""
@@ -182,11 +217,14 @@ class Server:
                 used += a.fp
                 active[slot] = a
                 progressed = True
-            # enqueue the next chunk of every active request (two chunks in flight at most)
+            # the newly admitted small requests, batched
+            if self._launch_batches(active):
+                progressed = True
+            # enqueue the next chunk of every other active request (two chunks in flight at most)
             for a in active.values():
                 while a.events and a.events[0].query():
                     a.events.popleft()
-                if a.enqueued < a.w.n_steps and len(a.events) < 2:
+                if not a.persistent and a.enqueued < a.w.n_steps and len(a.events) < 2:
                     chunk = self.chunk
                     if self.chunk_ms is not None:
                         chunk = int(min(256, max(2, self.chunk_ms * 1e-3 / est_step_s(a.w))))

@@ -119,3 +119,44 @@ def test_mirror_sized_requests_same_alone_and_in_the_mix():
     o = orun.oracle_run(reqs[3], reqs[3].n_steps)
     err = np.abs(res[3].rho - o).max() / np.abs(o).max()
     assert err <= 1e-12, err
+
+
+def test_batched_small_requests_same_alone_and_in_the_mix():
+    """Requests on the persistent path (N^L <= 2^14) that arrive together are
+    run in shared launches (one workgroup each), mixed with larger requests
+    that run in chunks; every result equals the request run alone, bit for
+    bit, and one is checked against the oracle."""
+    from oracle import run as orun
+    from paper_1205_6872_amd.serve import Server
+    rng = np.random.default_rng(47)
+    base = W.spin_boson_l7()
+    reqs = []
+    for k in range(20):
+        M = [2, 2, 3][k % 3]
+        L = int(rng.integers(2, 8)) if M == 2 else int(rng.integers(2, 5))
+        w0 = base if M == 2 else W.three_site_l8()
+        w = w0.with_(name=f"small_{k}", L=L, H=W.random_hermitian(rng, M), xi=float(rng.uniform(0.05, 0.4)),
+                     n_steps=int(rng.integers(5, 120)), dtype=["c128", "c64"][k % 2])
+        w.meta = {"arrival_s": 0.0, "final_only": k % 5 == 0}
+        reqs.append(w)
+    big = base.with_(name="big_l10", L=10, n_steps=30)
+    big.meta = {"arrival_s": 0.0}
+    reqs.append(big)
+    for w in reqs[:-1]:
+        with Q.create(Q.params_from(w)) as ctx:
+            assert ctx.persistent() != 0, (w.M, w.L, w.dtype)
+    srv = Server(max_active=24, chunk_steps=8)
+    res = srv.run(reqs, realtime=False)
+    assert srv.batched == 20 and srv.batch_calls < srv.batched, (srv.batched, srv.batch_calls)
+    for w, r in zip(reqs, res):
+        with Q.create(Q.params_from(w)) as ctx:
+            if w.meta.get("final_only"):
+                alone = ctx.propagate(w.n_steps, sel=[0, w.n_steps])
+            else:
+                alone = ctx.propagate(w.n_steps, sel=list(range(w.n_steps + 1)))
+        assert np.array_equal(r.rho, alone), (w.name, np.abs(r.rho - alone).max())
+    w = reqs[2]
+    o = orun.oracle_run(w, w.n_steps)
+    got = res[2].rho if not w.meta.get("final_only") else None
+    if got is not None:
+        assert np.abs(got - o).max() / np.abs(o).max() <= (1e-12 if w.dtype == "c128" else 1e-5)
