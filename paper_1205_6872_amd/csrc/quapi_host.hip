@@ -2029,7 +2029,8 @@ quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
     if (!ok)
         return fail(ctx, QUAPI_ERR_INVALID, "%d fused steps unavailable at N = %d, L = %d (1 always; 2: N = 4, L >= 3; "
                     "3: N = 4, L >= 4)", steps, N, L);
-    if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
+    BusyGuard guard(ctx);
+    if (!guard.ok) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
     ctx->fuse = steps;
     ctx->fuse_pinned = pinned;
     return QUAPI_OK;
@@ -2045,8 +2046,9 @@ quapi_status quapi_set_mirror(quapi_ctx *ctx, int enable) {
     if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
     if (enable && !ctx->mirror_ok)
         return fail(ctx, QUAPI_ERR_INVALID, "mirror mode needs M = 2, 3 or 4, L >= 2 and an exactly Hermitian rho0");
-    if (ctx->busy.load() != 0) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
     if (enable < 0 || enable > 2) return fail(ctx, QUAPI_ERR_INVALID, "enable must be 0, 1 or 2");
+    BusyGuard guard(ctx);       // the graphs destroyed below must not be replayed meanwhile
+    if (!guard.ok) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
     if (enable == ctx->mirror) return QUAPI_OK;
     // the captured graphs hold the launches of the old mode
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -2096,14 +2098,14 @@ quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries) {
 quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count, double *out) {
     if (!ctx || (!out && count)) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
     quapi_ctx *c = const_cast<quapi_ctx *>(ctx);
+    BusyGuard g(c);                        // the step count and, in the completion pass, the tensor
+    if (!g.ok) return fail(c, QUAPI_ERR_STATE, "context in use by another call");
     size_t entries = 0;
     quapi_tensor_size(ctx, &entries);
     if (first > entries || count > entries - first)
         return fail(c, QUAPI_ERR_INVALID, "range [%zu, %zu) exceeds the tensor of %zu entries", first,
                     first + count, entries);
     if (!count) return QUAPI_OK;
-    BusyGuard g(c);                        // the completion pass changes the tensor
-    if (!g.ok) return fail(c, QUAPI_ERR_STATE, "context in use by another call");
     if (quapi_status fs = ensure_full(c); fs != QUAPI_OK) return fs;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->prec == kPrecC128) {
