@@ -179,26 +179,16 @@ def roofline(r, traffic):
             "other_launches": r["other_launches"]}
 
 
-# The dominant kernel of each tier at M = 2, L = 15 and the sources it is built from.
+# The dominant kernel of each tier at M = 2, L = 15 (its sources' hash ties
+# the committed counter summary to the code: paper_1205_6872_amd.profsummary).
 TIER_KERNEL = {"c128": "step3", "c64": "step3", "c64f64": "step2"}
-KERNEL_SOURCES = {"step2": ("quapi_step2.hip", "quapi_device.h", "quapi_internal.h"),
-                  "step3": ("quapi_step3.hip", "quapi_device.h", "quapi_internal.h")}
-
-
-def kernel_source_hash(kernel: str) -> str:
-    """sha256 over the sources the fused kernel is compiled from."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(ROOT, "paper_1205_6872_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
 
 
 def measured_traffic(tier: str):
     """HBM bytes per launch of the tier's dominant kernel from the committed
     rocprofv3 counter summary, or None when the kernel's sources changed since
     the counters were taken."""
+    from paper_1205_6872_amd.profsummary import kernel_source_hash
     kernel = TIER_KERNEL[tier]
     path = os.path.join(ROOT, "profiles", f"{kernel}_kernel_traffic_spin_boson_l15.json")
     if not os.path.exists(path):
@@ -329,6 +319,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=None, help="timed full-window steps")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tiers", default="c128,c64,c64f64")
+    ap.add_argument("--total-steps", type=int, default=None,
+                    help="steps each tier runs in all (default: the workload's 1000); a shorter run for profiling")
     ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512, help="0 skips the serving run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -349,7 +341,7 @@ def main() -> int:
         return 2
     torch.cuda.set_device(0)
     w = W.spin_boson_l15("c128")
-    total = w.n_steps                      # every tier runs the whole 1000-step workload
+    total = args.total_steps or w.n_steps  # every tier runs the whole 1000-step workload
     tiers = [t for t in args.tiers.split(",") if t]
     res = {}
     for t in tiers:
