@@ -14,7 +14,7 @@ import numpy as np
 
 from . import bath, eta as eta_mod, system, tensor
 
-__all__ = ["OracleInputs", "inputs_from", "lineshape_grid", "setup", "oracle_run"]
+__all__ = ["OracleInputs", "inputs_from", "lineshape_grid", "setup", "oracle_run", "oracle_run_filtered"]
 
 
 @dataclass
@@ -80,3 +80,13 @@ def oracle_run(inp, n_steps: int, threads: int = 0, return_step_seconds: bool = 
     _, ec, _, K = setup(inp)
     return tensor.tensor_rho(inp.s, K, inp.rho0, ec, inp.L, n_steps, threads=threads,
                              return_step_seconds=return_step_seconds)
+
+
+def oracle_run_filtered(inp, n_steps: int, theta: float, threads: int = 0):
+    """rho(t_k), k = 0..n_steps, with path filtering at threshold theta: every
+    tensor entry whose magnitude is not above theta is dropped as soon as it
+    is formed.  Returns (rho, kept entries after each step, margin)."""
+    if not isinstance(inp, OracleInputs):
+        inp = inputs_from(inp)
+    _, ec, _, K = setup(inp)
+    return tensor.tensor_rho_filtered(inp.s, K, inp.rho0, ec, inp.L, n_steps, theta, threads=threads)

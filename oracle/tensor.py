@@ -15,7 +15,7 @@ import numpy as np
 
 from .eta import EtaClasses
 
-__all__ = ["build_oracle", "tensor_rho", "ORACLE_LIB"]
+__all__ = ["build_oracle", "tensor_rho", "tensor_rho_filtered", "ORACLE_LIB"]
 
 _HERE = Path(__file__).resolve().parent
 ORACLE_SRC = _HERE / "tensor_oracle.c"
@@ -43,6 +43,10 @@ def _load():
         lib.oracle_propagate.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
                                          dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
         lib.oracle_propagate.restype = ctypes.c_int
+        lib.oracle_propagate_filtered.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
+                                                  dp, dp, dp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_double,
+                                                  ctypes.POINTER(ctypes.c_longlong), dp]
+        lib.oracle_propagate_filtered.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -81,3 +85,32 @@ def tensor_rho(s, K: np.ndarray, rho0: np.ndarray, eta: EtaClasses, L: int, n_st
     if return_step_seconds:
         return rho, secs[:n_steps]
     return rho
+
+
+def tensor_rho_filtered(s, K: np.ndarray, rho0: np.ndarray, eta: EtaClasses, L: int, n_steps: int, theta: float,
+                        threads: int = 0):
+    """The tensor recursion with path filtering: every tensor entry whose
+    magnitude is not above theta is dropped as soon as it is formed (the
+    initial tensor and the tensor after every step).
+
+    Returns (rho, kept, margin): rho(t_k) for k = 0..n_steps as (n_steps+1, M, M);
+    kept[n] the entries left after step n; margin the smallest | |A_x| - theta | / theta
+    over all entries formed (how near any decision came to the threshold)."""
+    lib = _load()
+    s = np.ascontiguousarray(np.asarray(s, dtype=np.float64))
+    M = len(s)
+    N = M * M
+    Ks = np.asarray(K).reshape(-1, N, N)
+    Kri = _ri(Ks)
+    r0 = _ri(np.asarray(rho0).reshape(N))
+    arrs = [_ri([eta.self_interior]), _ri([eta.self_end]), _ri(eta.lag[:L + 1]),
+            _ri(eta.init[:L + 1]), _ri(eta.fin[:L + 1]), _ri(eta.fin_init[:L + 1])]
+    out = np.zeros(2 * N * (n_steps + 1), dtype=np.float64)
+    kept = np.zeros(n_steps + 1, dtype=np.int64)
+    margin = np.zeros(1, dtype=np.float64)
+    rc = lib.oracle_propagate_filtered(M, _ptr(s), _ptr(Kri), len(Ks), _ptr(r0), L, n_steps,
+                                       *[_ptr(a) for a in arrs], _ptr(out), int(threads), float(theta),
+                                       kept.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), _ptr(margin))
+    if rc != 0:
+        raise RuntimeError(f"oracle_propagate_filtered failed with code {rc}")
+    return out.view(np.complex128).reshape(n_steps + 1, M, M), kept, float(margin[0])

@@ -35,6 +35,8 @@
  * matrices of N x N, row-major (K[o' * N + o]), and step n uses matrix
  * min(n, n_K) - 1; rho0 and every output rho are N complex values.
  *
+ * Path filtering (oracle_propagate_filtered): see propagate_impl.
+ *
  * Reductions: rho sums are accumulated with Neumaier compensation over fixed
  * chunks of output entries and the chunk partials are combined in order, so
  * the result does not depend on the number of threads.
@@ -88,6 +90,38 @@ static double now_s(void) {
 }
 
 /*
+ * Path filtering (Sim's on-the-fly filtering, as read here): with theta >= 0,
+ * every entry of the augmented tensor whose magnitude is not above theta is
+ * dropped (set to zero) as soon as it is formed -- the initial tensor and the
+ * tensor after every step -- so the paths it stands for take no further part
+ * in the sum.  theta < 0 keeps everything (the plain recursion).  kept
+ * (optional): the entries left after step n at index n (n = 0 .. n_steps);
+ * margin (optional): the smallest | |A_x| - theta | / theta over every entry
+ * formed, i.e. how close any decision came to the threshold.
+ */
+static int propagate_impl(int M, const double *s, const double *K_ri, int n_K, const double *rho0_ri,
+                          int L, int n_steps,
+                          const double *eta_self_int, const double *eta_self_end,
+                          const double *eta_lag, const double *eta_init,
+                          const double *eta_fin, const double *eta_fin_init,
+                          double *rho_out, double *step_seconds, int n_threads,
+                          double theta, long long *kept, double *margin);
+
+static long long filter_entries(cplx *A, size_t count, double theta, double *margin) {
+    long long k = 0;
+    for (size_t x = 0; x < count; ++x) {
+        const double a = cabs(A[x]);
+        if (margin && theta > 0.0) {
+            const double d = fabs(a - theta) / theta;
+            if (d < *margin) *margin = d;
+        }
+        if (a <= theta) A[x] = 0;
+        else ++k;
+    }
+    return k;
+}
+
+/*
  * Returns 0 on success, 1 on bad arguments, 2 on allocation failure.
  * rho_out: (n_steps + 1) * N complex (interleaved); rho_out[0] = rho0.
  * step_seconds (optional, may be NULL): wall time of each step n = 1..n_steps
@@ -99,6 +133,29 @@ int oracle_propagate(int M, const double *s, const double *K_ri, int n_K, const 
                      const double *eta_lag, const double *eta_init,
                      const double *eta_fin, const double *eta_fin_init,
                      double *rho_out, double *step_seconds, int n_threads) {
+    return propagate_impl(M, s, K_ri, n_K, rho0_ri, L, n_steps, eta_self_int, eta_self_end, eta_lag, eta_init,
+                          eta_fin, eta_fin_init, rho_out, step_seconds, n_threads, -1.0, NULL, NULL);
+}
+
+/* The same recursion with the path filtering above (theta >= 0). */
+int oracle_propagate_filtered(int M, const double *s, const double *K_ri, int n_K, const double *rho0_ri,
+                              int L, int n_steps,
+                              const double *eta_self_int, const double *eta_self_end,
+                              const double *eta_lag, const double *eta_init,
+                              const double *eta_fin, const double *eta_fin_init,
+                              double *rho_out, int n_threads, double theta, long long *kept, double *margin) {
+    if (!(theta >= 0.0)) return 1;
+    return propagate_impl(M, s, K_ri, n_K, rho0_ri, L, n_steps, eta_self_int, eta_self_end, eta_lag, eta_init,
+                          eta_fin, eta_fin_init, rho_out, NULL, n_threads, theta, kept, margin);
+}
+
+static int propagate_impl(int M, const double *s, const double *K_ri, int n_K, const double *rho0_ri,
+                          int L, int n_steps,
+                          const double *eta_self_int, const double *eta_self_end,
+                          const double *eta_lag, const double *eta_init,
+                          const double *eta_fin, const double *eta_fin_init,
+                          double *rho_out, double *step_seconds, int n_threads,
+                          double theta, long long *kept, double *margin) {
     if (M < 1 || M > 8 || L < 1 || n_steps < 0 || n_K < 1) return 1;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -142,6 +199,11 @@ int oracle_propagate(int M, const double *s, const double *K_ri, int n_K, const 
         rho_out[2 * o] = rho0_ri[2 * o];
         rho_out[2 * o + 1] = rho0_ri[2 * o + 1];
         A[o] = ld(rho0_ri, o) * self_end[o];
+    }
+    if (margin) *margin = INFINITY;
+    if (theta >= 0.0) {
+        const long long k0 = filter_entries(A, (size_t)N, theta, margin);
+        if (kept) kept[0] = k0;
     }
 
     for (int n = 1; n <= n_steps; ++n) {
@@ -214,7 +276,10 @@ int oracle_propagate(int M, const double *s, const double *K_ri, int n_K, const 
             rho_out[(size_t)2 * N * n + 2 * o] = creal(v);
             rho_out[(size_t)2 * N * n + 2 * o + 1] = cimag(v);
         }
-        (void)out_count;
+        if (theta >= 0.0) {
+            const long long k = filter_entries(B, out_count, theta, margin);
+            if (kept) kept[n] = k;
+        }
         cplx *tmp = A; A = B; B = tmp;
         if (step_seconds) step_seconds[n - 1] = now_s() - t0;
     }
