@@ -165,6 +165,45 @@ quapi_status quapi_propagate(quapi_ctx *ctx, int n_steps, const int *sel, int n_
 quapi_status quapi_propagate_async(quapi_ctx *ctx, int n_steps, const int *sel, int n_sel,
                                    void *rho_out_dev);
 
+/* Path filtering: Sim's on-the-fly filtering of the tensor propagator, which
+ * the paper names in its Introduction as the way to cut the memory of the
+ * augmented tensor.  Read here as: every entry of the tensor whose magnitude
+ * is not above theta is dropped as soon as it is formed (the initial tensor
+ * and the tensor after every step), so the paths it stands for take no
+ * further part; theta = 0 drops exact zeros only and gives the unfiltered
+ * result.  The kept entries are stored as (flat index, value) pairs sorted
+ * by index, in two buffers of `capacity` entries, so the memory follows the
+ * kept count instead of N^L, and N^dk_max may reach 2^62.
+ *
+ * quapi_create_filtered: as quapi_create (its own device allocation; hip_stream
+ *   borrowed or NULL), with theta >= 0 finite and 1 <= capacity <=
+ *   (2^32 - 1) / N.  The context works with quapi_propagate,
+ *   quapi_propagate_async, quapi_step_count, quapi_get_setup, timing and
+ *   quapi_destroy; every step runs as its own sequence of launches (no fused
+ *   steps, mirror mode, persistent path or graphs), and quapi_read_tensor,
+ *   quapi_restore and quapi_tensor_size refuse it (INVALID).
+ *   When a step keeps more than `capacity` entries, the entries beyond it are
+ *   lost, a sticky overflow flag is set on the device, and the results from
+ *   that step on are wrong: quapi_propagate then returns QUAPI_ERR_NOMEM, and
+ *   after quapi_propagate_async the caller reads the flag with
+ *   quapi_filter_stats.  Deterministic (integer scans, fixed-order sums).
+ * quapi_filtered_footprint: device bytes of such a context (about
+ *   capacity * (2 * (8 + sizeof(complex)) + 4 N + 4) plus the tables); needs
+ *   no GPU.
+ * quapi_filter_stats: waits for the context's stream, then gives the entries
+ *   kept after the last step and the overflow flag (0 or 1).
+ * quapi_filter_read: waits for the stream, then copies kept entries
+ *   [first, first + count) in index order: keys (flat index, oldest point
+ *   fastest, as quapi_read_tensor's positions) and vals (count complex128,
+ *   interleaved); INVALID when the range exceeds the kept entries.
+ * All return INVALID for NULL arguments and for contexts that are not
+ * filtered (stats, read); STATE while another call runs on the context. */
+quapi_status quapi_filtered_footprint(const quapi_params *p, size_t capacity, size_t *device_bytes);
+quapi_status quapi_create_filtered(const quapi_params *p, double theta, size_t capacity, void *hip_stream,
+                                   quapi_ctx **out);
+quapi_status quapi_filter_stats(quapi_ctx *ctx, long long *entries, int *overflow);
+quapi_status quapi_filter_read(quapi_ctx *ctx, size_t first, size_t count, long long *keys, double *vals);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
  * propagation -- the setup of quapi_create, n_steps steps from step 0 and

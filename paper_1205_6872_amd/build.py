@@ -18,7 +18,7 @@ OBJ_DIR = LIB_DIR / "obj"
 LIB = LIB_DIR / "libquapi.so"
 SOURCES = [CSRC / "quapi_kernels.hip", CSRC / "quapi_step2.hip", CSRC / "quapi_step3.hip",
            CSRC / "quapi_host.hip", CSRC / "quapi_copy.hip",
-           CSRC / "quapi_small.hip"]
+           CSRC / "quapi_small.hip", CSRC / "quapi_filter.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -225,7 +225,12 @@ std::string hermitian_error(const double *H, int M, const char *name) {
     return "";
 }
 
-std::string validate(const quapi_params *p) {
+// Largest N^dk_max (as a power of two) of a dense context, and of a filtered
+// one (its keys are 64-bit flat indices).
+constexpr int kDenseMaxLog2 = 40;
+constexpr int kFilterMaxLog2 = 62;
+
+std::string validate(const quapi_params *p, int max_log2 = kDenseMaxLog2) {
     char buf[256];
     if (!p) return "params is NULL";
     if (p->M < 1 || p->M > kMaxM) {
@@ -274,7 +279,7 @@ std::string validate(const quapi_params *p) {
         return "bath.kind must be QUAPI_BATH_OHMIC or QUAPI_BATH_TABLE";
     }
     size_t entries;
-    if (!checked_pow((size_t)M * M, p->dk_max, &entries) || entries > (size_t)1 << 40)
+    if (!checked_pow((size_t)M * M, p->dk_max, &entries) || entries > (size_t)1 << max_log2)
         return "N^dk_max is too large";
     return "";
 }
@@ -285,6 +290,10 @@ struct Layout {
     size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_Ht, off_Ut, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
     size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_blk2, off_blk1, off_pairs, off_sink;
+    // filtered contexts: keys and values of the two tensors, flags, segment
+    // starts, scan partials, counters, rho partials, factor-level tables
+    size_t off_fkeys[2], off_fvals[2], off_fflags, off_fseg, off_fsums, off_fctr, off_fpart, off_fplan;
+    size_t fplan_entries;            // entries of one factor-level table set
     size_t total;
     int n_panels, n_tables, partial_blocks;
     int n_canon3, n_diag3, parts3, span3;   // mirror mode of the three-step kernel (high-digit blocks)
@@ -319,18 +328,22 @@ bool single_mirror_ok(int N, int L, const DigitSplit &main_split) {
     return L >= 2 && (N == 4 || N == 9 || (N == 16 && main_split.R == 16));
 }
 
-Layout make_layout(const quapi_params &p, int n_panels) {
+// filter_cap > 0: a filtered context holding up to filter_cap kept entries
+// (no dense tensors, no dense-step plans, mirror or fused-step buffers).
+Layout make_layout(const quapi_params &p, int n_panels, size_t filter_cap = 0) {
     Layout l{};
     const int M = p.M, N = M * M, L = p.dk_max;
+    const bool filtered = filter_cap > 0;
     size_t entries = 1;
     checked_pow((size_t)N, L, &entries);
     const size_t cs = p.dtype == QUAPI_C128 ? 16 : 8;
     l.n_panels = n_panels;
     l.n_tables = BankLayout{L}.count();
-    l.partial_blocks = max_grid(N, L);
-    l.main_split = split_digits(N, L - 1);
-    l.split2 = fused_ok(N, L) ? split_digits2(L - 2) : DigitSplit{0, 0, 1, 1, 1};
-    const bool triple = triple_ok(N, L);
+    const DigitSplit none{0, 0, 1, 1, 1};
+    l.partial_blocks = filtered ? 1 : max_grid(N, L);
+    l.main_split = filtered ? none : split_digits(N, L - 1);
+    l.split2 = !filtered && fused_ok(N, L) ? split_digits2(L - 2) : none;
+    const bool triple = !filtered && triple_ok(N, L);
     l.split3 = triple ? split_digits2(L - 3) : DigitSplit{0, 0, 1, 1, 1};
     if (triple) {
         // mirror mode: blocks whose high digits are below their mirror, and
@@ -352,7 +365,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
         l.span3 = ((passes + l.parts3 - 1) / l.parts3) * rows_per_pass;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon3 + l.n_diag3 * (l.parts3 + 1));
     }
-    if (fused_ok(N, L)) {
+    if (!filtered && fused_ok(N, L)) {
         // the two-step kernel: the same partition over its block digits
         const DigitSplit &s2 = l.split2;
         for (int h = 0; h < s2.grid; ++h) {
@@ -366,7 +379,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
         l.span2 = ((passes + l.parts2 - 1) / l.parts2) * rows_per_pass;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon2 + l.n_diag2 * (l.parts2 + 1));
     }
-    if (single_mirror_ok(N, L, l.main_split)) {
+    if (!filtered && single_mirror_ok(N, L, l.main_split)) {
         // the N = 9 step and the N = 16 MFMA step: the same partition over
         // their block digits; a block sweeps its rows with its 4 waves (MFMA)
         // or its kBlock / R thread columns
@@ -382,7 +395,7 @@ Layout make_layout(const quapi_params &p, int n_panels) {
         l.span1 = ((passes + l.parts1 - 1) / l.parts1) * rows_per_pass;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon1 + l.n_diag1 * (l.parts1 + 1));
     }
-    l.a_bytes = entries * cs;
+    l.a_bytes = filtered ? 0 : entries * cs;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -415,11 +428,12 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_sink = take(sizeof(RhoSink));
     // six FP64 factor tables of the full-window split: [N][R], [N][Q], [N][grid], x2 classes
     const DigitSplit &ms = l.main_split;
-    l.off_plan = take((size_t)2 * N * (ms.R + ms.Q + ms.grid) * 16);
+    l.off_plan = take(filtered ? 0 : (size_t)2 * N * (ms.R + ms.Q + ms.grid) * 16);
     // four table sets (interior / final, steps n and n+1) of the fused split
     const DigitSplit &s2 = l.split2;
-    l.off_plan2 = take(fused_ok(N, L) ? (size_t)4 * N * (s2.R + s2.Q + s2.grid) * 16 : 0);
-    l.off_coef = take(fused_ok(N, L) ? (size_t)kCoefCount * 16 : 0);
+    const bool fused = !filtered && fused_ok(N, L);
+    l.off_plan2 = take(fused ? (size_t)4 * N * (s2.R + s2.Q + s2.grid) * 16 : 0);
+    l.off_coef = take(fused ? (size_t)kCoefCount * 16 : 0);
     // six table sets (interior / final, steps n, n+1, n+2) of the three-step split
     const DigitSplit &s3 = l.split3;
     l.off_plan3 = take(triple ? (size_t)6 * N * (s3.R + s3.Q + s3.grid) * 16 : 0);
@@ -427,6 +441,18 @@ Layout make_layout(const quapi_params &p, int n_panels) {
     l.off_blk3 = take(triple ? (size_t)(l.n_canon3 + l.n_diag3) * sizeof(int) : 0);
     l.off_blk2 = take((size_t)(l.n_canon2 + l.n_diag2) * sizeof(int));
     l.off_blk1 = take((size_t)(l.n_canon1 + l.n_diag1) * sizeof(int));
+    const size_t fc = filtered ? filter_cap : 0;
+    for (int b = 0; b < 2; ++b) {
+        l.off_fkeys[b] = take(fc * 8);
+        l.off_fvals[b] = take(fc * cs);
+    }
+    l.off_fflags = take(fc * N * 4);                 // a step's outputs: segments * N <= capacity * N
+    l.off_fseg = take(filtered ? (fc + 1) * 4 : 0);
+    l.off_fsums = take(filtered ? (size_t)kFilterScanBlocks * 4 : 0);
+    l.off_fctr = take(filtered ? 8 * 8 : 0);          // counts of both buffers, scan total, segments, flags, overflow
+    l.off_fpart = take(filtered ? (size_t)kFilterStepBlocks * N * 16 : 0);
+    l.fplan_entries = filtered ? std::max<size_t>(1, filter_plan_entries(N, L - 1)) : 0;
+    l.off_fplan = take(l.fplan_entries * 2 * 16);
     l.total = off;
     return l;
 }
@@ -503,6 +529,21 @@ struct quapi_ctx {
     std::vector<int> blk1_h;
     double2 *plan3 = nullptr;
     void *coef3 = nullptr;
+    // Filtered propagation (quapi_create_filtered): the kept entries as sorted
+    // (key, value) pairs in two buffers of fcap entries, fkeys[cur] / fvals[cur]
+    // the current tensor; fctr[0], fctr[1] their entry counts, fctr[2] the
+    // last scan total, fctr[3] segments, fctr[4] flags, fctr[5] (as int) the
+    // sticky overflow flag.
+    bool filtered = false;
+    double theta = 0.0;
+    size_t fcap = 0;
+    unsigned long long *fkeys[2] = {nullptr, nullptr};
+    void *fvals[2] = {nullptr, nullptr};
+    unsigned *fflags = nullptr, *fseg = nullptr, *fsums = nullptr;
+    unsigned long long *fctr = nullptr;
+    double2 *fpart = nullptr, *fplan = nullptr;
+    size_t fplan_entries = 0;
+    int fplan_for = -1;           // the step set fplan holds: 0 the full window, n growth step n
     std::vector<double> rho0_h;
     // host copies of uploaded inputs (kept alive until the uploads complete)
     std::vector<double> s_h, H_h, pa_h, ph_h, tw_h, tJ_h, glx_h, glw_h;
@@ -574,20 +615,13 @@ struct StepPlan {
     bool grow;
 };
 
-StepPlan plan_step(const quapi_ctx *c, int n) {
-    const int N = c->N, L = c->L;
+// The bank tables of global step n: a.n_digits, a.tab / a.tabf per digit of
+// m, and the oldest-point (full window) or self (growth) tables.
+void step_tables(int L, int n, StepArgs &a) {
     const BankLayout B{L};
-    StepPlan sp{};
-    StepArgs &a = sp.args;
-    sp.grow = n < L;
-    a.n_digits = sp.grow ? n : L - 1;
-    a.m_count = ipow_ll(N, a.n_digits);
-    sp.split = split_digits(N, a.n_digits);
-    a.d_lo = sp.split.d_lo;
-    a.d_mid = sp.split.d_mid;
-    a.R = sp.split.R;
-    a.Q = sp.split.Q;
-    if (sp.grow) {
+    const bool grow = n < L;
+    a.n_digits = grow ? n : L - 1;
+    if (grow) {
         // digits are points 0 .. n-1; point 0 couples through the initial-point classes
         for (int j = 0; j < n; ++j) {
             if (j == 0) {
@@ -611,6 +645,20 @@ StepPlan plan_step(const quapi_ctx *c, int n) {
         a.old_tab = n == L ? B.old_first() : B.old_main();
         a.oldf_tab = n == L ? B.oldf_first() : B.oldf_main();
     }
+}
+
+StepPlan plan_step(const quapi_ctx *c, int n) {
+    const int N = c->N, L = c->L;
+    StepPlan sp{};
+    StepArgs &a = sp.args;
+    sp.grow = n < L;
+    step_tables(L, n, a);
+    a.m_count = ipow_ll(N, a.n_digits);
+    sp.split = split_digits(N, a.n_digits);
+    a.d_lo = sp.split.d_lo;
+    a.d_mid = sp.split.d_mid;
+    a.R = sp.split.R;
+    a.Q = sp.split.Q;
     a.bank = c->bank;
     a.bank_c = c->bank_f ? (const void *)c->bank_f : (const void *)c->bank;
     return sp;
@@ -827,6 +875,99 @@ quapi_status enqueue_step(quapi_ctx *c, int n, bool rho) {
     c->cur = 1 - c->cur;
     c->half_cur = half;
     c->step = n;
+    return QUAPI_OK;
+}
+
+// Filtered step n (1-based) on the context's stream, with rho(t_n) into the
+// sink's next slot: the factor-level tables of the step's digits (once for
+// the full window, per growth step, per step when driven), the segments of
+// the kept input entries, the counting pass, the scan of its keep flags, the
+// writing pass, and the new entry count.  Nothing on the host waits.
+quapi_status enqueue_filter_step(quapi_ctx *c, int n, bool rho) {
+    const int N = c->N, L = c->L;
+    StepArgs sa{};
+    step_tables(L, n, sa);
+    const bool full = n >= L;
+    const int nd = sa.n_digits;
+    const int n_lv = filter_levels(N, nd);
+    if (filter_plan_entries(N, nd) > c->fplan_entries && nd > 0)
+        return fail(c, QUAPI_ERR_DEVICE, "internal filter plan check failed at step %d", n);
+    const int set = full ? 0 : n;
+    if (c->fplan_for != set) {
+        FilterPlanArgs pa{};
+        pa.bank = c->bank;
+        pa.N = N;
+        pa.nd = nd;
+        pa.n_lv = n_lv;
+        std::memcpy(pa.tab, sa.tab, sizeof pa.tab);
+        std::memcpy(pa.tabf, sa.tabf, sizeof pa.tabf);
+        pa.t = c->fplan;
+        pa.tf = c->fplan + c->fplan_entries;
+        hipError_t e = launch_filter_plan(pa, c->stream);
+        if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "filter plan launch: %s", hipGetErrorString(e));
+        c->fplan_for = set;
+    }
+    const int in = c->cur, out = 1 - c->cur;
+    unsigned long long *ctr = c->fctr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        e0 = take_event(c);
+        e1 = take_event(c);
+        if (e0) (void)hipEventRecord(e0, c->stream);
+    }
+    FilterSegArgs g{};
+    g.keys = c->fkeys[in];
+    g.count = ctr + in;
+    g.flags = c->fflags;
+    g.sums = c->fsums;
+    g.total = ctr + 2;
+    g.seg_start = c->fseg;
+    g.nseg = ctr + 3;
+    g.nflags = ctr + 4;
+    g.full = full ? 1 : 0;
+    hipError_t e = launch_filter_segments(N, g, c->stream);
+    FilterStepArgs a{};
+    a.bank = c->bank;
+    a.keys_in = c->fkeys[in];
+    a.vals_in = c->fvals[in];
+    a.keys_out = c->fkeys[out];
+    a.vals_out = c->fvals[out];
+    a.seg_start = c->fseg;
+    a.nseg = ctr + 3;
+    a.flags = c->fflags;
+    a.total = ctr + 2;
+    a.partials = c->fpart;
+    a.t = c->fplan;
+    a.tf = c->fplan + c->fplan_entries;
+    a.capacity = c->fcap;
+    a.stride_new = (unsigned long long)ipow_ll(N, full ? L - 1 : n);
+    a.theta = c->theta;
+    a.full = full ? 1 : 0;
+    a.n_lv = n_lv;
+    a.old_tab = sa.old_tab;
+    a.oldf_tab = sa.oldf_tab;
+    if (e == hipSuccess) e = launch_filter_step(N, c->prec, a, true, rho, c->stream);
+    if (e == hipSuccess) e = launch_filter_scan(c->fflags, ctr + 4, c->fsums, ctr + 2, c->stream);
+    if (e == hipSuccess) e = launch_filter_step(N, c->prec, a, false, false, c->stream);
+    if (e == hipSuccess) e = launch_filter_count(ctr + 2, c->fcap, ctr + out, (int *)(ctr + 5), c->stream);
+    if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "filtered step launch: %s", hipGetErrorString(e));
+    if (c->timing && e0 && e1) {
+        (void)hipEventRecord(e1, c->stream);
+        c->recs.push_back({full ? 0 : 1, e0, e1, full ? 1 : 0, full ? 1 : 0});
+    }
+    if (rho) {
+        e = launch_rho_finalize(N, c->fpart, kFilterStepBlocks, c->pairs, c->sink, c->stream);
+        if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "rho finalize launch: %s", hipGetErrorString(e));
+    }
+    c->cur = out;
+    c->step = n;
+    return QUAPI_OK;
+}
+
+// The overflow flag of a filtered context (waits for its stream).
+quapi_status filter_overflow(quapi_ctx *c, int *overflow) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(overflow, c->fctr + 5, sizeof(int), hipMemcpyDeviceToHost));
     return QUAPI_OK;
 }
 
@@ -1517,8 +1658,9 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
             hipError_t e = launch_tables(ta, c->stream);
             if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "tables launch: %s", hipGetErrorString(e));
             c->plan_ready = false;
+            c->fplan_for = -1;
         }
-        st = enqueue_step(c, n, s0);
+        st = c->filtered ? enqueue_filter_step(c, n, s0) : enqueue_step(c, n, s0);
         if (st != QUAPI_OK) return st;
         if (s0) {
             if (sel) ++si;
@@ -1532,6 +1674,14 @@ quapi_status propagate_impl(quapi_ctx *c, int n_steps, const int *sel, int n_sel
         st = flush();
         if (st != QUAPI_OK) return st;
         HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (c->filtered) {
+            int overflow = 0;
+            st = filter_overflow(c, &overflow);
+            if (st != QUAPI_OK) return st;
+            if (overflow)
+                return fail(c, QUAPI_ERR_NOMEM, "the filtered tensor outgrew its capacity of %zu entries by step %d",
+                            c->fcap, c->step);
+        }
     }
     return QUAPI_OK;
 }
@@ -1572,17 +1722,19 @@ void release(quapi_ctx *c) {
 // quapi_create, and with one_stream the context of quapi_propagate_static:
 // the caller's stream only (no side or aux streams, no events, no graphs) and
 // the given workspace (never a device allocation).
+// fcap > 0: a filtered context (quapi_create_filtered) with threshold theta.
 quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace, size_t ws_bytes, bool one_stream,
-                        quapi_ctx **out) {
+                        quapi_ctx **out, double theta = -1.0, size_t fcap = 0) {
     if (!out) return fail(nullptr, QUAPI_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    const std::string msg = validate(p);
+    const bool filtered = fcap > 0;
+    const std::string msg = validate(p, filtered ? kFilterMaxLog2 : kDenseMaxLog2);
     if (!msg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", msg.c_str());
     const int M = p->M, N = M * M, L = p->dk_max;
     std::vector<double> pa, ph;
     std::vector<int> pseg;
     plan_panels(*p, (L + 1) * p->dt, pa, ph, pseg);
-    const Layout lay = make_layout(*p, (int)pa.size());
+    const Layout lay = make_layout(*p, (int)pa.size(), fcap);
     if (workspace) {
         if (ws_bytes < lay.total)
             return fail(nullptr, QUAPI_ERR_INVALID, "workspace of %zu bytes is smaller than the footprint %zu",
@@ -1677,6 +1829,23 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
     c->pairs = (double2 *)(w + lay.off_pairs);
     c->sink = (RhoSink *)(w + lay.off_sink);
     c->plan = (double2 *)(w + lay.off_plan);
+    if (filtered) {
+        c->filtered = true;
+        c->theta = theta;
+        c->fcap = fcap;
+        for (int b = 0; b < 2; ++b) {
+            c->fkeys[b] = (unsigned long long *)(w + lay.off_fkeys[b]);
+            c->fvals[b] = w + lay.off_fvals[b];
+        }
+        c->fflags = (unsigned *)(w + lay.off_fflags);
+        c->fseg = (unsigned *)(w + lay.off_fseg);
+        c->fsums = (unsigned *)(w + lay.off_fsums);
+        c->fctr = (unsigned long long *)(w + lay.off_fctr);
+        c->fpart = (double2 *)(w + lay.off_fpart);
+        c->fplan = (double2 *)(w + lay.off_fplan);
+        c->fplan_entries = lay.fplan_entries;
+        c->graph_failed = true;   // the steps read their sizes from device memory; nothing to capture
+    }
 
     c->s_h.assign(p->s, p->s + M);
     c->H_h.assign(p->H, p->H + 2 * M * M);
@@ -1689,18 +1858,18 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
             for (int b = 0; b < M; ++b)
                 herm = herm && p->rho0[2 * (a * M + b)] == p->rho0[2 * (b * M + a)] &&
                        p->rho0[2 * (a * M + b) + 1] == -p->rho0[2 * (b * M + a) + 1];
-        if (triple_ok(N, L)) {
+        if (triple_ok(N, L) && !filtered) {
             for (int pass = 0; pass < 2; ++pass)
                 for (int h = 0; h < lay.split3.grid; ++h)
                     if (pass == 0 ? h < mirror4(h) : h == mirror4(h)) c->blk3_h.push_back(h);
             c->mirror_ok = herm;
         }
-        if (fused_ok(N, L)) {
+        if (fused_ok(N, L) && !filtered) {
             for (int pass = 0; pass < 2; ++pass)
                 for (int h = 0; h < lay.split2.grid; ++h)
                     if (pass == 0 ? h < mirror4(h) : h == mirror4(h)) c->blk2_h.push_back(h);
         }
-        if (single_mirror_ok(N, L, lay.main_split)) {
+        if (single_mirror_ok(N, L, lay.main_split) && !filtered) {
             for (int pass = 0; pass < 2; ++pass)
                 for (int h = 0; h < lay.main_split.grid; ++h)
                     if (pass == 0 ? h < mirror_n(N, h) : h == mirror_n(N, h)) c->blk1_h.push_back(h);
@@ -1708,7 +1877,7 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
         }
         c->mirror = c->mirror_ok ? 1 : 0;
     }
-    c->fuse = c->n_H > 0 ? 1 : fusion_width(N, L, c->prec);
+    c->fuse = c->n_H > 0 || filtered ? 1 : fusion_width(N, L, c->prec);
     {
         // the persistent path: the tensor in LDS when both buffers fit a
         // block's LDS, else in the global buffers (still L2 resident)
@@ -1718,7 +1887,7 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             lds_max = 64 * 1024;
-        if (ent <= (size_t)kSmallMaxEntries) {
+        if (ent <= (size_t)kSmallMaxEntries && !filtered) {
             c->small = small_lds_bytes(N, c->prec, L, true) <= (size_t)lds_max ? 1
                        : small_lds_bytes(N, c->prec, L, false) <= (size_t)lds_max ? 2 : 0;
         }
@@ -1802,7 +1971,10 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
         ta.U_given = c->U;
     }
     if (e == hipSuccess) e = launch_tables(ta, c->stream);
-    if (e == hipSuccess)
+    if (e == hipSuccess && filtered)
+        e = launch_filter_init(c->prec, c->rho0_d, c->bank, BankLayout{L}.self_end(), N, theta, fcap, c->fkeys[0],
+                               c->fvals[0], c->fctr, (int *)(c->fctr + 5), c->stream);
+    else if (e == hipSuccess)
         e = launch_init_tensor(N, c->prec, c->rho0_d, c->bank, BankLayout{L}.self_end(), c->A[0], c->stream);
     if (s1) (void)hipEventRecord(s1, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1839,6 +2011,22 @@ std::mutex g_static_mu[kMaxStaticDevices];        // one static call at a time p
 void *g_static_ptr[kMaxStaticDevices] = {};       // the device address of `scratch`, per device
 }  // namespace
 
+namespace {
+// The capacity limits of a filtered context: at least one entry, and the
+// step's outputs (segments * N <= capacity * N) counted in 32 bits.
+std::string filter_args_error(const quapi_params *p, double theta, size_t capacity) {
+    if (!(theta >= 0.0) || !std::isfinite(theta)) return "theta must be finite and >= 0";
+    if (capacity < 1) return "capacity must be >= 1";
+    const int N = p->M * p->M;
+    if (capacity > (size_t)0xffffffffu / (size_t)N) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "capacity must be <= %zu at M = %d", (size_t)0xffffffffu / (size_t)N, p->M);
+        return buf;
+    }
+    return "";
+}
+}  // namespace
+
 // ===================================================================== ABI
 extern "C" {
 
@@ -1861,6 +2049,64 @@ quapi_status quapi_footprint(const quapi_params *p, size_t *device_bytes) {
 quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspace, size_t ws_bytes,
                           quapi_ctx **out) {
     return create_ctx(p, hip_stream, workspace, ws_bytes, false, out);
+}
+
+quapi_status quapi_filtered_footprint(const quapi_params *p, size_t capacity, size_t *device_bytes) {
+    const std::string msg = validate(p, kFilterMaxLog2);
+    if (!msg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", msg.c_str());
+    const std::string fmsg = filter_args_error(p, 0.0, capacity);
+    if (!fmsg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", fmsg.c_str());
+    if (!device_bytes) return fail(nullptr, QUAPI_ERR_INVALID, "device_bytes is NULL");
+    *device_bytes = make_layout(*p, count_panels(*p), capacity).total;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_create_filtered(const quapi_params *p, double theta, size_t capacity, void *hip_stream,
+                                   quapi_ctx **out) {
+    const std::string msg = validate(p, kFilterMaxLog2);
+    if (!msg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", msg.c_str());
+    const std::string fmsg = filter_args_error(p, theta, capacity);
+    if (!fmsg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", fmsg.c_str());
+    return create_ctx(p, hip_stream, nullptr, 0, false, out, theta, capacity);
+}
+
+quapi_status quapi_filter_stats(quapi_ctx *ctx, long long *entries, int *overflow) {
+    if (!ctx || !entries || !overflow) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    if (!ctx->filtered) return fail(ctx, QUAPI_ERR_INVALID, "not a filtered context");
+    BusyGuard g(ctx);
+    if (!g.ok) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    unsigned long long ctr[6] = {};
+    HIP_TRY(ctx, hipMemcpy(ctr, ctx->fctr, sizeof ctr, hipMemcpyDeviceToHost));
+    *entries = (long long)ctr[ctx->cur];
+    int ov = 0;
+    std::memcpy(&ov, &ctr[5], sizeof ov);
+    *overflow = ov;
+    return QUAPI_OK;
+}
+
+quapi_status quapi_filter_read(quapi_ctx *ctx, size_t first, size_t count, long long *keys, double *vals) {
+    if (!ctx || (count && (!keys || !vals))) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    if (!ctx->filtered) return fail(ctx, QUAPI_ERR_INVALID, "not a filtered context");
+    BusyGuard g(ctx);
+    if (!g.ok) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    unsigned long long n = 0;
+    HIP_TRY(ctx, hipMemcpy(&n, ctx->fctr + ctx->cur, sizeof n, hipMemcpyDeviceToHost));
+    if (first > n || count > n - first)
+        return fail(ctx, QUAPI_ERR_INVALID, "range [%zu, %zu) exceeds the %llu kept entries", first, first + count, n);
+    if (!count) return QUAPI_OK;
+    HIP_TRY(ctx, hipMemcpy(keys, ctx->fkeys[ctx->cur] + first, count * 8, hipMemcpyDeviceToHost));
+    if (ctx->prec == kPrecC128) {
+        HIP_TRY(ctx, hipMemcpy(vals, (const char *)ctx->fvals[ctx->cur] + first * 16, count * 16,
+                               hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(2 * count);
+        HIP_TRY(ctx, hipMemcpy(tmp.data(), (const char *)ctx->fvals[ctx->cur] + first * 8, count * 8,
+                               hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < 2 * count; ++i) vals[i] = tmp[i];
+    }
+    return QUAPI_OK;
 }
 
 quapi_status quapi_propagate_static(const quapi_params *p, int n_steps, const int *sel, int n_sel,
@@ -2020,9 +2266,10 @@ quapi_status quapi_fused_steps(const quapi_ctx *ctx, int *steps) {
 
 quapi_status quapi_set_fused_steps(quapi_ctx *ctx, int steps) {
     if (!ctx) return fail(nullptr, QUAPI_ERR_INVALID, "ctx is NULL");
+    if (ctx->filtered && steps > 1) return fail(ctx, QUAPI_ERR_INVALID, "a filtered context runs one step at a time");
     const int N = ctx->N, L = ctx->L;
     const bool pinned = steps != 0;
-    if (steps == 0) steps = ctx->n_H > 0 ? 1 : fusion_width(N, L, ctx->prec);
+    if (steps == 0) steps = ctx->n_H > 0 || ctx->filtered ? 1 : fusion_width(N, L, ctx->prec);
     if (ctx->n_H > 0 && steps != 1)
         return fail(ctx, QUAPI_ERR_INVALID, "a driven context runs one step per launch");
     const bool ok = steps == 1 || (steps == 2 && fused_ok(N, L)) || (steps == 3 && triple_ok(N, L));
@@ -2090,6 +2337,8 @@ quapi_status quapi_get_setup(const quapi_ctx *ctx, int what, double *out, size_t
 
 quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries) {
     if (!ctx || !entries) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
+    if (ctx->filtered)
+        return fail(const_cast<quapi_ctx *>(ctx), QUAPI_ERR_INVALID, "a filtered context: use quapi_filter_stats");
     const int axes = std::min(ctx->step + 1, ctx->L);
     *entries = (size_t)ipow_ll(ctx->N, axes);
     return QUAPI_OK;
@@ -2098,6 +2347,7 @@ quapi_status quapi_tensor_size(const quapi_ctx *ctx, size_t *entries) {
 quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count, double *out) {
     if (!ctx || (!out && count)) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
     quapi_ctx *c = const_cast<quapi_ctx *>(ctx);
+    if (c->filtered) return fail(c, QUAPI_ERR_INVALID, "a filtered context: use quapi_filter_read");
     BusyGuard g(c);                        // the step count and, in the completion pass, the tensor
     if (!g.ok) return fail(c, QUAPI_ERR_STATE, "context in use by another call");
     size_t entries = 0;
@@ -2121,6 +2371,7 @@ quapi_status quapi_read_tensor(const quapi_ctx *ctx, size_t first, size_t count,
 quapi_status quapi_restore(quapi_ctx *ctx, int step, const double *tensor, size_t count) {
     if (!ctx || !tensor) return fail(nullptr, QUAPI_ERR_INVALID, "NULL argument");
     quapi_ctx *c = ctx;
+    if (c->filtered) return fail(c, QUAPI_ERR_INVALID, "a filtered context cannot be restored from a dense tensor");
     if (step < 0) return fail(c, QUAPI_ERR_INVALID, "step must be >= 0");
     const size_t want = (size_t)ipow_ll(c->N, std::min(step + 1, c->L));
     if (count != want)

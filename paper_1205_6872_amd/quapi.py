@@ -35,6 +35,7 @@ EXPORTED_SYMBOLS = (
     "quapi_tensor_size", "quapi_set_timing", "quapi_get_timing", "quapi_destroy",
     "quapi_last_error", "quapi_copy_bandwidth", "quapi_propagate_static",
     "quapi_persistent", "quapi_propagate_batch",
+    "quapi_filtered_footprint", "quapi_create_filtered", "quapi_filter_stats", "quapi_filter_read",
 )
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -93,6 +94,10 @@ def load_library() -> ctypes.CDLL:
     lib.quapi_propagate_static.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ip, ctypes.c_int, vp, vp]
     lib.quapi_persistent.argtypes = [vp, ip]
     lib.quapi_propagate_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ip, ip, ctypes.POINTER(vp)]
+    lib.quapi_filtered_footprint.argtypes = [ctypes.POINTER(Params), sz, ctypes.POINTER(sz)]
+    lib.quapi_create_filtered.argtypes = [ctypes.POINTER(Params), ctypes.c_double, sz, vp, ctypes.POINTER(vp)]
+    lib.quapi_filter_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ip]
+    lib.quapi_filter_read.argtypes = [vp, sz, sz, ctypes.POINTER(ctypes.c_longlong), _DP]
     lib.quapi_last_error.argtypes = [vp]
     lib.quapi_last_error.restype = ctypes.c_char_p
     for name in EXPORTED_SYMBOLS:
@@ -289,6 +294,26 @@ class Context:
         h = self._live()
         _check(lib().quapi_restore(h, int(step), _ptr(buf), t.size), h)
 
+    def filter_stats(self) -> tuple:
+        """Filtered context: (entries kept after the last step, overflow flag)."""
+        n = ctypes.c_longlong(0)
+        ov = ctypes.c_int(0)
+        h = self._live()
+        _check(lib().quapi_filter_stats(h, ctypes.byref(n), ctypes.byref(ov)), h)
+        return int(n.value), int(ov.value)
+
+    def filter_read(self, first: int = 0, count: Optional[int] = None) -> tuple:
+        """Filtered context: (keys int64, values complex128) of kept entries
+        [first, first + count) in index order (count None: all from first)."""
+        if count is None:
+            count = self.filter_stats()[0] - first
+        keys = np.zeros(max(count, 1), dtype=np.int64)
+        vals = np.zeros(2 * max(count, 1), dtype=np.float64)
+        h = self._live()
+        _check(lib().quapi_filter_read(h, int(first), int(count),
+                                       keys.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), _ptr(vals)), h)
+        return keys[:count].copy(), vals.view(np.complex128)[:count].copy()
+
     def set_timing(self, enable: bool = True) -> None:
         _check(lib().quapi_set_timing(self._live(), int(bool(enable))))
 
@@ -368,6 +393,22 @@ def create(p: _ParamsHolder, stream: Optional[int] = None, workspace: Optional[i
                               ctypes.c_void_p(workspace) if workspace else None, int(ws_bytes),
                               ctypes.byref(h)))
     return Context(h, p.p.M, p.p.dk_max, keep=keep)
+
+
+def filtered_footprint(p: _ParamsHolder, capacity: int) -> int:
+    """Device bytes of a filtered context holding up to `capacity` kept entries."""
+    v = ctypes.c_size_t(0)
+    _check(lib().quapi_filtered_footprint(ctypes.byref(p.p), int(capacity), ctypes.byref(v)))
+    return int(v.value)
+
+
+def create_filtered(p: _ParamsHolder, theta: float, capacity: int, stream: Optional[int] = None) -> Context:
+    """quapi_create_filtered: entries with |A| <= theta are dropped as they form;
+    at most `capacity` kept entries."""
+    h = ctypes.c_void_p(None)
+    _check(lib().quapi_create_filtered(ctypes.byref(p.p), float(theta), int(capacity),
+                                       ctypes.c_void_p(stream) if stream else None, ctypes.byref(h)))
+    return Context(h, p.p.M, p.p.dk_max)
 
 
 def create_in_torch(p: _ParamsHolder, stream=None, device: str = "cuda:0") -> Context:

@@ -161,3 +161,34 @@ def test_static_entry_point_refuses_a_working_set_above_its_scratch_without_a_de
     with pytest.raises(Q.QuapiError) as ei:
         Q.propagate_static(Q.params_from(big), 3, None, 0)
     assert ei.value.status == Q.ERR_INVALID and "static scratch" in str(ei.value)
+
+
+def test_filtered_footprint_follows_the_capacity_not_n_to_the_l():
+    # M = 2, L = 21: 4^21 entries densely (70 TB at complex128), but a
+    # filtered context is sized by its capacity
+    p = _p(L=21)
+    with pytest.raises(Q.QuapiError):
+        Q.footprint(p)
+    cap = 10 ** 7
+    fp = Q.filtered_footprint(p, cap)
+    per_entry = 2 * (8 + 16) + 4 * 4 + 4            # keys + values twice, flags, segment starts
+    assert cap * per_entry <= fp <= cap * per_entry + 16 * 2 ** 20
+    fp64 = Q.filtered_footprint(_p(L=21, dtype="c64"), cap)
+    assert fp - fp64 == pytest.approx(2 * 8 * cap, abs=2 * 2 ** 20)
+
+
+@pytest.mark.parametrize("theta,cap,needle", [(-1.0, 100, "theta"), (float("nan"), 100, "theta"),
+                                               (0.0, 0, "capacity"), (0.0, 2 ** 31, "capacity")])
+def test_filtered_arguments_are_checked_before_any_device_call(theta, cap, needle):
+    h = ctypes.c_void_p(None)
+    p = _p()
+    st = Q.lib().quapi_create_filtered(ctypes.byref(p.p), theta, cap, None, ctypes.byref(h))
+    assert st == Q.ERR_INVALID
+    assert needle in Q.lib().quapi_last_error(None).decode()
+    assert not h.value
+
+
+def test_filtered_size_limit_is_two_to_the_62():
+    assert Q.filtered_footprint(_p(L=30), 1000) > 0            # 4^30 = 2^60
+    with pytest.raises(Q.QuapiError):
+        Q.filtered_footprint(Q.params_from(W.three_site_l8(), L=20), 1000)   # 9^20 > 2^62
