@@ -176,8 +176,8 @@ quapi_status quapi_propagate_async(quapi_ctx *ctx, int n_steps, const int *sel, 
  * kept count instead of N^L, and N^dk_max may reach 2^62.
  *
  * quapi_create_filtered: as quapi_create (its own device allocation; hip_stream
- *   borrowed or NULL), with theta >= 0 finite and 1 <= capacity <=
- *   (2^32 - 1) / N.  The context works with quapi_propagate,
+ *   borrowed or NULL), with theta >= 0 finite and 1 <= capacity <= 2^38.
+ *   The context works with quapi_propagate,
  *   quapi_propagate_async, quapi_step_count, quapi_get_setup, timing and
  *   quapi_destroy; every step runs as its own sequence of launches (no fused
  *   steps, mirror mode, persistent path or graphs), and quapi_read_tensor,
@@ -188,8 +188,8 @@ quapi_status quapi_propagate_async(quapi_ctx *ctx, int n_steps, const int *sel, 
  *   after quapi_propagate_async the caller reads the flag with
  *   quapi_filter_stats.  Deterministic (integer scans, fixed-order sums).
  * quapi_filtered_footprint: device bytes of such a context (about
- *   capacity * (2 * (8 + sizeof(complex)) + 4 N + 4) plus the tables); needs
- *   no GPU.
+ *   capacity * (2 * (8 + sizeof(complex)) + 2) plus a few MB of tables);
+ *   needs no GPU.
  * quapi_filter_stats: waits for the context's stream, then gives the entries
  *   kept after the last step and the overflow flag (0 or 1).
  * quapi_filter_read: waits for the stream, then copies kept entries

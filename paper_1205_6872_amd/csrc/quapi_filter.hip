@@ -15,15 +15,25 @@
 // point's table with the new point's self factor folded in.  An output is
 // kept when |out| > theta.  Because the new point is the most significant
 // digit, writing the kept outputs in the order (o, segment) leaves them
-// sorted by the new key: no sort is needed, only exclusive scans to place
-// them.  rho(t_n) comes from the same segments with the final-point classes.
+// sorted by the new key: no sort is needed.
 //
-// A step is: segment heads, their scan and the segment starts; a counting
-// pass (keep flags per (o, segment) and the rho block partials); the scan of
-// the flags; a writing pass that recomputes the outputs and stores the kept
-// ones at their places.  Every pass has a fixed grid and reads its element
-// count from device memory, so a run needs no host synchronization, and the
-// integer scans and fixed-order partial sums make it deterministic.
+// A step is three launches (and the rho finalize when rho is selected):
+//   count   block b walks its contiguous range of input entries in tiles,
+//           finds the segment heads of a tile (ballots), gathers them in
+//           LDS, and gives one thread per segment: it forms the N outputs,
+//           stores their keep bits as a mask at the segment's head entry,
+//           counts the kept outputs per o for the block, and adds the
+//           segment's rho(t_n) terms (final-point classes);
+//   offsets one block turns the N x blocks counts into exclusive offsets
+//           in (o, block) order, and sets the new entry count (at most the
+//           capacity) and the overflow flag;
+//   write   the same walk; each segment's mask gives, with ballots and the
+//           block's running offset per o, the place of every kept output,
+//           which is formed again and stored.
+// Both walks cost one read of the keys and values; the write pass stores the
+// kept outputs once.  The grids are fixed and read the entry count from
+// device memory, so a run needs no host synchronization; integer counts and
+// fixed-order partial sums make it deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,289 +45,366 @@ namespace quapi {
 namespace {
 
 constexpr int kFB = kFilterBlock;        // threads per block
-constexpr int kScanItems = 4;            // scan items per thread and tile
-constexpr int kScanTile = kFB * kScanItems;
+constexpr int kWaves = kFB / 64;
+constexpr int kSpan = 4;                 // entries per thread and tile
+constexpr int kTile = kFB * kSpan;       // entries per tile
 
-// ------------------------------------------------------------------ scans
-// Exclusive scan of x[0 .. n), n = *n_dev, in place, with kFilterScanBlocks
-// blocks each owning one contiguous chunk: (1) chunk sums, (2) a scan of the
-// sums (and the total to *total), (3) each chunk rescanned from its offset.
-__device__ __forceinline__ unsigned long long scan_chunk(unsigned long long n, int b, unsigned long long *lo) {
-    const unsigned long long chunk = (n + kFilterScanBlocks - 1) / kFilterScanBlocks;
-    *lo = chunk * b;
-    const unsigned long long hi = *lo + chunk;
-    return hi < n ? hi : n;
+// ------------------------------------------------------------ factor tables
+// The factor product over the digits of m is split into levels: level 0 the
+// lowest D0 digits, level l >= 1 the next D digits each, with
+// T_l[v][o] = prod over the digits of v of the tables of those digits at o, so
+// that P(o, m) = prod_l T_l[digits of m in level l][o] (FP64), and the same
+// for the final-point classes.  An entry holds both (p, pf), and the N values
+// of o for one (l, v) are contiguous.  Level 0 is small enough for LDS: the
+// lowest digits differ from segment to segment, the higher ones change slowly
+// along the sorted keys, so their lookups from global memory mostly hit the
+// same cache lines.  S0 = N^D0 and S = N^D are compile-time constants.
+template <int N> struct FilterLevel {
+    static constexpr int D0 = N == 4 ? 3 : N == 1 ? kMaxL : 1;
+    static constexpr int S0 = N == 4 ? 64 : N;
+    static constexpr int S = N == 4 ? 4096 : N == 9 ? 729 : N == 16 ? 4096 : 1;
+    static constexpr int kMax = 7;       // levels of the largest tensor (N^L <= 2^62)
+};
+
+__host__ __device__ inline int filter_level0_digits(int N) { return N == 4 ? 3 : N == 1 ? kMaxL : 1; }
+__host__ __device__ inline int filter_level0_size(int N) { return N == 4 ? 64 : N; }
+__host__ __device__ inline int filter_level_digits(int N) { return N == 4 ? 6 : N == 1 ? kMaxL : 3; }
+__host__ __device__ inline int filter_level_size(int N) {
+    return N == 4 ? 4096 : N == 9 ? 729 : N == 16 ? 4096 : 1;
 }
 
-// Block-wide exclusive scan of one value per thread: returns the prefix, and
-// the block total in *tot.  Every thread of the block must call it.
-__device__ unsigned block_excl_scan(unsigned v, unsigned *s_w, unsigned *tot) {
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    unsigned x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const unsigned y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) s_w[wave] = x;
-    __syncthreads();
-    unsigned before = 0, all = 0;
-    for (int w = 0; w < kFB / 64; ++w) {
-        if (w < wave) before += s_w[w];
-        all += s_w[w];
-    }
-    __syncthreads();
-    *tot = all;
-    return before + x - v;
-}
-
-__global__ void __launch_bounds__(kFB) scan_sums_kernel(const unsigned *__restrict__ x,
-                                                        const unsigned long long *n_dev, unsigned *sums) {
-    __shared__ unsigned s_w[kFB / 64];
-    unsigned long long lo;
-    const unsigned long long hi = scan_chunk(*n_dev, blockIdx.x, &lo);
-    unsigned acc = 0;
-    for (unsigned long long k = lo + threadIdx.x; k < hi; k += kFB) acc += x[k];
-    unsigned tot;
-    (void)block_excl_scan(acc, s_w, &tot);
-    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(kFB) scan_offsets_kernel(unsigned *sums, unsigned long long *total) {
-    __shared__ unsigned s_w[kFB / 64];
-    constexpr int per = kFilterScanBlocks / kFB;
-    unsigned v[per], acc = 0;
-    for (int k = 0; k < per; ++k) {
-        v[k] = sums[threadIdx.x * per + k];
-        acc += v[k];
-    }
-    unsigned tot;
-    unsigned run = block_excl_scan(acc, s_w, &tot);
-    for (int k = 0; k < per; ++k) {
-        sums[threadIdx.x * per + k] = run;
-        run += v[k];
-    }
-    if (threadIdx.x == 0) *total = tot;
-}
-
-__global__ void __launch_bounds__(kFB) scan_apply_kernel(unsigned *__restrict__ x, const unsigned long long *n_dev,
-                                                         const unsigned *__restrict__ offsets) {
-    __shared__ unsigned s_w[kFB / 64];
-    unsigned long long lo;
-    const unsigned long long hi = scan_chunk(*n_dev, blockIdx.x, &lo);
-    unsigned run = offsets[blockIdx.x];
-    for (unsigned long long base = lo; base < hi; base += kScanTile) {
-        unsigned v[kScanItems], acc = 0;
-        const unsigned long long k0 = base + (unsigned long long)kScanItems * threadIdx.x;
-        for (int u = 0; u < kScanItems; ++u) {
-            v[u] = k0 + u < hi ? x[k0 + u] : 0u;
-            acc += v[u];
+__global__ void __launch_bounds__(kFB) filter_plan_kernel(const FilterPlanArgs a) {
+    const int N = a.N, S0 = filter_level0_size(N), S = filter_level_size(N);
+    const int D0 = filter_level0_digits(N), D = filter_level_digits(N);
+    const long long total = (long long)N * (S0 + (long long)(a.n_lv - 1) * S);
+    const double2 one = make_double2(1.0, 0.0);
+    for (long long idx = (long long)blockIdx.x * kFB + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * kFB) {
+        const int o = (int)(idx % N);
+        const long long e = idx / N;
+        int l, v;
+        if (e < S0) {
+            l = 0;
+            v = (int)e;
+        } else {
+            l = 1 + (int)((e - S0) / S);
+            v = (int)((e - S0) % S);
         }
-        unsigned tot;
-        unsigned p = run + block_excl_scan(acc, s_w, &tot);
-        for (int u = 0; u < kScanItems; ++u) {
-            if (k0 + u < hi) x[k0 + u] = p;
-            p += v[u];
+        const int j0 = l == 0 ? 0 : D0 + (l - 1) * D, j1 = l == 0 ? D0 : j0 + D;
+        double2 p = one, pf = one;
+        for (int j = j0; j < a.nd && j < j1; ++j) {
+            const int dg = v % N;
+            v /= N;
+            p = cmul(p, a.bank[(size_t)a.tab[j] * (N * N) + o * N + dg]);
+            pf = cmul(pf, a.bank[(size_t)a.tabf[j] * (N * N) + o * N + dg]);
         }
-        run += tot;
+        a.t[2 * idx] = p;
+        a.t[2 * idx + 1] = pf;
     }
 }
 
-// -------------------------------------------------------------- segments
+// ------------------------------------------------------------------- step
 // The digits a segment shares: all but the oldest (full window), or all.
 template <int N>
 __device__ __forceinline__ unsigned long long seg_of(unsigned long long key, bool full) {
     return full ? key / N : key;
 }
 
-// head[k] = 1 where entry k starts a segment.
-template <int N>
-__global__ void __launch_bounds__(kFB) seg_head_kernel(const unsigned long long *__restrict__ keys,
-                                                       const unsigned long long *n_dev, int full,
-                                                       unsigned *__restrict__ head) {
-    const unsigned long long n = *n_dev;
-    for (unsigned long long k = (unsigned long long)blockIdx.x * kFB + threadIdx.x; k < n;
-         k += (unsigned long long)gridDim.x * kFB)
-        head[k] = (k == 0 || seg_of<N>(keys[k - 1], full) != seg_of<N>(keys[k], full)) ? 1u : 0u;
-}
+__device__ __forceinline__ unsigned long long lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
-// seg_start[s] = the first entry of segment s, seg_start[S] = n; *nseg = S,
-// *nflags = S * N (the outputs of the step).  excl: the scanned heads.
-template <int N>
-__global__ void __launch_bounds__(kFB) seg_start_kernel(const unsigned long long *__restrict__ keys,
-                                                        const unsigned long long *n_dev, int full,
-                                                        const unsigned *__restrict__ excl,
-                                                        const unsigned long long *n_heads,
-                                                        unsigned *__restrict__ seg_start, unsigned long long *nseg,
-                                                        unsigned long long *nflags) {
-    const unsigned long long n = *n_dev;
-    for (unsigned long long k = (unsigned long long)blockIdx.x * kFB + threadIdx.x; k < n;
-         k += (unsigned long long)gridDim.x * kFB)
-        if (k == 0 || seg_of<N>(keys[k - 1], full) != seg_of<N>(keys[k], full)) seg_start[excl[k]] = (unsigned)k;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const unsigned long long S = *n_heads;
-        seg_start[S] = (unsigned)n;
-        *nseg = S;
-        *nflags = S * N;
-    }
-}
-
-// ------------------------------------------------------------ factor tables
-// The factor product over the digits of m is split into levels of D digits:
-// T_l[o][v] = prod over the digits of v of Tab_{lD + j}[o][digit_j(v)], so that
-// P(o, m) = prod_l T_l[o][(m / S^l) % S] with S = N^D (FP64).  S is a power of
-// two for N = 4, 16 and a compile-time constant for N = 9.
-template <int N> struct FilterLevel {
-    static constexpr int S = N == 4 ? 4096 : N == 9 ? 729 : N == 16 ? 4096 : 1;
-};
-
-__host__ __device__ inline int filter_level_size(int N) {
-    return N == 4 ? 4096 : N == 9 ? 729 : N == 16 ? 4096 : 1;
-}
-__host__ __device__ inline int filter_level_digits(int N) { return N == 4 ? 6 : N == 1 ? 1 : 3; }
-
-__global__ void __launch_bounds__(kFB) filter_plan_kernel(const FilterPlanArgs a) {
-    const int N = a.N, S = filter_level_size(N), D = filter_level_digits(N);
-    const long long per = (long long)N * S;
-    const long long total = per * a.n_lv;
-    const double2 one = make_double2(1.0, 0.0);
-    for (long long idx = (long long)blockIdx.x * kFB + threadIdx.x; idx < total;
-         idx += (long long)gridDim.x * kFB) {
-        const int l = (int)(idx / per);
-        const int o = (int)((idx % per) / S);
-        int v = (int)(idx % S);
-        double2 p = one, pf = one;
-        for (int j = l * D; j < a.nd && j < (l + 1) * D; ++j) {
-            const int dg = v % N;
-            v /= N;
-            p = cmul(p, a.bank[(size_t)a.tab[j] * (N * N) + o * N + dg]);
-            pf = cmul(pf, a.bank[(size_t)a.tabf[j] * (N * N) + o * N + dg]);
-        }
-        a.t[idx] = p;
-        a.tf[idx] = pf;
-    }
-}
-
-// ------------------------------------------------------------------- step
-// The outputs of segment s for every new point o.  COUNT: the keep flags at
-// [o * nseg + s] and, with RHO, the block partial sums of rho(t_n); otherwise
-// the kept outputs at the places the scanned flags give.  The loop over o is
-// not unrolled (at N = 9, 16 an unrolled one spills); each thread's rho sums
-// sit in dynamic LDS, [o][thread] (filter_step_lds_bytes).
+// The count (COUNT) or write pass of one step; see the top of the file.
+// Dynamic LDS (RHO): each thread's rho sums, [o][thread].
 template <int N, typename S, typename T, bool COUNT, bool RHO>
 __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a) {
     using C = typename Cx<T>::type;
     using CS = typename Cx<S>::type;
     using LV = FilterLevel<N>;
+    static_assert(N <= 16, "keep masks are 16 bits");
+    // the outputs of a segment run unrolled at N <= 4 (their loads overlap);
+    // at N = 9, 16 one at a time (unrolled, they spill)
+    constexpr int kOutUnroll = 1;
+    // N <= 4: the upper factor levels of a segment are multiplied for every o
+    // at once, before the outputs, so that their loads are in flight together
+    constexpr bool kHoist = N <= 4;
     extern __shared__ __align__(16) unsigned char f_smem[];
     double2 *s_acc = (double2 *)f_smem;
     __shared__ C s_old[N * N], s_oldf[N * N];
-    __shared__ double2 s_red[kFB / 64][RHO ? N : 1];
-    const int t = threadIdx.x;
+    __shared__ double2 s_t0[2 * LV::S0 * N];           // level 0 of the factor tables
+    __shared__ unsigned s_heads[kTile];                // tile offsets of the tile's segment heads
+    __shared__ unsigned s_hw[kSpan][kWaves];           // heads per sub-tile and wave
+    __shared__ unsigned s_kw[kWaves][N];               // write pass: kept outputs per wave and o
+    __shared__ unsigned long long s_run[N];            // write pass: the block's next place per o
+    __shared__ unsigned s_cnt[N];                      // count pass: the block's kept outputs per o
+    __shared__ double2 s_red[kWaves][RHO ? N : 1];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const bool full = a.full != 0;
     const double2 *__restrict__ bank = a.bank;
+    const unsigned long long *__restrict__ keys = a.keys_in;
+    const CS *__restrict__ vin = (const CS *)a.vals_in;
+    CS *__restrict__ vout = (CS *)a.vals_out;
     for (int idx = t; idx < N * N; idx += kFB) {
         s_old[idx] = from_d2<C>(bank[(size_t)a.old_tab * (N * N) + idx]);
         if (RHO) s_oldf[idx] = from_d2<C>(bank[(size_t)a.oldf_tab * (N * N) + idx]);
     }
+    if (a.n_lv > 0)
+        for (int idx = t; idx < 2 * LV::S0 * N; idx += kFB) s_t0[idx] = a.t[idx];
     if (RHO)
         for (int o = 0; o < N; ++o) s_acc[o * kFB + t] = make_double2(0.0, 0.0);
+    if (t < N) {
+        if (COUNT) s_cnt[t] = 0;
+        else s_run[t] = a.bofs[(size_t)t * gridDim.x + blockIdx.x];
+    }
+    const unsigned long long n_in = *a.count_in;
+    const unsigned long long chunk = (n_in + gridDim.x - 1) / gridDim.x;
+    const unsigned long long lo = chunk * blockIdx.x;
+    const unsigned long long hi = lo + chunk < n_in ? lo + chunk : n_in;
     __syncthreads();
-    const unsigned long long nseg = *a.nseg;
-    const unsigned long long nflags = nseg * N;
-    const CS *__restrict__ vin = (const CS *)a.vals_in;
-    CS *__restrict__ vout = (CS *)a.vals_out;
-    const double2 *__restrict__ tp = a.t;
-    const double2 *__restrict__ tpf = a.tf;
-    for (unsigned long long s = (unsigned long long)blockIdx.x * kFB + t; s < nseg;
-         s += (unsigned long long)gridDim.x * kFB) {
-        const unsigned k0 = a.seg_start[s], k1 = a.seg_start[s + 1];
-        const unsigned long long m = seg_of<N>(a.keys_in[k0], full);
-        // the segment's values by oldest digit (the dropped ones are zero)
-        C x[N];
+
+    for (unsigned long long base = lo; base < hi; base += kTile) {
+        // the segment heads of the tile, gathered in key order (sub-tile u, then lane)
+        bool head[kSpan];
+        unsigned long long bal[kSpan];
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = C{};
-        if (full) {
-            for (unsigned k = k0; k < k1; ++k) {
-                const int i = (int)(a.keys_in[k] % N);
-                const C v = conv<C>(vin[k]);
-#pragma unroll
-                for (int ii = 0; ii < N; ++ii)
-                    if (ii == i) x[ii] = v;
-            }
-        } else {
-            x[0] = conv<C>(vin[k0]);
+        for (int u = 0; u < kSpan; ++u) {
+            const unsigned long long k = base + (unsigned long long)u * kFB + t;
+            head[u] = k < hi && (k == 0 || seg_of<N>(keys[k - 1], full) != seg_of<N>(keys[k], full));
+            bal[u] = __ballot(head[u]);
+            if (lane == 0) s_hw[u][wave] = (unsigned)__popcll(bal[u]);
         }
-#pragma unroll 1
-        for (int o = 0; o < N; ++o) {
-            double2 p = make_double2(1.0, 0.0), pf = p;
-            unsigned long long v = m;
-            for (int l = 0; l < a.n_lv; ++l) {
-                const size_t e = ((size_t)l * N + o) * LV::S + (size_t)(v % LV::S);
-                v /= LV::S;
-                p = cmul(p, tp[e]);
-                if (RHO) pf = cmul(pf, tpf[e]);
-            }
-            C sum = C{}, sumf = C{};
-            if (full) {
+        __syncthreads();
+        unsigned n_heads = 0;
 #pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    cmac(sum, s_old[o * N + i], x[i]);
-                    if (RHO) cmac(sumf, s_oldf[o * N + i], x[i]);
-                }
-            } else {
-                sum = cmul(s_old[o * N], x[0]);
-                if (RHO) sumf = cmul(s_oldf[o * N], x[0]);
+        for (int u = 0; u < kSpan; ++u) {
+            unsigned before = n_heads;
+            for (int w = 0; w < kWaves; ++w) {
+                if (w < wave) before += s_hw[u][w];
+                n_heads += s_hw[u][w];
             }
-            const C out = cmul(from_d2<C>(p), sum);
-            const unsigned long long slot = (unsigned long long)o * nseg + s;
+            if (head[u]) s_heads[before + __popcll(bal[u] & lanes_below(lane))] = (unsigned)(u * kFB + t);
+        }
+        __syncthreads();
+
+        // one thread per segment, in rounds of kFB segments
+        for (unsigned r = 0; r < n_heads; r += kFB) {
+            const bool active = r + t < n_heads;
+            unsigned long long kh = 0, m = 0;
+            C x[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) x[i] = C{};
+            unsigned mask = 0;
+            unsigned lv[LV::kMax];                     // level indices of m
+            if (active) {
+                kh = base + s_heads[r + t];
+                m = seg_of<N>(keys[kh], full);
+                if (full) {
+                    // the segment's values by oldest digit (the dropped ones are zero)
+                    if constexpr (N <= 4) {
+                        // all N candidates loaded at once; those of the next segments are ignored
+                        unsigned long long kk[N];
+                        CS vv[N];
+#pragma unroll
+                        for (int e = 0; e < N; ++e) {
+                            const bool in = kh + e < n_in;
+                            kk[e] = in ? keys[kh + e] : ~0ull;
+                            vv[e] = in ? vin[kh + e] : CS{};
+                        }
+#pragma unroll
+                        for (int e = 0; e < N; ++e) {
+                            if (seg_of<N>(kk[e], true) != m) continue;
+                            const int i = (int)(kk[e] % N);
+#pragma unroll
+                            for (int ii = 0; ii < N; ++ii)
+                                if (ii == i) x[ii] = conv<C>(vv[e]);
+                        }
+                    } else {
+                        for (int e = 0; e < N && kh + e < n_in; ++e) {
+                            const unsigned long long key = keys[kh + e];
+                            if (seg_of<N>(key, true) != m) break;
+                            const int i = (int)(key % N);
+                            const C v = conv<C>(vin[kh + e]);
+#pragma unroll
+                            for (int ii = 0; ii < N; ++ii)
+                                if (ii == i) x[ii] = v;
+                        }
+                    }
+                } else {
+                    x[0] = conv<C>(vin[kh]);
+                }
+                if (!COUNT) mask = a.masks[kh];
+            }
+            {
+                lv[0] = (unsigned)(m % LV::S0);
+                unsigned long long v = m / LV::S0;
+#pragma unroll
+                for (int l = 1; l < LV::kMax; ++l) {
+                    lv[l] = (unsigned)(v % LV::S);
+                    v /= LV::S;
+                }
+            }
+            if (!COUNT) {
+                // places: the kept outputs of earlier waves and lanes of this round
+#pragma unroll 1
+                for (int o = 0; o < N; ++o) {
+                    const unsigned long long b = __ballot((mask >> o) & 1u);
+                    if (lane == 0) s_kw[wave][o] = (unsigned)__popcll(b);
+                }
+                __syncthreads();
+            }
+            double2 up[kHoist ? N : 1], upf[kHoist ? N : 1];
+            if constexpr (kHoist) {
+#pragma unroll
+                for (int o = 0; o < N; ++o) up[o] = upf[o] = make_double2(1.0, 0.0);
+#pragma unroll
+                for (int l = 1; l < LV::kMax; ++l) {
+                    if (l < a.n_lv && active) {
+                        const double2 *q = a.t + 2 * (((size_t)LV::S0 + (size_t)(l - 1) * LV::S + lv[l]) * N);
+#pragma unroll
+                        for (int o = 0; o < N; ++o) {
+                            up[o] = cmul(up[o], q[2 * o]);
+                            if (RHO) upf[o] = cmul(upf[o], q[2 * o + 1]);
+                        }
+                    }
+                }
+            }
+#pragma unroll kOutUnroll
+            for (int o = 0; o < N; ++o) {
+                const bool want = active && (COUNT || ((mask >> o) & 1u));
+                unsigned long long place = 0;
+                if (!COUNT) {
+                    const unsigned long long b = __ballot((mask >> o) & 1u);
+                    place = s_run[o] + __popcll(b & lanes_below(lane));
+                    for (int w = 0; w < wave; ++w) place += s_kw[w][o];
+                }
+                if (want) {
+                    double2 p = make_double2(1.0, 0.0), pf = p;
+                    if (a.n_lv > 0) {
+                        p = s_t0[2 * (lv[0] * N + o)];
+                        if (RHO) pf = s_t0[2 * (lv[0] * N + o) + 1];
+                    }
+                    if constexpr (kHoist) {
+                        double2 u = up[0], uf = upf[0];
+#pragma unroll
+                        for (int oo = 1; oo < N; ++oo)
+                            if (oo == o) {
+                                u = up[oo];
+                                uf = upf[oo];
+                            }
+                        p = cmul(p, u);
+                        if (RHO) pf = cmul(pf, uf);
+                    } else {
+#pragma unroll
+                        for (int l = 1; l < LV::kMax; ++l) {
+                            if (l < a.n_lv) {
+                                const double2 *q =
+                                    a.t + 2 * (((size_t)LV::S0 + (size_t)(l - 1) * LV::S + lv[l]) * N + o);
+                                p = cmul(p, q[0]);
+                                if (RHO) pf = cmul(pf, q[1]);
+                            }
+                        }
+                    }
+                    C sum = C{}, sumf = C{};
+                    if (full) {
+#pragma unroll
+                        for (int i = 0; i < N; ++i) {
+                            cmac(sum, s_old[o * N + i], x[i]);
+                            if (RHO) cmac(sumf, s_oldf[o * N + i], x[i]);
+                        }
+                    } else {
+                        sum = cmul(s_old[o * N], x[0]);
+                        if (RHO) sumf = cmul(s_oldf[o * N], x[0]);
+                    }
+                    const C out = cmul(from_d2<C>(p), sum);
+                    if (COUNT) {
+                        const double re = out.x, im = out.y;
+                        if (sqrt(fma(re, re, im * im)) > a.theta) mask |= 1u << o;
+                        if (RHO) {
+                            const double2 w = cmul(pf, to_d2(sumf));
+                            double2 &acc = s_acc[o * kFB + t];
+                            acc.x += w.x;
+                            acc.y += w.y;
+                        }
+                    } else if (place < a.capacity) {
+                        a.keys_out[place] = m + a.stride_new * (unsigned long long)o;
+                        vout[place] = conv<CS>(out);
+                    }
+                }
+            }
             if (COUNT) {
-                const double re = out.x, im = out.y;
-                a.flags[slot] = sqrt(fma(re, re, im * im)) > a.theta ? 1u : 0u;
-                if (RHO) {
-                    const double2 w = cmul(pf, to_d2(sumf));
-                    double2 &r = s_acc[o * kFB + t];
-                    r.x += w.x;
-                    r.y += w.y;
+                if (active) a.masks[kh] = (unsigned short)mask;
+#pragma unroll 1
+                for (int o = 0; o < N; ++o) {
+                    const unsigned long long b = __ballot((mask >> o) & 1u);
+                    if (lane == 0 && b) atomicAdd(&s_cnt[o], (unsigned)__popcll(b));
                 }
             } else {
-                // kept in the counting pass iff the scan steps up after this slot
-                const unsigned long long pos = a.flags[slot];
-                const unsigned long long next = slot + 1 < nflags ? a.flags[slot + 1] : *a.total;
-                if (next > pos && pos < a.capacity) {
-                    a.keys_out[pos] = m + a.stride_new * (unsigned long long)o;
-                    vout[pos] = conv<CS>(out);
+                __syncthreads();
+                if (t < N) {
+                    unsigned add = 0;
+                    for (int w = 0; w < kWaves; ++w) add += s_kw[w][t];
+                    s_run[t] += add;
                 }
+                __syncthreads();
             }
         }
     }
-    if (COUNT && RHO) {
-        const int lane = t & 63, wave = t >> 6;
-        for (int o = 0; o < N; ++o) {
-            double2 v = s_acc[o * kFB + t];
-            for (int off = 32; off > 0; off >>= 1) {
-                v.x += __shfl_xor(v.x, off, 64);
-                v.y += __shfl_xor(v.y, off, 64);
-            }
-            if (lane == 0) s_red[wave][o] = v;
-        }
+    if (COUNT) {
         __syncthreads();
-        if (t < N) {
-            double2 r = make_double2(0.0, 0.0);
-            for (int w = 0; w < kFB / 64; ++w) {
-                r.x += s_red[w][t].x;
-                r.y += s_red[w][t].y;
+        if (t < N) a.bofs[(size_t)t * gridDim.x + blockIdx.x] = s_cnt[t];
+        if (RHO) {
+            for (int o = 0; o < N; ++o) {
+                double2 v = s_acc[o * kFB + t];
+                for (int off = 32; off > 0; off >>= 1) {
+                    v.x += __shfl_xor(v.x, off, 64);
+                    v.y += __shfl_xor(v.y, off, 64);
+                }
+                if (lane == 0) s_red[wave][o] = v;
             }
-            a.partials[(size_t)blockIdx.x * N + t] = r;
+            __syncthreads();
+            if (t < N) {
+                double2 r = make_double2(0.0, 0.0);
+                for (int w = 0; w < kWaves; ++w) {
+                    r.x += s_red[w][t].x;
+                    r.y += s_red[w][t].y;
+                }
+                a.partials[(size_t)blockIdx.x * N + t] = r;
+            }
         }
     }
 }
 
-// The entry count after a step (at most the capacity) and the overflow flag.
-__global__ void filter_count_kernel(const unsigned long long *total, unsigned long long capacity,
-                                    unsigned long long *count_out, int *overflow) {
-    const unsigned long long k = *total;
-    *count_out = k < capacity ? k : capacity;
-    if (k > capacity) *overflow = 1;
+// Exclusive offsets of the n per-(o, block) counts in place (one block of
+// kFB threads, each owning a contiguous run), the total kept outputs, the new
+// entry count (at most the capacity) and the sticky overflow flag.
+__global__ void __launch_bounds__(kFB) filter_offsets_kernel(unsigned long long *bofs, int n,
+                                                             unsigned long long capacity,
+                                                             unsigned long long *count_out, int *overflow) {
+    __shared__ unsigned long long s_w[kWaves];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int per = (n + kFB - 1) / kFB;
+    const int lo = std::min(n, t * per), hi = std::min(n, lo + per);
+    unsigned long long mine = 0;
+    for (int i = lo; i < hi; ++i) mine += bofs[i];
+    unsigned long long x = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    unsigned long long run = x - mine, total = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) run += s_w[w];
+        total += s_w[w];
+    }
+    for (int i = lo; i < hi; ++i) {
+        const unsigned long long c = bofs[i];
+        bofs[i] = run;
+        run += c;
+    }
+    if (t == 0) {
+        *count_out = total < capacity ? total : capacity;
+        if (total > capacity) *overflow = 1;
+    }
 }
 
 // The initial tensor: rho0[o] times the initial self factor (FP64), kept if
@@ -362,28 +449,20 @@ hipError_t launch_filter_step_n(int prec, const FilterStepArgs &a, bool count, b
     }
 }
 
-template <int N>
-hipError_t launch_filter_segments_n(const FilterSegArgs &a, hipStream_t st) {
-    const dim3 g(kFilterStepBlocks), b(kFB);
-    hipLaunchKernelGGL((seg_head_kernel<N>), g, b, 0, st, a.keys, a.count, a.full, a.flags);
-    hipError_t e = launch_filter_scan(a.flags, a.count, a.sums, a.total, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((seg_start_kernel<N>), g, b, 0, st, a.keys, a.count, a.full, a.flags, a.total, a.seg_start,
-                       a.nseg, a.nflags);
-    return hipGetLastError();
-}
-
 }  // namespace
 
 size_t filter_step_lds_bytes(int N, bool rho) { return rho ? (size_t)N * kFB * sizeof(double2) : 0; }
 
 int filter_levels(int N, int n_digits) {
-    const int D = filter_level_digits(N);
-    return (n_digits + D - 1) / D;
+    if (n_digits <= 0) return 0;
+    const int D0 = filter_level0_digits(N), D = filter_level_digits(N);
+    return 1 + (std::max(n_digits - D0, 0) + D - 1) / D;
 }
 
 size_t filter_plan_entries(int N, int n_digits) {
-    return (size_t)filter_levels(N, n_digits) * N * filter_level_size(N);
+    const int n_lv = filter_levels(N, n_digits);
+    if (n_lv == 0) return 0;
+    return (size_t)N * (filter_level0_size(N) + (size_t)(n_lv - 1) * filter_level_size(N));
 }
 
 hipError_t launch_filter_plan(const FilterPlanArgs &a, hipStream_t st) {
@@ -392,25 +471,6 @@ hipError_t launch_filter_plan(const FilterPlanArgs &a, hipStream_t st) {
     const int grid = (int)std::min<long long>(1024, (total + kFB - 1) / kFB);
     hipLaunchKernelGGL(filter_plan_kernel, dim3(grid), dim3(kFB), 0, st, a);
     return hipGetLastError();
-}
-
-hipError_t launch_filter_scan(unsigned *x, const unsigned long long *n_dev, unsigned *sums,
-                              unsigned long long *total, hipStream_t st) {
-    static_assert(kFilterScanBlocks % kFB == 0, "the offsets scan gives each thread kFilterScanBlocks / kFB sums");
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(kFilterScanBlocks), dim3(kFB), 0, st, x, n_dev, sums);
-    hipLaunchKernelGGL(scan_offsets_kernel, dim3(1), dim3(kFB), 0, st, sums, total);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3(kFilterScanBlocks), dim3(kFB), 0, st, x, n_dev, sums);
-    return hipGetLastError();
-}
-
-hipError_t launch_filter_segments(int N, const FilterSegArgs &a, hipStream_t st) {
-    switch (N) {
-    case 1: return launch_filter_segments_n<1>(a, st);
-    case 4: return launch_filter_segments_n<4>(a, st);
-    case 9: return launch_filter_segments_n<9>(a, st);
-    case 16: return launch_filter_segments_n<16>(a, st);
-    default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_filter_step(int N, int prec, const FilterStepArgs &a, bool count, bool rho, hipStream_t st) {
@@ -423,9 +483,10 @@ hipError_t launch_filter_step(int N, int prec, const FilterStepArgs &a, bool cou
     }
 }
 
-hipError_t launch_filter_count(const unsigned long long *total, unsigned long long capacity,
-                               unsigned long long *count_out, int *overflow, hipStream_t st) {
-    hipLaunchKernelGGL(filter_count_kernel, dim3(1), dim3(1), 0, st, total, capacity, count_out, overflow);
+hipError_t launch_filter_offsets(int N, unsigned long long *bofs, unsigned long long capacity,
+                                 unsigned long long *count_out, int *overflow, hipStream_t st) {
+    hipLaunchKernelGGL(filter_offsets_kernel, dim3(1), dim3(kFB), 0, st, bofs, N * kFilterStepBlocks, capacity,
+                       count_out, overflow);
     return hipGetLastError();
 }
 

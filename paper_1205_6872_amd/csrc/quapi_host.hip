@@ -292,7 +292,7 @@ struct Layout {
     size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_blk2, off_blk1, off_pairs, off_sink;
     // filtered contexts: keys and values of the two tensors, flags, segment
     // starts, scan partials, counters, rho partials, factor-level tables
-    size_t off_fkeys[2], off_fvals[2], off_fflags, off_fseg, off_fsums, off_fctr, off_fpart, off_fplan;
+    size_t off_fkeys[2], off_fvals[2], off_fmask, off_fbofs, off_fctr, off_fpart, off_fplan;
     size_t fplan_entries;            // entries of one factor-level table set
     size_t total;
     int n_panels, n_tables, partial_blocks;
@@ -446,10 +446,9 @@ Layout make_layout(const quapi_params &p, int n_panels, size_t filter_cap = 0) {
         l.off_fkeys[b] = take(fc * 8);
         l.off_fvals[b] = take(fc * cs);
     }
-    l.off_fflags = take(fc * N * 4);                 // a step's outputs: segments * N <= capacity * N
-    l.off_fseg = take(filtered ? (fc + 1) * 4 : 0);
-    l.off_fsums = take(filtered ? (size_t)kFilterScanBlocks * 4 : 0);
-    l.off_fctr = take(filtered ? 8 * 8 : 0);          // counts of both buffers, scan total, segments, flags, overflow
+    l.off_fmask = take(fc * 2);                      // a keep mask per input entry (segment heads)
+    l.off_fbofs = take(filtered ? (size_t)N * kFilterStepBlocks * 8 : 0);
+    l.off_fctr = take(filtered ? 8 * 8 : 0);          // entry counts of both buffers, overflow flag
     l.off_fpart = take(filtered ? (size_t)kFilterStepBlocks * N * 16 : 0);
     l.fplan_entries = filtered ? std::max<size_t>(1, filter_plan_entries(N, L - 1)) : 0;
     l.off_fplan = take(l.fplan_entries * 2 * 16);
@@ -531,16 +530,16 @@ struct quapi_ctx {
     void *coef3 = nullptr;
     // Filtered propagation (quapi_create_filtered): the kept entries as sorted
     // (key, value) pairs in two buffers of fcap entries, fkeys[cur] / fvals[cur]
-    // the current tensor; fctr[0], fctr[1] their entry counts, fctr[2] the
-    // last scan total, fctr[3] segments, fctr[4] flags, fctr[5] (as int) the
-    // sticky overflow flag.
+    // the current tensor; fctr[0], fctr[1] their entry counts, fctr[2] (as int)
+    // the sticky overflow flag; fmask the keep masks, fbofs the per-(o, block)
+    // counts and offsets of a step.
     bool filtered = false;
     double theta = 0.0;
     size_t fcap = 0;
     unsigned long long *fkeys[2] = {nullptr, nullptr};
     void *fvals[2] = {nullptr, nullptr};
-    unsigned *fflags = nullptr, *fseg = nullptr, *fsums = nullptr;
-    unsigned long long *fctr = nullptr;
+    unsigned short *fmask = nullptr;
+    unsigned long long *fbofs = nullptr, *fctr = nullptr;
     double2 *fpart = nullptr, *fplan = nullptr;
     size_t fplan_entries = 0;
     int fplan_for = -1;           // the step set fplan holds: 0 the full window, n growth step n
@@ -902,7 +901,6 @@ quapi_status enqueue_filter_step(quapi_ctx *c, int n, bool rho) {
         std::memcpy(pa.tab, sa.tab, sizeof pa.tab);
         std::memcpy(pa.tabf, sa.tabf, sizeof pa.tabf);
         pa.t = c->fplan;
-        pa.tf = c->fplan + c->fplan_entries;
         hipError_t e = launch_filter_plan(pa, c->stream);
         if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "filter plan launch: %s", hipGetErrorString(e));
         c->fplan_for = set;
@@ -915,30 +913,17 @@ quapi_status enqueue_filter_step(quapi_ctx *c, int n, bool rho) {
         e1 = take_event(c);
         if (e0) (void)hipEventRecord(e0, c->stream);
     }
-    FilterSegArgs g{};
-    g.keys = c->fkeys[in];
-    g.count = ctr + in;
-    g.flags = c->fflags;
-    g.sums = c->fsums;
-    g.total = ctr + 2;
-    g.seg_start = c->fseg;
-    g.nseg = ctr + 3;
-    g.nflags = ctr + 4;
-    g.full = full ? 1 : 0;
-    hipError_t e = launch_filter_segments(N, g, c->stream);
     FilterStepArgs a{};
     a.bank = c->bank;
+    a.count_in = ctr + in;
     a.keys_in = c->fkeys[in];
     a.vals_in = c->fvals[in];
     a.keys_out = c->fkeys[out];
     a.vals_out = c->fvals[out];
-    a.seg_start = c->fseg;
-    a.nseg = ctr + 3;
-    a.flags = c->fflags;
-    a.total = ctr + 2;
+    a.masks = c->fmask;
+    a.bofs = c->fbofs;
     a.partials = c->fpart;
     a.t = c->fplan;
-    a.tf = c->fplan + c->fplan_entries;
     a.capacity = c->fcap;
     a.stride_new = (unsigned long long)ipow_ll(N, full ? L - 1 : n);
     a.theta = c->theta;
@@ -946,10 +931,9 @@ quapi_status enqueue_filter_step(quapi_ctx *c, int n, bool rho) {
     a.n_lv = n_lv;
     a.old_tab = sa.old_tab;
     a.oldf_tab = sa.oldf_tab;
-    if (e == hipSuccess) e = launch_filter_step(N, c->prec, a, true, rho, c->stream);
-    if (e == hipSuccess) e = launch_filter_scan(c->fflags, ctr + 4, c->fsums, ctr + 2, c->stream);
+    hipError_t e = launch_filter_step(N, c->prec, a, true, rho, c->stream);
+    if (e == hipSuccess) e = launch_filter_offsets(N, c->fbofs, c->fcap, ctr + out, (int *)(ctr + 2), c->stream);
     if (e == hipSuccess) e = launch_filter_step(N, c->prec, a, false, false, c->stream);
-    if (e == hipSuccess) e = launch_filter_count(ctr + 2, c->fcap, ctr + out, (int *)(ctr + 5), c->stream);
     if (e != hipSuccess) return fail(c, QUAPI_ERR_DEVICE, "filtered step launch: %s", hipGetErrorString(e));
     if (c->timing && e0 && e1) {
         (void)hipEventRecord(e1, c->stream);
@@ -967,7 +951,7 @@ quapi_status enqueue_filter_step(quapi_ctx *c, int n, bool rho) {
 // The overflow flag of a filtered context (waits for its stream).
 quapi_status filter_overflow(quapi_ctx *c, int *overflow) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, hipMemcpy(overflow, c->fctr + 5, sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(overflow, c->fctr + 2, sizeof(int), hipMemcpyDeviceToHost));
     return QUAPI_OK;
 }
 
@@ -1837,9 +1821,8 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
             c->fkeys[b] = (unsigned long long *)(w + lay.off_fkeys[b]);
             c->fvals[b] = w + lay.off_fvals[b];
         }
-        c->fflags = (unsigned *)(w + lay.off_fflags);
-        c->fseg = (unsigned *)(w + lay.off_fseg);
-        c->fsums = (unsigned *)(w + lay.off_fsums);
+        c->fmask = (unsigned short *)(w + lay.off_fmask);
+        c->fbofs = (unsigned long long *)(w + lay.off_fbofs);
         c->fctr = (unsigned long long *)(w + lay.off_fctr);
         c->fpart = (double2 *)(w + lay.off_fpart);
         c->fplan = (double2 *)(w + lay.off_fplan);
@@ -1973,7 +1956,7 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
     if (e == hipSuccess) e = launch_tables(ta, c->stream);
     if (e == hipSuccess && filtered)
         e = launch_filter_init(c->prec, c->rho0_d, c->bank, BankLayout{L}.self_end(), N, theta, fcap, c->fkeys[0],
-                               c->fvals[0], c->fctr, (int *)(c->fctr + 5), c->stream);
+                               c->fvals[0], c->fctr, (int *)(c->fctr + 2), c->stream);
     else if (e == hipSuccess)
         e = launch_init_tensor(N, c->prec, c->rho0_d, c->bank, BankLayout{L}.self_end(), c->A[0], c->stream);
     if (s1) (void)hipEventRecord(s1, c->stream);
@@ -2012,17 +1995,12 @@ void *g_static_ptr[kMaxStaticDevices] = {};       // the device address of `scra
 }  // namespace
 
 namespace {
-// The capacity limits of a filtered context: at least one entry, and the
-// step's outputs (segments * N <= capacity * N) counted in 32 bits.
-std::string filter_args_error(const quapi_params *p, double theta, size_t capacity) {
+// The capacity limits of a filtered context: at least one entry, and at most
+// 2^38 (a block's share of a step's outputs is counted in 32 bits).
+constexpr size_t kFilterMaxCapacity = size_t(1) << 38;
+std::string filter_args_error(double theta, size_t capacity) {
     if (!(theta >= 0.0) || !std::isfinite(theta)) return "theta must be finite and >= 0";
-    if (capacity < 1) return "capacity must be >= 1";
-    const int N = p->M * p->M;
-    if (capacity > (size_t)0xffffffffu / (size_t)N) {
-        char buf[128];
-        snprintf(buf, sizeof buf, "capacity must be <= %zu at M = %d", (size_t)0xffffffffu / (size_t)N, p->M);
-        return buf;
-    }
+    if (capacity < 1 || capacity > kFilterMaxCapacity) return "capacity must be in 1 .. 2^38";
     return "";
 }
 }  // namespace
@@ -2054,7 +2032,7 @@ quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspa
 quapi_status quapi_filtered_footprint(const quapi_params *p, size_t capacity, size_t *device_bytes) {
     const std::string msg = validate(p, kFilterMaxLog2);
     if (!msg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", msg.c_str());
-    const std::string fmsg = filter_args_error(p, 0.0, capacity);
+    const std::string fmsg = filter_args_error(0.0, capacity);
     if (!fmsg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", fmsg.c_str());
     if (!device_bytes) return fail(nullptr, QUAPI_ERR_INVALID, "device_bytes is NULL");
     *device_bytes = make_layout(*p, count_panels(*p), capacity).total;
@@ -2065,7 +2043,7 @@ quapi_status quapi_create_filtered(const quapi_params *p, double theta, size_t c
                                    quapi_ctx **out) {
     const std::string msg = validate(p, kFilterMaxLog2);
     if (!msg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", msg.c_str());
-    const std::string fmsg = filter_args_error(p, theta, capacity);
+    const std::string fmsg = filter_args_error(theta, capacity);
     if (!fmsg.empty()) return fail(nullptr, QUAPI_ERR_INVALID, "%s", fmsg.c_str());
     return create_ctx(p, hip_stream, nullptr, 0, false, out, theta, capacity);
 }
@@ -2076,11 +2054,11 @@ quapi_status quapi_filter_stats(quapi_ctx *ctx, long long *entries, int *overflo
     BusyGuard g(ctx);
     if (!g.ok) return fail(ctx, QUAPI_ERR_STATE, "context in use by another call");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    unsigned long long ctr[6] = {};
+    unsigned long long ctr[3] = {};
     HIP_TRY(ctx, hipMemcpy(ctr, ctx->fctr, sizeof ctr, hipMemcpyDeviceToHost));
     *entries = (long long)ctr[ctx->cur];
     int ov = 0;
-    std::memcpy(&ov, &ctr[5], sizeof ov);
+    std::memcpy(&ov, &ctr[2], sizeof ov);
     *overflow = ov;
     return QUAPI_OK;
 }

@@ -276,55 +276,43 @@ size_t step3_lds_bytes(int prec, bool with_rho, int R, int Q);
 size_t step2_lds_bytes(int prec, bool with_rho, int R, int Q);
 
 // Filtered propagation (quapi_filter.hip): the kept tensor entries as sorted
-// (key, value) pairs.  Fixed grids; element counts are read from device memory.
+// (key, value) pairs.  Fixed grids; the entry count is read from device memory.
 constexpr int kFilterBlock = 256;
-constexpr int kFilterStepBlocks = 2048;      // blocks of the step passes (rho partial rows)
-constexpr int kFilterScanBlocks = 1024;      // chunks of an exclusive scan
+constexpr int kFilterStepBlocks = 2048;      // blocks of the count and write passes (rho partial rows)
 // Factor-product tables of a step's digits, in levels (filter_levels of them,
-// N x filter_level_size entries each, FP64), interior and final classes.
+// filter_level_size x N entries each), every entry the FP64 pair (interior,
+// final classes).
 struct FilterPlanArgs {
     const double2 *bank;
     int N, nd, n_lv;
     int16_t tab[kMaxL], tabf[kMaxL];
-    double2 *t, *tf;
-};
-struct FilterSegArgs {
-    const unsigned long long *keys, *count;  // the step's input keys and their number
-    unsigned *flags;                         // scratch: segment heads, then their exclusive scan
-    unsigned *sums;                          // kFilterScanBlocks scan partials
-    unsigned long long *total;               // the scan total (segments)
-    unsigned *seg_start;                     // out: segment starts (count + 1)
-    unsigned long long *nseg, *nflags;       // out: segments, and segments * N
-    int full;                                // full-window step: a segment spans the oldest digit
+    double2 *t;
 };
 struct FilterStepArgs {
     const double2 *bank;
+    const unsigned long long *count_in;      // entries of the input
     const unsigned long long *keys_in;
     const void *vals_in;
     unsigned long long *keys_out;
     void *vals_out;
-    const unsigned *seg_start;
-    const unsigned long long *nseg;
-    unsigned *flags;            // counting pass: keep flags [o * nseg + s]; writing pass: their exclusive scan
-    const unsigned long long *total;     // writing pass: the scan total (the kept outputs)
-    double2 *partials;          // [kFilterStepBlocks][N] block partial sums of rho (counting pass)
-    const double2 *t, *tf;      // factor-product levels (interior, final classes)
+    unsigned short *masks;      // [entries] keep bits of a segment's N outputs, at its head entry
+    unsigned long long *bofs;   // [N][kFilterStepBlocks] kept outputs per (o, block), then their offsets
+    double2 *partials;          // [kFilterStepBlocks][N] block partial sums of rho (count pass)
+    const double2 *t;           // factor-product levels, (interior, final) pairs
     unsigned long long capacity;
     unsigned long long stride_new;   // N^(L-1) (full window) or N^n (growth step n)
     double theta;
     int full, n_lv;
     int old_tab, oldf_tab;      // oldest-point tables (full window) or self factors (growth, column 0)
 };
-size_t filter_step_lds_bytes(int N, bool rho);      // dynamic LDS of the counting pass with rho
+size_t filter_step_lds_bytes(int N, bool rho);      // dynamic LDS of the count pass with rho
 int filter_levels(int N, int n_digits);
 size_t filter_plan_entries(int N, int n_digits);
 hipError_t launch_filter_plan(const FilterPlanArgs &a, hipStream_t st);
-hipError_t launch_filter_scan(unsigned *x, const unsigned long long *n_dev, unsigned *sums,
-                              unsigned long long *total, hipStream_t st);
-hipError_t launch_filter_segments(int N, const FilterSegArgs &a, hipStream_t st);
+// count = true: keep masks, per-(o, block) counts and (rho) partials; false: the write pass.
 hipError_t launch_filter_step(int N, int prec, const FilterStepArgs &a, bool count, bool rho, hipStream_t st);
-hipError_t launch_filter_count(const unsigned long long *total, unsigned long long capacity,
-                               unsigned long long *count_out, int *overflow, hipStream_t st);
+hipError_t launch_filter_offsets(int N, unsigned long long *bofs, unsigned long long capacity,
+                                 unsigned long long *count_out, int *overflow, hipStream_t st);
 hipError_t launch_filter_init(int prec, const double2 *rho0, const double2 *bank, int self_end_tab, int N,
                               double theta, unsigned long long capacity, unsigned long long *keys, void *vals,
                               unsigned long long *count, int *overflow, hipStream_t st);
