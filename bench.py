@@ -41,6 +41,15 @@ with torch copy_ beside it.  `cpu_baseline` times the oracle (plain C,
 OpenMP, all host threads it is given) on 10 full-window steps of the same
 workload.
 
+`filtered` runs the same workload with path filtering (every tensor entry
+whose magnitude is not above theta = 1e-10 dropped as it forms; the kept
+entries stored as sorted (index, value) pairs), rho at every step, and
+reports its time per step, the kept entries, the algorithmic HBM rate of its
+step kernels ((kept in + kept out) x (key + value) bytes per step) and its
+max|drho| against the unfiltered complex128 run; `filtered_c64` the same
+with complex64 storage; `filtered_l18` the memory length L = 18
+(theta = 1e-7, 300 steps), whose two dense tensors would need 2.2 TB.
+
 `serving` replays the seeded 512-request Poisson trace of mixed requests
 (M in {2,3,4}, N^L <= 2^28, 50-1000 steps, complex64/complex128, 20
 requests/s) in real time through the continuous-batching server and reports
@@ -53,7 +62,7 @@ case of many runs that differ only in the pulse area (Sec. III quantum dot
 driven by a Gaussian pulse, 32 areas from 0 to 4 pi, rho at the last step).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tiers c128,c64,c64f64]
-                       [--serve-requests R] [--no-table1] [--no-pulse-sweep]
+                       [--serve-requests R] [--no-table1] [--no-pulse-sweep] [--no-filtered]
                        [--no-copy-ceiling] [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -243,6 +252,79 @@ def copy_ceiling(nbytes: int = 2 ** 34):
             "note": "16 GiB copied; bytes counted as one read plus one write"}
 
 
+def filtered_run(w, theta: float, dtype: str = "c128", total_steps: int = None, window: int = 50,
+                 capacity: int = 2 ** 30, rho_ref=None):
+    """Path-filtered propagation (entries not above theta dropped as they form)
+    of workload w: growth, then the full-window steps in windows of `window`
+    steps with rho at every step.  Reports the wall time per full-window step,
+    the step kernels' time (HIP events around the count, offsets and write
+    launches), the kept entries, and the step's algorithmic HBM rate: every
+    kept input entry read once and every kept output written once, key and
+    value, (n_in + n_out) (8 + sizeof(complex)) bytes per step.  With rho_ref
+    (the unfiltered complex128 rho of the same run), the filter's error."""
+    import numpy as np
+    import torch
+    from paper_1205_6872_amd import quapi as Q
+    total_steps = total_steps or w.n_steps
+    csize = 16 if dtype == "c128" else 8
+    p = Q.params_from(w, dtype=dtype)
+    footprint = Q.filtered_footprint(p, capacity)
+    ctx = Q.create_filtered(p, theta, capacity)
+    try:
+        rho = [ctx.propagate(0, [0])]
+        rho.append(ctx.propagate(w.L))                 # growth steps and the first full-window step
+        n_prev = ctx.filter_stats()[0]
+        kept_after_growth = n_prev
+        ctx.set_timing(True)
+        ctx.get_timing()
+        overflow = 0
+        wall = kern = alg = 0.0
+        steps = 0
+        kept_max = n_prev
+        while ctx.step_count() < total_steps:
+            k = min(window, total_steps - ctx.step_count())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rho.append(ctx.propagate(k))
+            wall += time.perf_counter() - t0
+            tm = ctx.get_timing()
+            n_now, overflow = ctx.filter_stats()
+            if overflow:
+                break
+            kern += tm["step_ms"]
+            alg += k * (n_prev + n_now) * (8 + csize)      # n_prev .. n_now: linear over the window
+            steps += k
+            kept_max = max(kept_max, n_now)
+            n_prev = n_now
+    finally:
+        ctx.destroy()
+    rho = np.concatenate(rho)
+    ms_step = wall * 1e3 / max(steps, 1)
+    kernel_ms = kern / max(steps, 1)
+    achieved = alg / max(steps, 1) / (kernel_ms * 1e-3) / 1e9 if steps else 0.0
+    out = {"workload": f"{w.name} physics at L = {w.L}, {dtype}, theta = {theta:g}, rho every step",
+           "dtype": "f64" if dtype == "c128" else "f32", "theta": theta, "L": w.L, "M": w.M,
+           "dense_entries": w.N ** w.L, "steps_timed": steps, "timed_steps": [w.L + 1, total_steps],
+           "kept_after_growth": int(kept_after_growth), "kept_final": int(n_prev), "kept_max": int(kept_max),
+           "kept_fraction_final": n_prev / w.N ** w.L, "ms_per_step": round(ms_step, 4),
+           "kernel_ms_per_step": round(kernel_ms, 4),
+           "dense_equivalent_gelem_s": round(w.N ** w.L * steps / max(wall, 1e-12) / 1e9, 3),
+           "kept_gelem_s": round(alg / (2 * (8 + csize)) / max(wall, 1e-12) / 1e9, 3),
+           "device_bytes": footprint, "capacity": capacity, "overflow": bool(overflow),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "filter_step_kernel count + filter_offsets_kernel + filter_step_kernel write",
+                        "definition": ("(kept input + kept output entries) x (8-byte key + value) per step / "
+                                       "the step kernels' mean time / 8 TB/s")}}
+    if rho_ref is not None:
+        # rho_ref starts at step 1, rho at step 0
+        n = min(len(rho) - 1, len(rho_ref))
+        out["max_abs_drho_vs_unfiltered_c128"] = float(np.abs(rho[1:n + 1] - rho_ref[:n]).max())
+        out["max_trace_err"] = float(np.abs(np.trace(rho[1:n + 1], axis1=1, axis2=2) - 1).max())
+        out["steps_compared"] = n
+    return out
+
+
 def serve_trace(n_requests: int, policy: str = "sjf", chunk_ms=8.0, chunk_steps: int = 32):
     """Serve the first n_requests of the seeded 512-request trace in real time."""
     from paper_1205_6872_amd import workloads as W
@@ -326,6 +408,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-table1", action="store_true", help="skip the paper's Table 1 sweep")
     ap.add_argument("--no-pulse-sweep", action="store_true", help="skip the pulse-area sweep")
+    ap.add_argument("--no-filtered", action="store_true", help="skip the path-filtered runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
@@ -390,6 +473,13 @@ def main() -> int:
             "max_abs_drho_vs_f64": d, "trace_drift_vs_f64": drift, "steps_compared": len(a["rho"]),
             "targets": {"max_abs_drho": 1e-5, "trace_drift": 1e-6},
         }
+    if not args.no_filtered:
+        log("bench: path-filtered runs (theta = 1e-10 at L = 15; theta = 1e-7 at L = 18, beyond dense memory)")
+        ref = res["c128"]["rho"] if "c128" in res else None
+        out["filtered"] = filtered_run(w, 1e-10, "c128", total, capacity=2 ** 28, rho_ref=ref)
+        out["filtered_c64"] = filtered_run(w, 1e-10, "c64", total, capacity=2 ** 28, rho_ref=ref)
+        out["filtered_l18"] = filtered_run(w.with_(L=18), 1e-7, "c128", min(total, 300), capacity=2 ** 26)
+        out["filtered_l18"]["dense_bytes_needed"] = 2 * w.N ** 18 * 16
     if not args.no_copy_ceiling:
         out["copy_ceiling"] = copy_ceiling()
     if args.serve_requests > 0:

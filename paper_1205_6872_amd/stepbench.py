@@ -3,6 +3,7 @@
     python3 -m paper_1205_6872_amd.stepbench [--cases M:L,...] [--dtypes c128,c64,c64f64] [--steps K]
                                              [--fused-steps 1,2,3] [--mirror on,off]
     python3 -m paper_1205_6872_amd.stepbench --paper-table1
+    python3 -m paper_1205_6872_amd.stepbench --filtered L:theta,... [--dtypes ..] [--steps K]
 
 For each case (M levels, memory length L) and storage/arithmetic mode it runs
 the growth steps, then K full-window steps with rho at every step and K
@@ -13,7 +14,12 @@ mode, and the step-equivalent rate 2 * N^L * sizeof(complex) per step (the
 bytes of one full-tensor step).  --fused-steps pins the width, --mirror the
 mode (on: at every size).  The system is a seeded random Hermitian H with
 evenly spaced coupling eigenvalues and an Ohmic bath (xi = 0.3,
-omega_c = 7.5, kT = 0.2, dt = 0.25).
+omega_c = 7.5, kT = 0.2, dt = 0.25).  --filtered runs the spin-boson
+workload of the M = 2, L = 15 benchmark (xi = 0.5, omega_c = 10, kT = 0.05,
+dt = 0.1) at memory length L with path filtering at threshold theta: the
+growth steps, then K full-window steps with rho at every step, and prints
+the mean step time (the count, offsets and write launches) and the kept
+entries before and after.
 """
 from __future__ import annotations
 
@@ -101,6 +107,24 @@ def paper_table1(dks=range(2, 16), main_steps: int = 989, dt: float = 0.25, dtyp
     return rows
 
 
+def time_filtered(L: int, theta: float, dtype: str, steps: int) -> dict:
+    w = W.spin_boson_l15(dtype).with_(L=L)
+    cap = min(w.N ** L, 2 ** 28)
+    with Q.create_filtered(Q.params_from(w, dtype=dtype), theta, cap) as ctx:
+        ctx.propagate(L)
+        n0 = ctx.filter_stats()[0]
+        ctx.set_timing(True)
+        ctx.get_timing()
+        ctx.propagate(steps)
+        tm = ctx.get_timing()
+        n1, overflow = ctx.filter_stats()
+    ms = tm["step_ms"] / max(tm["step_launches"], 1)
+    cs = 16 if dtype == "c128" else 8
+    return {"case": f"spin_boson_l15 physics, L = {L}, theta = {theta:g}", "dtype": dtype, "steps": steps,
+            "kept_before": n0, "kept_after": n1, "overflow": bool(overflow), "step_ms": round(ms, 4),
+            "alg_gbs": round((n0 + n1) * (8 + cs) / (ms * 1e-3) / 1e9, 1)}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--cases", default="4:7,3:8,2:12")
@@ -110,7 +134,14 @@ def main(argv=None) -> int:
     ap.add_argument("--mirror", default="default", help="comma list of on (every size) / off / default")
     ap.add_argument("--paper-table1", action="store_true",
                     help="the paper's Table 1 sweep (its model system, dk = 2..15, 989 main steps)")
+    ap.add_argument("--filtered", default="", help="comma list of L:theta (path-filtered runs)")
     args = ap.parse_args(argv)
+    if args.filtered:
+        for c in args.filtered.split(","):
+            L, th = c.split(":")
+            for d in args.dtypes.split(","):
+                print(json.dumps(time_filtered(int(L), float(th), d, args.steps)), flush=True)
+        return 0
     if args.paper_table1:
         for row in paper_table1():
             print(json.dumps(row), flush=True)
