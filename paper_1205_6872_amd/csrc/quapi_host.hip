@@ -289,7 +289,8 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_Ht, off_Ut, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
-    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_blk2, off_blk1, off_pairs, off_sink;
+    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_low3, off_blk2, off_blk1, off_pairs,
+        off_sink;
     // filtered contexts: keys and values of the two tensors, flags, segment
     // starts, scan partials, counters, rho partials, factor-level tables
     size_t off_fkeys[2], off_fvals[2], off_fmask, off_fbofs, off_fctr, off_fpart, off_fplan;
@@ -297,6 +298,7 @@ struct Layout {
     size_t total;
     int n_panels, n_tables, partial_blocks;
     int n_canon3, n_diag3, parts3, span3;   // mirror mode of the three-step kernel (high-digit blocks)
+    int n_low3;                             // items of a block below their mirror (mode 2's list)
     int n_canon2, n_diag2, parts2, span2;   // mirror mode of the two-step kernel
     int n_canon1, n_diag1, parts1, span1;   // mirror mode of the single step (main split)
     DigitSplit main_split;   // digit split of the full-window steps
@@ -306,13 +308,12 @@ struct Layout {
 
 constexpr int kSlots = 4;    // rho partial buffers: a fused launch takes two
 
-// The three-step mirror launches run modes 2, 3 concurrently with mode 1 with
-// FP32 arithmetic from 2^28 entries (measured on one GPU, the same build with
-// and without: L = 15 complex64 1.88 -> 1.84 ms per launch; complex128 no
-// gain, 3.62 -> 3.64 ms; below 2^28 entries the fork and join cost more than
-// they hide).
+// The three-step mirror launch of the self-mirror items (mode 3) runs
+// concurrently with the mode-1 launch from 2^28 entries, in its tail (below
+// 2^28 entries the fork and join cost more than they hide).
 bool step3_concurrent(size_t entries, int prec) {
-    return prec == kPrecC64 && entries >= (size_t(1) << 28);
+    (void)prec;
+    return entries >= (size_t(1) << 28);
 }
 
 // Blocks per high-digit value in mirror mode 2: about one block per compute
@@ -354,15 +355,14 @@ Layout make_layout(const quapi_params &p, int n_panels, size_t filter_cap = 0) {
             if (h < hb) ++l.n_canon3;
             else if (h == hb) ++l.n_diag3;
         }
-        // mode 2: run alone (below 2^28 entries), its blocks are latency
-        // bound, so each value's sweep is split into enough blocks for about
-        // one per compute unit; run concurrently with mode 1, fewer longer
-        // blocks (about four sweep rows per thread) cost less setup
-        const int rows_per_pass = kBlock / s3.R;
-        const int passes = (s3.Q + rows_per_pass - 1) / rows_per_pass;
-        l.parts3 = step3_concurrent(entries, p.dtype == QUAPI_C64 ? kPrecC64 : kPrecC128)
-                       ? (passes + 3) / 4 : mirror_parts(passes, l.n_diag3);
-        l.span3 = ((passes + l.parts3 - 1) / l.parts3) * rows_per_pass;
+        // the blocks of the diagonal values walk the list of a block's items
+        // below their mirror, one item per thread, two passes per block, as
+        // the tail of the mode-1 launch
+        for (int low = 0; low < s3.R * s3.Q; ++low)
+            if (mirror4(low) > low) ++l.n_low3;
+        const int passes = (l.n_low3 + kBlock - 1) / kBlock;
+        l.parts3 = std::max(1, (passes + 1) / 2);
+        l.span3 = ((passes + l.parts3 - 1) / l.parts3) * kBlock;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon3 + l.n_diag3 * (l.parts3 + 1));
     }
     if (!filtered && fused_ok(N, L)) {
@@ -439,6 +439,7 @@ Layout make_layout(const quapi_params &p, int n_panels, size_t filter_cap = 0) {
     l.off_plan3 = take(triple ? (size_t)6 * N * (s3.R + s3.Q + s3.grid) * 16 : 0);
     l.off_coef3 = take(triple ? (size_t)kC3Count * 16 : 0);
     l.off_blk3 = take(triple ? (size_t)(l.n_canon3 + l.n_diag3) * sizeof(int) : 0);
+    l.off_low3 = take(triple ? (size_t)l.n_low3 * sizeof(int) : 0);
     l.off_blk2 = take((size_t)(l.n_canon2 + l.n_diag2) * sizeof(int));
     l.off_blk1 = take((size_t)(l.n_canon1 + l.n_diag1) * sizeof(int));
     const size_t fc = filtered ? filter_cap : 0;
@@ -522,6 +523,8 @@ struct quapi_ctx {
     bool half_cur = false;
     int *blk3 = nullptr;          // high-digit values: n_canon3 below their mirror, then n_diag3 equal
     std::vector<int> blk3_h;
+    int *low3 = nullptr;          // mode 2's list of the items qm * R + r below their mirror
+    std::vector<int> low3_h;
     int *blk2 = nullptr;          // the same for the two-step kernel (n_canon2, n_diag2)
     std::vector<int> blk2_h;
     int *blk1 = nullptr;          // the same for the single step (n_canon1, n_diag1)
@@ -1215,11 +1218,15 @@ hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows, bo
     const bool fork = concurrent && l.n_diag3 > 0 && l.n_canon3 > 0;
     hipStream_t small = fork ? c->aux : c->stream;
     auto mode1 = [&]() {
-        if (e == hipSuccess && l.n_canon3 > 0) {
+        if (e == hipSuccess && l.n_canon3 + l.n_diag3 > 0) {
             a.mode = 1;
             a.blk_hi = c->blk3;
-            a.n_blk = l.n_canon3;
-            a.parts = 1;
+            a.n_canon = l.n_canon3;
+            a.low_list = c->low3;
+            a.n_low = l.n_low3;
+            a.n_blk = l.n_canon3 + l.n_diag3 * l.parts3;
+            a.parts = l.parts3;
+            a.q_span = l.span3;
             a.part_base = 0;
             e = launch_step3(c->prec, rho, a, c->stream);
         }
@@ -1229,15 +1236,6 @@ hipError_t launch_step3_modes(quapi_ctx *c, bool rho, Step3Args a, int *rows, bo
         if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
     } else {
         mode1();                                  // one stream: the large launch first
-    }
-    if (e == hipSuccess && l.n_diag3 > 0) {
-        a.mode = 2;
-        a.blk_hi = c->blk3 + l.n_canon3;
-        a.n_blk = l.n_diag3 * l.parts3;
-        a.parts = l.parts3;
-        a.q_span = l.span3;
-        a.part_base = l.n_canon3;
-        e = launch_step3(c->prec, rho, a, small);
     }
     if (e == hipSuccess && l.n_diag3 > 0) {
         a.mode = 3;
@@ -1803,6 +1801,7 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
     c->plan3 = (double2 *)(w + lay.off_plan3);
     c->coef3 = w + lay.off_coef3;
     c->blk3 = (int *)(w + lay.off_blk3);
+    c->low3 = (int *)(w + lay.off_low3);
     c->blk2 = (int *)(w + lay.off_blk2);
     c->blk1 = (int *)(w + lay.off_blk1);
     c->n_H = p->n_H;
@@ -1845,6 +1844,8 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
             for (int pass = 0; pass < 2; ++pass)
                 for (int h = 0; h < lay.split3.grid; ++h)
                     if (pass == 0 ? h < mirror4(h) : h == mirror4(h)) c->blk3_h.push_back(h);
+            for (int low = 0; low < lay.split3.R * lay.split3.Q; ++low)
+                if (mirror4(low) > low) c->low3_h.push_back(low);
             c->mirror_ok = herm;
         }
         if (fused_ok(N, L) && !filtered) {
@@ -1896,6 +1897,8 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
     if (e == hipSuccess && c->n_H > 0) e = up(lay.off_Ht, c->Ht_h.data(), c->Ht_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_rho0, c->rho0_h.data(), (size_t)N * 16);
     if (e == hipSuccess && !c->blk3_h.empty()) e = up(lay.off_blk3, c->blk3_h.data(), c->blk3_h.size() * sizeof(int));
+    if (e == hipSuccess && (int)c->low3_h.size() != lay.n_low3) e = hipErrorInvalidValue;
+    if (e == hipSuccess && !c->low3_h.empty()) e = up(lay.off_low3, c->low3_h.data(), c->low3_h.size() * sizeof(int));
     if (e == hipSuccess && !c->blk2_h.empty()) e = up(lay.off_blk2, c->blk2_h.data(), c->blk2_h.size() * sizeof(int));
     if (e == hipSuccess && !c->blk1_h.empty()) e = up(lay.off_blk1, c->blk1_h.data(), c->blk1_h.size() * sizeof(int));
     if (e == hipSuccess) e = up(lay.off_pa, c->pa_h.data(), c->pa_h.size() * 8);

@@ -126,16 +126,19 @@ struct Step3Args {
     long long m_count;
     int R, Q, grid;
     const void *coef;           // kC3Count complex entries in the compute precision
-    // Mirror mode (half of the tensor), three launches over high-digit values
-    // blk_hi[..]: mode 1 the values below their mirror (every item below its
-    // mirror), one block each; mode 2 the values equal to their mirror (all
-    // digits diagonal), each split into `parts` blocks of q_span sweep rows,
-    // n_blk = values * parts, running the items below their mirror; mode 3
-    // the same values, one block each, running the items that are their own
-    // mirror.  rho partials go to row part_base + block.  Mode 0 runs every
-    // block of the grid.
+    // Mirror mode (half of the tensor), two launches over high-digit values
+    // blk_hi[..] (n_canon values below their mirror, then those equal to it,
+    // all digits diagonal): mode 1 one block per value below its mirror
+    // (every item below its mirror), then `parts` blocks per value equal to
+    // it, each running q_span items of low_list (the n_low item indices
+    // qm * R + r below their mirror, the same list for every such value):
+    // n_blk = n_canon + values * parts; mode 3 (blk_hi from the equal
+    // values) one block per value equal to its mirror, running the items
+    // that are their own mirror.  rho partials go to row part_base + block.
+    // Mode 0 runs every block of the grid.
     const int *blk_hi;
-    int n_blk, parts, q_span, part_base, mode;
+    const int *low_list;
+    int n_blk, n_canon, parts, q_span, part_base, mode, n_low;
 };
 
 // The mirror of an entry (N = 4, M = 2): every digit o = (a, b) -> (b, a),

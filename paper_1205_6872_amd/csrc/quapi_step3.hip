@@ -94,17 +94,22 @@ __global__ void step3_coef_kernel(const Coef3Args a) {
 // (slot o + N o' + N^2 i'').  With RHO, rho at each of the three steps comes
 // from the values that stage reads, with the final-point classes.
 //
-// MODE 1, 2, 3 (mirror mode): an entry and its mirror are conjugates, so
+// MODE 1, 3 (mirror mode): an entry and its mirror are conjugates, so
 // only the items m not above their mirror mb are run, and of each output
 // entry only the one not above its mirror is stored (the conjugate goes to
 // the mirrored address).  Only those entries of the input need be valid: an
 // item that is its own mirror (all digits diagonal) takes its other entries
 // as the conjugates of theirs.  rho gets each item's terms and, for the
 // mirrored item that is not run, their conjugates at the mirrored point.
-// Mode 1 runs the blocks whose high digits are below their mirror, where
-// every item is below its mirror; mode 2 the few blocks whose high digits are
-// all diagonal, skipping the items not below their mirror; mode 3, one block
-// per such high-digit value, the items that are their own mirror.  So each
+// Mode 1 runs every item below its mirror: first the blocks whose high
+// digits are below their mirror (all their items), then, as the tail of the
+// same launch, the blocks of the high-digit values that are all diagonal,
+// which walk the list of the items below their mirror (one per thread, so
+// no lane idles: as a launch of its own with the other items skipped, this
+// part took 0.17 ms of the 3.64 ms complex128 pass at L = 15; in the tail of
+// the mode-1 launch it adds about 0.06 ms).  Mode 3, one block per diagonal
+// high-digit value, runs the items that are their own mirror, from 2^28
+// entries on a second stream, concurrently with the tail of mode 1.  Each
 // mode knows at compile time which of the cases it handles.
 __device__ __forceinline__ constexpr int mirror_digit(int d) { return d == 1 ? 2 : d == 2 ? 1 : d; }
 // The item digits whose bits are those of x: bit i -> digit i = 3 (else 0).
@@ -143,9 +148,14 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 2 : 1) step3_kernel(c
     const int t = threadIdx.x;
     const int cR = kBlock / R, active = cR * R;
     // high digits of m
-    const long long blk = MODE == 0   ? (long long)blockIdx.x
-                          : MODE == 2 ? (long long)a.blk_hi[blockIdx.x / a.parts]
-                                      : (long long)a.blk_hi[blockIdx.x];
+    // mode 1: blocks below n_canon run the canonical high-digit values (every
+    // item below its mirror), the rest the listed items of the values that
+    // are their own mirror, `parts` blocks per value (block-uniform)
+    const bool listed = MODE == 1 && (int)blockIdx.x >= a.n_canon;
+    const int lblk = listed ? (int)blockIdx.x - a.n_canon : 0;
+    const long long blk = MODE == 0 ? (long long)blockIdx.x
+                          : listed  ? (long long)a.blk_hi[a.n_canon + lblk / a.parts]
+                                    : (long long)a.blk_hi[blockIdx.x];
     if (t < NS * N) {
         const int s = t / N, o = t % N;
         s_phi[t] = a.t_hi[s][(size_t)o * a.grid + blk];
@@ -203,20 +213,23 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 2 : 1) step3_kernel(c
         // them in mode 2; in mode 3 the items with all digits diagonal, whose
         // bits give the low and the sweep digits
         const int dl = (31 - __clz(R)) >> 1, dm = (31 - __clz(Q)) >> 1;
-        const int part = MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
-        const int i0 = MODE == 3 ? t : MODE == 2 ? part * a.q_span + t / R : t / R;
-        const int i1 = MODE == 3 ? (1 << (dl + dm)) : MODE == 2 ? min(Q, (part + 1) * a.q_span) : Q;
-        const int istep = MODE == 3 ? kBlock : cR;
+        // a listed block walks the list of the items below their mirror (the
+        // same for every high-digit value that is its own mirror), q_span of
+        // them per block, one per thread: every lane has an item
+        const int part = listed ? lblk % a.parts : 0;
+        const int i0 = MODE == 3 ? t : listed ? part * a.q_span + t : t / R;
+        const int i1 = MODE == 3 ? (1 << (dl + dm)) : listed ? min(a.n_low, (part + 1) * a.q_span) : Q;
+        const int istep = MODE == 3 || listed ? kBlock : cR;
         for (int it = i0; it < i1; it += istep) {
             asm volatile("" ::: "memory");
-            int r = MODE == 3 ? diagonal_digits((unsigned)it & ((1u << dl) - 1)) : t % R;
+            const int low = listed ? a.low_list[it] : 0;
+            int r = MODE == 3 ? diagonal_digits((unsigned)it & ((1u << dl) - 1)) : listed ? low & (R - 1) : t % R;
             // opaque per item: the factor reads from LDS below stay in the loop
             // instead of being hoisted (and, short of registers, spilled)
             asm volatile("" : "+v"(r));
-            const int qm = MODE == 3 ? diagonal_digits((unsigned)it >> dl) : it;
+            const int qm = MODE == 3 ? diagonal_digits((unsigned)it >> dl) : listed ? low / R : it;
             const long long m = m0 + (long long)qm * R + r;
             const long long mb = HALF ? mirror4(m) : m;
-            if (MODE == 2 && mb <= m) continue;   // own mirror (mode 3), or run by its mirror
             constexpr bool selfm = MODE == 3;
             // an item that is its own mirror holds valid values only at the
             // slots not above their mirror: the others are their mirrors' conjugates
@@ -469,8 +482,6 @@ hipError_t launch_step3_t(const Step3Args &a, hipStream_t st) {
     const Step3Lds lay = step3_lds_layout((int)sizeof(C), RHO, a.R, a.Q);
     if (a.mode == 1)
         hipLaunchKernelGGL((step3_kernel<S, T, RHO, 1>), dim3(a.n_blk), dim3(kBlock), lay.total, st, a);
-    else if (a.mode == 2)
-        hipLaunchKernelGGL((step3_kernel<S, T, RHO, 2>), dim3(a.n_blk), dim3(kBlock), lay.total, st, a);
     else if (a.mode == 3)
         hipLaunchKernelGGL((step3_kernel<S, T, RHO, 3>), dim3(a.n_blk), dim3(kBlock), lay.total, st, a);
     else
