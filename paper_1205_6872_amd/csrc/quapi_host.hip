@@ -289,8 +289,8 @@ struct Layout {
     size_t a_bytes;                  // one tensor buffer
     size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_Ht, off_Ut, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
-    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_low3, off_blk2, off_blk1, off_pairs,
-        off_sink;
+    size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_low3, off_blk2, off_low2, off_blk1,
+        off_pairs, off_sink;
     // filtered contexts: keys and values of the two tensors, flags, segment
     // starts, scan partials, counters, rho partials, factor-level tables
     size_t off_fkeys[2], off_fvals[2], off_fmask, off_fbofs, off_fctr, off_fpart, off_fplan;
@@ -300,6 +300,7 @@ struct Layout {
     int n_canon3, n_diag3, parts3, span3;   // mirror mode of the three-step kernel (high-digit blocks)
     int n_low3;                             // items of a block below their mirror (mode 2's list)
     int n_canon2, n_diag2, parts2, span2;   // mirror mode of the two-step kernel
+    int n_low2;                             // items of a block below their mirror (its list)
     int n_canon1, n_diag1, parts1, span1;   // mirror mode of the single step (main split)
     DigitSplit main_split;   // digit split of the full-window steps
     DigitSplit split2;       // digit split of the fused two-step kernel
@@ -373,10 +374,11 @@ Layout make_layout(const quapi_params &p, int n_panels, size_t filter_cap = 0) {
             if (h < hb) ++l.n_canon2;
             else if (h == hb) ++l.n_diag2;
         }
-        const int rows_per_pass = kBlock / s2.R;
-        const int passes = (s2.Q + rows_per_pass - 1) / rows_per_pass;
-        l.parts2 = mirror_parts(passes, l.n_diag2);
-        l.span2 = ((passes + l.parts2 - 1) / l.parts2) * rows_per_pass;
+        for (int low = 0; low < s2.R * s2.Q; ++low)
+            if (mirror4(low) > low) ++l.n_low2;
+        const int passes = (l.n_low2 + kBlock - 1) / kBlock;
+        l.parts2 = std::max(1, (passes + 1) / 2);
+        l.span2 = ((passes + l.parts2 - 1) / l.parts2) * kBlock;
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon2 + l.n_diag2 * (l.parts2 + 1));
     }
     if (!filtered && single_mirror_ok(N, L, l.main_split)) {
@@ -441,6 +443,7 @@ Layout make_layout(const quapi_params &p, int n_panels, size_t filter_cap = 0) {
     l.off_blk3 = take(triple ? (size_t)(l.n_canon3 + l.n_diag3) * sizeof(int) : 0);
     l.off_low3 = take(triple ? (size_t)l.n_low3 * sizeof(int) : 0);
     l.off_blk2 = take((size_t)(l.n_canon2 + l.n_diag2) * sizeof(int));
+    l.off_low2 = take((size_t)l.n_low2 * sizeof(int));
     l.off_blk1 = take((size_t)(l.n_canon1 + l.n_diag1) * sizeof(int));
     const size_t fc = filtered ? filter_cap : 0;
     for (int b = 0; b < 2; ++b) {
@@ -527,6 +530,8 @@ struct quapi_ctx {
     std::vector<int> low3_h;
     int *blk2 = nullptr;          // the same for the two-step kernel (n_canon2, n_diag2)
     std::vector<int> blk2_h;
+    int *low2 = nullptr;          // its list of the items below their mirror
+    std::vector<int> low2_h;
     int *blk1 = nullptr;          // the same for the single step (n_canon1, n_diag1)
     std::vector<int> blk1_h;
     double2 *plan3 = nullptr;
@@ -1048,21 +1053,17 @@ hipError_t launch_step2_modes(quapi_ctx *c, bool rho, Step2Args a, int *rows) {
     }
     const Layout &l = c->lay;
     hipError_t e = hipSuccess;
-    if (l.n_canon2 > 0) {
+    if (l.n_canon2 + l.n_diag2 > 0) {
+        // the canonical blocks, then the listed items of the diagonal values
         a.mode = 1;
         a.blk_hi = c->blk2;
-        a.n_blk = l.n_canon2;
-        a.parts = 1;
-        a.part_base = 0;
-        e = launch_step2(c->prec, rho, a, c->stream);
-    }
-    if (e == hipSuccess && l.n_diag2 > 0) {
-        a.mode = 2;
-        a.blk_hi = c->blk2 + l.n_canon2;
-        a.n_blk = l.n_diag2 * l.parts2;
+        a.n_canon = l.n_canon2;
+        a.low_list = c->low2;
+        a.n_low = l.n_low2;
+        a.n_blk = l.n_canon2 + l.n_diag2 * l.parts2;
         a.parts = l.parts2;
         a.q_span = l.span2;
-        a.part_base = l.n_canon2;
+        a.part_base = 0;
         e = launch_step2(c->prec, rho, a, c->stream);
     }
     if (e == hipSuccess && l.n_diag2 > 0) {
@@ -1803,6 +1804,7 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
     c->blk3 = (int *)(w + lay.off_blk3);
     c->low3 = (int *)(w + lay.off_low3);
     c->blk2 = (int *)(w + lay.off_blk2);
+    c->low2 = (int *)(w + lay.off_low2);
     c->blk1 = (int *)(w + lay.off_blk1);
     c->n_H = p->n_H;
     c->Ht_d = (const double2 *)(w + lay.off_Ht);
@@ -1852,6 +1854,8 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
             for (int pass = 0; pass < 2; ++pass)
                 for (int h = 0; h < lay.split2.grid; ++h)
                     if (pass == 0 ? h < mirror4(h) : h == mirror4(h)) c->blk2_h.push_back(h);
+            for (int low = 0; low < lay.split2.R * lay.split2.Q; ++low)
+                if (mirror4(low) > low) c->low2_h.push_back(low);
         }
         if (single_mirror_ok(N, L, lay.main_split) && !filtered) {
             for (int pass = 0; pass < 2; ++pass)
@@ -1900,6 +1904,8 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
     if (e == hipSuccess && (int)c->low3_h.size() != lay.n_low3) e = hipErrorInvalidValue;
     if (e == hipSuccess && !c->low3_h.empty()) e = up(lay.off_low3, c->low3_h.data(), c->low3_h.size() * sizeof(int));
     if (e == hipSuccess && !c->blk2_h.empty()) e = up(lay.off_blk2, c->blk2_h.data(), c->blk2_h.size() * sizeof(int));
+    if (e == hipSuccess && (int)c->low2_h.size() != lay.n_low2) e = hipErrorInvalidValue;
+    if (e == hipSuccess && !c->low2_h.empty()) e = up(lay.off_low2, c->low2_h.data(), c->low2_h.size() * sizeof(int));
     if (e == hipSuccess && !c->blk1_h.empty()) e = up(lay.off_blk1, c->blk1_h.data(), c->blk1_h.size() * sizeof(int));
     if (e == hipSuccess) e = up(lay.off_pa, c->pa_h.data(), c->pa_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_ph, c->ph_h.data(), c->ph_h.size() * 8);

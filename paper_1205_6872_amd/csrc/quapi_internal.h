@@ -87,10 +87,12 @@ struct Step2Args {
     long long m_count;
     int R, Q, grid;
     const void *coef;           // kCoefCount complex entries in the compute precision
-    // Mirror mode, as for the three-step kernel (Step3Args): modes 1, 2, 3
-    // over the high-digit values blk_hi[..]; rho partials at part_base + block.
+    // Mirror mode, as for the three-step kernel (Step3Args): modes 1 (with
+    // the listed items of the diagonal values as its tail) and 3 over the
+    // high-digit values blk_hi[..]; rho partials at part_base + block.
     const int *blk_hi;
-    int n_blk, parts, q_span, part_base, mode;
+    const int *low_list;
+    int n_blk, n_canon, parts, q_span, part_base, mode, n_low;
 };
 
 // Coefficients of the fused step in the compute precision, grouped by the new

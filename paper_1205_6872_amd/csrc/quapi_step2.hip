@@ -62,14 +62,16 @@ __global__ void step2_coef_kernel(const CoefArgs a) {
 // The coefficients that do not depend on m are read per use through scalar
 // loads; the m-dependent digit products come from LDS.
 //
-// MODE 1, 2, 3: mirror mode, as in the three-step kernel (an entry and its
+// MODE 1, 3: mirror mode, as in the three-step kernel (an entry and its
 // mirror, every digit 2a + b -> 2b + a, are conjugates): mode 1 the blocks
-// whose high digits are below their mirror; mode 2 those equal to it, the
-// items below their mirror; mode 3 the items that are their own mirror,
-// whose input slots above the mirror are read from the mirrored slot,
-// conjugated.  Outputs above their mirror go, conjugated, to the mirrored
-// address; each block adds the mirrored items' rho terms as
-// S[o] + conj(S[mirror(o)]) (modes 1, 2).
+// whose high digits are below their mirror and then, as the tail of the same
+// launch, blocks of the high-digit values equal to it, which take the items
+// below their mirror from a list, one per thread (as a launch of its own
+// with the other items skipped this part took 0.058 ms of a 1.88 ms pass at
+// L = 15); mode 3 the items that are their own mirror, whose input slots
+// above the mirror are read from the mirrored slot, conjugated.  Outputs
+// above their mirror go, conjugated, to the mirrored address; each block
+// adds the mirrored items' rho terms as S[o] + conj(S[mirror(o)]) (mode 1).
 __device__ __forceinline__ constexpr int mirror_digit4(int d) { return d == 1 ? 2 : d == 2 ? 1 : d; }
 __device__ __forceinline__ int diagonal_digits4(unsigned x) {    // bit k -> digit k = 3
     int out = 0;
@@ -98,9 +100,13 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
 
     const int t = threadIdx.x;
     const int cR = kBlock / R, active = cR * R;
-    const long long blk = MODE == 0   ? (long long)blockIdx.x
-                          : MODE == 2 ? (long long)a.blk_hi[blockIdx.x / a.parts]
-                                      : (long long)a.blk_hi[blockIdx.x];     // high digits
+    // mode 1: blocks below n_canon run the canonical high-digit values, the
+    // rest the listed items of the values equal to their mirror (block-uniform)
+    const bool listed = MODE == 1 && (int)blockIdx.x >= a.n_canon;
+    const int lblk = listed ? (int)blockIdx.x - a.n_canon : 0;
+    const long long blk = MODE == 0 ? (long long)blockIdx.x
+                          : listed  ? (long long)a.blk_hi[a.n_canon + lblk / a.parts]
+                                    : (long long)a.blk_hi[blockIdx.x];     // high digits
     if (t < NS * N) {
         const int s = t / N, o = t % N;
         s_phi[t] = a.t_hi[s][(size_t)o * a.grid + blk];
@@ -125,23 +131,25 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
         const CS *__restrict__ ain = (const CS *)a.a_in;
         CS *__restrict__ aout = (CS *)a.a_out;
         const long long mc = a.m_count;
-        // sweep rows: all (mode 0, 1), a part (mode 2), or in mode 3 those whose
-        // digits are all diagonal, for threads whose low digits are
-        const int part = MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
+        // sweep rows: all (mode 0, 1), the listed items (q_span of them per
+        // block, one per thread), or in mode 3 those whose digits are all
+        // diagonal, for threads whose low digits are
+        const int part = listed ? lblk % a.parts : 0;
         const bool thread_runs = MODE != 3 || diagonal_digits_only4(r);
         const int dm = (31 - __clz(Q)) >> 1;
-        const int i0 = (MODE == 2 ? part * a.q_span : 0) + t / R;
-        const int i1 = !thread_runs ? 0 : MODE == 3 ? (1 << dm) : MODE == 2 ? min(Q, (part + 1) * a.q_span) : Q;
-        for (int it = i0; it < i1; it += cR) {
+        const int i0 = listed ? part * a.q_span + t : t / R;
+        const int i1 = !thread_runs ? 0 : MODE == 3 ? (1 << dm) : listed ? min(a.n_low, (part + 1) * a.q_span) : Q;
+        const int istep = listed ? kBlock : cR;
+        for (int it = i0; it < i1; it += istep) {
             asm volatile("" ::: "memory");
-            const int qm = MODE == 3 ? diagonal_digits4((unsigned)it) : it;
-            const long long m = m0 + (long long)qm * R + r;
+            const int low = listed ? a.low_list[it] : 0;
+            const int qm = MODE == 3 ? diagonal_digits4((unsigned)it) : listed ? low / R : it;
             // opaque per item: the factor reads from LDS stay in the loop
             // instead of being hoisted into registers for the whole block
-            int rl = r;
+            int rl = listed ? low & (R - 1) : r;
             asm volatile("" : "+v"(rl));
+            const long long m = m0 + (long long)qm * R + rl;
             const long long mb = MODE == 0 ? m : mirror4(m);
-            if (MODE == 2 && mb <= m) continue;   // own mirror (mode 3), or run by its mirror
             constexpr bool selfm = MODE == 3;
             C x[NN];
 #pragma unroll
@@ -281,7 +289,7 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const Step2Args a) {
                 s.x += s_red[(which * (kBlock / 64) + w) * N + o].x;
                 s.y += s_red[(which * (kBlock / 64) + w) * N + o].y;
             }
-            if (MODE == 1 || MODE == 2) {           // the mirrored items' terms
+            if (MODE == 1) {                        // the mirrored items' terms
                 for (int w = 0; w < kBlock / 64; ++w) {
                     s.x += s_red[(which * (kBlock / 64) + w) * N + ob].x;
                     s.y -= s_red[(which * (kBlock / 64) + w) * N + ob].y;
@@ -300,7 +308,6 @@ hipError_t launch_step2_t(const Step2Args &a, hipStream_t st) {
     switch (a.mode) {
     case 0: hipLaunchKernelGGL((step2_kernel<S, T, RHO, 0>), dim3(a.grid), b, lay.total, st, a); break;
     case 1: hipLaunchKernelGGL((step2_kernel<S, T, RHO, 1>), dim3(a.n_blk), b, lay.total, st, a); break;
-    case 2: hipLaunchKernelGGL((step2_kernel<S, T, RHO, 2>), dim3(a.n_blk), b, lay.total, st, a); break;
     case 3: hipLaunchKernelGGL((step2_kernel<S, T, RHO, 3>), dim3(a.n_blk), b, lay.total, st, a); break;
     default: return hipErrorInvalidValue;
     }
