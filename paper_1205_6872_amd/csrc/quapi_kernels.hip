@@ -395,6 +395,13 @@ struct MirrorDigits {
     static constexpr int M = N == 4 ? 2 : N == 9 ? 3 : 4;
     static __host__ __device__ constexpr int digit(int d) { return M * (d % M) + d / M; }
     static __device__ long long index(long long x) { return N == 4 ? mirror4(x) : mirror9(x); }
+    // the mirror of a small index (few digits), in 32-bit arithmetic
+    static __device__ int index_small(int x) {
+        if (N == 4) return (int)mirror4(x);
+        int out = 0, w = 1;
+        for (; x > 0; x /= N, w *= N) out += digit(x % N) * w;
+        return out;
+    }
     static __device__ bool diagonal_only(int v) {          // every digit a (M + 1)
         for (; v > 0; v /= N)
             if (v % N % (M + 1) != 0) return false;
@@ -512,6 +519,12 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
         const CS *__restrict__ ain = (const CS *)a.a_in;
         CS *__restrict__ aout = (CS *)a.a_out;
         const long long mc = a.m_count;
+        // the mirror acts digit by digit, and m = (blk, qm, r) splits into whole
+        // digits, so mirror(m) = mirror(blk) R Q + mirror(qm) R + mirror(r):
+        // the block and thread parts once, the sweep part per item in 32-bit
+        // arithmetic, instead of a 64-bit digit loop per item (N = 9)
+        const long long mb0 = MODE == 0 ? 0 : MD::index(blk) * (long long)R * Q + MD::index_small(r);
+        auto mirror_of = [&](int qm) { return mb0 + (long long)MD::index_small(qm) * R; };
         // sweep rows: all (mode 0, 1), a part (mode 2), or in mode 3 those with
         // all digits diagonal, for threads whose low digits are diagonal
         const int part = MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
@@ -532,7 +545,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
                 const int it = qm0 + u * cR;
                 const int qm = MODE == 3 ? MD::diagonal(it) : it;
                 const long long m = m0 + (long long)qm * R + r;
-                has[u] = it < i1 && (MODE != 2 || m < MD::index(m));
+                has[u] = it < i1 && (MODE != 2 || m < mirror_of(qm));
                 if (has[u]) {
 #pragma unroll
                     for (int i = 0; i < I; ++i) {
@@ -551,7 +564,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
                 const int it = qm0 + u * cR;
                 const int qm = MODE == 3 ? MD::diagonal(it) : it;
                 const long long m = m0 + (long long)qm * R + r;
-                const long long mb = MODE == 0 ? m : MD::index(m);
+                const long long mb = MODE == 0 ? m : mirror_of(qm);
 #pragma unroll
                 for (int o = 0; o < N; ++o) {
                     if (!OLD_REG) asm volatile("" ::: "memory");   // table reads of this o only
