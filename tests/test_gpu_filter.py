@@ -10,7 +10,9 @@ every step are compared exactly and rho(t_n) at every step to 1e-12 of its
 scale.  complex64 storage (FP32 or FP64 arithmetic): values are rounded to
 FP32 at every step, so entries within about 1e-5 relative of theta may be
 decided differently; kept counts agree within 1e-3 relative and rho within
-2e-5.  Also: theta = 0 equals the unfiltered oracle and keeps exactly the
+2e-5.  At the benchmark's own size (M = 2, L = 15, theta = 1e-10) the
+complex128 run is compared with the oracle the same way over its growth and
+7 full-window steps.  Also: theta = 0 equals the unfiltered oracle and keeps exactly the
 dense GPU tensor; results are bitwise reproducible and do not depend on how
 the steps are split into calls; an undersized capacity gives NOMEM and the
 overflow flag; a theta above every entry empties the tensor.
@@ -162,3 +164,22 @@ def test_dense_only_calls_refuse_a_filtered_context():
                 call()
             assert ei.value.status == Q.ERR_INVALID
         assert ctx.persistent() == 0 and ctx.mirror() == 0 and ctx.fused_steps() == 1
+
+
+@pytest.mark.timeout(900)
+def test_headline_l15_filtered_against_oracle():
+    """The benchmark's workload (M = 2, L = 15) with theta = 1e-10, the
+    configuration bench.py times: growth and 7 full-window steps, kept counts
+    after every step and rho at every step against the oracle's filtered run
+    (2 x 17 GB of host memory)."""
+    w = W.spin_boson_l15("c128")
+    n, theta = w.L + 7, 1e-10
+    print(f"oracle: {w.name} filtered, theta = {theta:g}, {n} steps", flush=True)
+    ro, ko, margin = orun.oracle_run_filtered(w, n, theta)
+    print(f"oracle: kept {ko[-1]} after step {n}, margin {margin:.2e}", flush=True)
+    assert margin > 1e-9, margin
+    rg, kg = gpu_filtered(w, n, theta, cap=2 ** 28)
+    assert list(kg) == list(ko)
+    err = (np.abs(rg - ro).reshape(n + 1, -1).max(axis=1) / np.abs(ro).reshape(n + 1, -1).max(axis=1)).max()
+    print(f"max relative |drho| per step: {err:.3e}", flush=True)
+    assert err <= 1e-12
