@@ -290,7 +290,7 @@ struct Layout {
     size_t off_a0, off_a1, off_bank, off_bankf, off_g, off_eta, off_U, off_s, off_H, off_Ht, off_Ut, off_rho0;
     size_t off_pa, off_ph, off_pseg, off_tw, off_tJ, off_glx, off_glw, off_partials, off_stage;
     size_t off_plan, off_plan2, off_coef, off_plan3, off_coef3, off_blk3, off_low3, off_blk2, off_low2, off_blk1,
-        off_pairs, off_sink;
+        off_low1, off_pairs, off_sink;
     // filtered contexts: keys and values of the two tensors, flags, segment
     // starts, scan partials, counters, rho partials, factor-level tables
     size_t off_fkeys[2], off_fvals[2], off_fmask, off_fbofs, off_fctr, off_fpart, off_fplan;
@@ -302,6 +302,7 @@ struct Layout {
     int n_canon2, n_diag2, parts2, span2;   // mirror mode of the two-step kernel
     int n_low2;                             // items of a block below their mirror (its list)
     int n_canon1, n_diag1, parts1, span1;   // mirror mode of the single step (main split)
+    int n_low1;                             // N = 9: items of a block below their mirror (its list)
     DigitSplit main_split;   // digit split of the full-window steps
     DigitSplit split2;       // digit split of the fused two-step kernel
     DigitSplit split3;       // digit split of the three-step kernel
@@ -391,10 +392,22 @@ Layout make_layout(const quapi_params &p, int n_panels, size_t filter_cap = 0) {
             if (h < hb) ++l.n_canon1;
             else if (h == hb) ++l.n_diag1;
         }
-        const int rows_per_pass = N == 16 ? kBlock / 64 : kBlock / s1.R;
-        const int passes = (s1.Q + rows_per_pass - 1) / rows_per_pass;
-        l.parts1 = mirror_parts(passes, l.n_diag1);
-        l.span1 = ((passes + l.parts1 - 1) / l.parts1) * rows_per_pass;
+        if (N == 9) {
+            // the listed items of the diagonal values, one per active thread
+            // (kBlock / R columns of R), two passes per block, in the tail of
+            // the mode-1 launch
+            for (int low = 0; low < s1.R * s1.Q; ++low)
+                if (mirror9(low) > low) ++l.n_low1;
+            const int active = (kBlock / s1.R) * s1.R;
+            const int passes = (l.n_low1 + active - 1) / active;
+            l.parts1 = std::max(1, (passes + 1) / 2);
+            l.span1 = ((passes + l.parts1 - 1) / l.parts1) * active;
+        } else {
+            const int rows_per_pass = N == 16 ? kBlock / 64 : kBlock / s1.R;
+            const int passes = (s1.Q + rows_per_pass - 1) / rows_per_pass;
+            l.parts1 = mirror_parts(passes, l.n_diag1);
+            l.span1 = ((passes + l.parts1 - 1) / l.parts1) * rows_per_pass;
+        }
         l.partial_blocks = std::max(l.partial_blocks, l.n_canon1 + l.n_diag1 * (l.parts1 + 1));
     }
     l.a_bytes = filtered ? 0 : entries * cs;
@@ -445,6 +458,7 @@ Layout make_layout(const quapi_params &p, int n_panels, size_t filter_cap = 0) {
     l.off_blk2 = take((size_t)(l.n_canon2 + l.n_diag2) * sizeof(int));
     l.off_low2 = take((size_t)l.n_low2 * sizeof(int));
     l.off_blk1 = take((size_t)(l.n_canon1 + l.n_diag1) * sizeof(int));
+    l.off_low1 = take((size_t)l.n_low1 * sizeof(int));
     const size_t fc = filtered ? filter_cap : 0;
     for (int b = 0; b < 2; ++b) {
         l.off_fkeys[b] = take(fc * 8);
@@ -534,6 +548,8 @@ struct quapi_ctx {
     std::vector<int> low2_h;
     int *blk1 = nullptr;          // the same for the single step (n_canon1, n_diag1)
     std::vector<int> blk1_h;
+    int *low1 = nullptr;          // N = 9: its list of the items below their mirror
+    std::vector<int> low1_h;
     double2 *plan3 = nullptr;
     void *coef3 = nullptr;
     // Filtered propagation (quapi_create_filtered): the kept entries as sorted
@@ -816,15 +832,20 @@ hipError_t launch_full_step(quapi_ctx *c, bool rho, StepArgs a, int grid, int *r
     }
     const Layout &l = c->lay;
     hipError_t e = hipSuccess;
-    if (l.n_canon1 > 0) {
+    const bool listed = c->N == 9;      // the diagonal values' items in the tail of mode 1
+    if (l.n_canon1 > 0 || (listed && l.n_diag1 > 0)) {
         a.mode = 1;
         a.blk_hi = c->blk1;
-        a.n_blk = l.n_canon1;
-        a.parts = 1;
+        a.n_canon = l.n_canon1;
+        a.n_blk = l.n_canon1 + (listed ? l.n_diag1 * l.parts1 : 0);
+        a.low_list = c->low1;
+        a.n_low = l.n_low1;
+        a.parts = listed ? l.parts1 : 1;
+        a.q_span = l.span1;
         a.part_base = 0;
         e = launch_step(c->N, c->prec, rho, false, a, grid, c->stream);
     }
-    if (e == hipSuccess && l.n_diag1 > 0) {
+    if (e == hipSuccess && l.n_diag1 > 0 && !listed) {
         a.mode = 2;
         a.blk_hi = c->blk1 + l.n_canon1;
         a.n_blk = l.n_diag1 * l.parts1;
@@ -1806,6 +1827,7 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
     c->blk2 = (int *)(w + lay.off_blk2);
     c->low2 = (int *)(w + lay.off_low2);
     c->blk1 = (int *)(w + lay.off_blk1);
+    c->low1 = (int *)(w + lay.off_low1);
     c->n_H = p->n_H;
     c->Ht_d = (const double2 *)(w + lay.off_Ht);
     c->Ut_d = (double2 *)(w + lay.off_Ut);
@@ -1861,6 +1883,9 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
             for (int pass = 0; pass < 2; ++pass)
                 for (int h = 0; h < lay.main_split.grid; ++h)
                     if (pass == 0 ? h < mirror_n(N, h) : h == mirror_n(N, h)) c->blk1_h.push_back(h);
+            if (N == 9)
+                for (int low = 0; low < lay.main_split.R * lay.main_split.Q; ++low)
+                    if (mirror9(low) > low) c->low1_h.push_back(low);
             c->mirror_ok = herm;
         }
         c->mirror = c->mirror_ok ? 1 : 0;
@@ -1907,6 +1932,8 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
     if (e == hipSuccess && (int)c->low2_h.size() != lay.n_low2) e = hipErrorInvalidValue;
     if (e == hipSuccess && !c->low2_h.empty()) e = up(lay.off_low2, c->low2_h.data(), c->low2_h.size() * sizeof(int));
     if (e == hipSuccess && !c->blk1_h.empty()) e = up(lay.off_blk1, c->blk1_h.data(), c->blk1_h.size() * sizeof(int));
+    if (e == hipSuccess && (int)c->low1_h.size() != lay.n_low1) e = hipErrorInvalidValue;
+    if (e == hipSuccess && !c->low1_h.empty()) e = up(lay.off_low1, c->low1_h.data(), c->low1_h.size() * sizeof(int));
     if (e == hipSuccess) e = up(lay.off_pa, c->pa_h.data(), c->pa_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_ph, c->ph_h.data(), c->ph_h.size() * 8);
     if (e == hipSuccess) e = up(lay.off_pseg, c->pseg_h.data(), c->pseg_h.size() * 4);

@@ -64,13 +64,18 @@ struct StepArgs {
     int old_tab, oldf_tab;      // bank indices of the oldest-point tables
     int16_t tab[kMaxL];         // bank index of the interior table for digit j
     int16_t tabf[kMaxL];        // bank index of the final-point table for digit j
-    // Mirror mode of the N = 9 and N = 16 steps (as for the three-step kernel):
-    // mode 1 the high-digit values blk_hi[..] below their mirror, mode 2 those
-    // equal to it in `parts` blocks of q_span sweep rows (items below their
-    // mirror), mode 3 the same values, the items that are their own mirror;
-    // rho partials at row part_base + block.  Mode 0: every block.
+    // Mirror mode of the N = 4, 9 and 16 single steps (as for the three-step
+    // kernel): mode 1 the high-digit values blk_hi[..] below their mirror
+    // (n_canon of them), mode 2 those equal to it in `parts` blocks of q_span
+    // sweep rows (items below their mirror), mode 3 the same values, the items
+    // that are their own mirror; rho partials at row part_base + block.  At
+    // N = 9 the mode-1 launch also runs, after its n_canon blocks, `parts`
+    // blocks per value equal to its mirror over q_span items of low_list (the
+    // n_low indices qm * R + r below their mirror), and mode 2 does not run.
+    // Mode 0: every block.
     const int *blk_hi;
-    int n_blk, parts, q_span, part_base, mode;
+    const int *low_list;
+    int n_blk, n_canon, parts, q_span, part_base, mode, n_low;
 };
 
 // Two consecutive full-window steps n, n+1 (n > L, N = 4) in one pass:

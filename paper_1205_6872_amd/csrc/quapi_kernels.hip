@@ -441,7 +441,13 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
     const int cR = kBlock / R;       // sweep stride in units of R
     const int active = cR * R;       // threads that own items
     const double2 *__restrict__ bank = a.bank;
+    // N = 9, mode 1: blocks below n_canon run the canonical high-digit values,
+    // the rest the listed items of the values equal to their mirror
+    constexpr bool kListed = N == 9 && MODE == 1;
+    const bool listed = kListed && (int)blockIdx.x >= a.n_canon;
+    const int lblk = listed ? (int)blockIdx.x - a.n_canon : 0;
     const long long blk = MODE == 0   ? (long long)blockIdx.x
+                          : listed    ? (long long)a.blk_hi[a.n_canon + lblk / a.parts]
                           : MODE == 2 ? (long long)a.blk_hi[blockIdx.x / a.parts]
                                       : (long long)a.blk_hi[blockIdx.x];     // high digits
     const double2 one = make_double2(1.0, 0.0);
@@ -523,29 +529,43 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
         // digits, so mirror(m) = mirror(blk) R Q + mirror(qm) R + mirror(r):
         // the block and thread parts once, the sweep part per item in 32-bit
         // arithmetic, instead of a 64-bit digit loop per item (N = 9)
-        const long long mb0 = MODE == 0 ? 0 : MD::index(blk) * (long long)R * Q + MD::index_small(r);
-        auto mirror_of = [&](int qm) { return mb0 + (long long)MD::index_small(qm) * R; };
+        const long long mbh = MODE == 0 ? 0 : MD::index(blk) * (long long)R * Q;
+        const int r_mir = MODE == 0 ? 0 : MD::index_small(r);
+        auto mirror_of = [&](int qm, int rr) {
+            return mbh + (long long)MD::index_small(qm) * R + (listed ? MD::index_small(rr) : r_mir);
+        };
         // sweep rows: all (mode 0, 1), a part (mode 2), or in mode 3 those with
-        // all digits diagonal, for threads whose low digits are diagonal
-        const int part = MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
+        // all digits diagonal, for threads whose low digits are diagonal; a
+        // listed block (N = 9) walks its part of the list of the items below
+        // their mirror (qm * R + r, the same for every diagonal high value),
+        // one item per active thread
+        const int part = listed ? lblk % a.parts : MODE == 2 ? (int)(blockIdx.x % a.parts) : 0;
         const bool thread_runs = MODE != 3 || MD::diagonal_only(r);
         int n_diag_rows = 1;
         if (MODE == 3)
             for (int q = Q; q > 1; q /= N) n_diag_rows *= MD::M;
-        const int i0 = (MODE == 2 ? part * a.q_span : 0) + t / R;
-        const int i1 = !thread_runs ? 0 : MODE == 3 ? n_diag_rows : MODE == 2 ? min(Q, (part + 1) * a.q_span) : Q;
-        for (int qm0 = i0; qm0 < i1; qm0 += ILP * cR) {
+        const int i0 = listed ? part * a.q_span + t : (MODE == 2 ? part * a.q_span : 0) + t / R;
+        const int i1 = !thread_runs ? 0
+                       : MODE == 3  ? n_diag_rows
+                       : listed     ? min(a.n_low, (part + 1) * a.q_span)
+                       : MODE == 2  ? min(Q, (part + 1) * a.q_span)
+                                    : Q;
+        const int istride = listed ? active : cR;
+        static_assert(!kListed || ILP == 1, "listed items: one item per thread and pass");
+        for (int qm0 = i0; qm0 < i1; qm0 += ILP * istride) {
             // For N >= 9 the N*N table reads must stay in the loop: hoisted as
             // loop invariants they would need more registers than a thread has.
             if (!OLD_REG) asm volatile("" ::: "memory");
             C x[ILP][I];
             bool has[ILP];
+            const int low = listed ? a.low_list[qm0] : 0;       // listed: one item (ILP = 1)
+            const int rr = listed ? low % R : r;
 #pragma unroll
             for (int u = 0; u < ILP; ++u) {      // issue every load first
-                const int it = qm0 + u * cR;
-                const int qm = MODE == 3 ? MD::diagonal(it) : it;
-                const long long m = m0 + (long long)qm * R + r;
-                has[u] = it < i1 && (MODE != 2 || m < mirror_of(qm));
+                const int it = qm0 + u * istride;
+                const int qm = MODE == 3 ? MD::diagonal(it) : listed ? low / R : it;
+                const long long m = m0 + (long long)qm * R + rr;
+                has[u] = it < i1 && (MODE != 2 || m < mirror_of(qm, rr));
                 if (has[u]) {
 #pragma unroll
                     for (int i = 0; i < I; ++i) {
@@ -561,14 +581,14 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 #pragma unroll
             for (int u = 0; u < ILP; ++u) {
                 if (!has[u]) continue;
-                const int it = qm0 + u * cR;
-                const int qm = MODE == 3 ? MD::diagonal(it) : it;
-                const long long m = m0 + (long long)qm * R + r;
-                const long long mb = MODE == 0 ? m : mirror_of(qm);
+                const int it = qm0 + u * istride;
+                const int qm = MODE == 3 ? MD::diagonal(it) : listed ? low / R : it;
+                const long long m = m0 + (long long)qm * R + rr;
+                const long long mb = MODE == 0 ? m : mirror_of(qm, rr);
 #pragma unroll
                 for (int o = 0; o < N; ++o) {
                     if (!OLD_REG) asm volatile("" ::: "memory");   // table reads of this o only
-                    const C p = cmul(PLO_REG ? plo[o] : s_plo[o * R + r], s_tq[o * Q + qm]);
+                    const C p = cmul(PLO_REG ? plo[o] : s_plo[o * R + rr], s_tq[o * Q + qm]);
                     C v;
                     if (TRACE_ROWS && o % (MD::M + 1) == 0 && a.n_digits > 0) {
                         // a diagonal point with L >= 2: its oldest-point row is
@@ -599,7 +619,9 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 #pragma unroll
                         for (int i = 0; i < I; ++i)
                             cmac(sf, OLD_REG ? oldf_r[o * I + i] : coef_ld(oldf_c, o * N + i), x[u][i]);
-                        const double2 v = to_d2(cmul(sf, s_tqf[o * Q + qm]));
+                        double2 v = to_d2(cmul(sf, s_tqf[o * Q + qm]));
+                        // a listed item has its own low digits: their factor per item
+                        if (kListed && listed) v = cmul(v, s_plof[o * R + rr]);
                         acc[o].x += v.x;
                         acc[o].y += v.y;
                     }
@@ -612,7 +634,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs a) {
 #pragma unroll
         for (int o = 0; o < N; ++o) {
             double2 v = make_double2(0.0, 0.0);
-            if (t < active) v = cmul(acc[o], PLO_REG ? plof[o] : s_plof[o * R + r]);
+            if (t < active) v = listed ? acc[o] : cmul(acc[o], PLO_REG ? plof[o] : s_plof[o * R + r]);
             for (int off = 32; off > 0; off >>= 1) {
                 v.x += __shfl_xor(v.x, off, 64);
                 v.y += __shfl_xor(v.y, off, 64);
