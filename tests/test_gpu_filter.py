@@ -183,3 +183,26 @@ def test_headline_l15_filtered_against_oracle():
     err = (np.abs(rg - ro).reshape(n + 1, -1).max(axis=1) / np.abs(ro).reshape(n + 1, -1).max(axis=1)).max()
     print(f"max relative |drho| per step: {err:.3e}", flush=True)
     assert err <= 1e-12
+
+
+def test_selection_and_async_give_the_same_bits():
+    # rho at the last step only ('justFinalPoint'), or written to device memory
+    # by the asynchronous call, equals the every-step run bit for bit (the kept
+    # entries do not depend on which steps return rho)
+    import torch
+    w = W.spin_boson_l15("c128").with_(L=9)
+    n, theta = 30, 1e-9
+    full, kept = gpu_filtered(w, n, theta, split=[n])
+    p = Q.params_from(w)
+    with Q.create_filtered(p, theta, 4 ** 9) as ctx:
+        last = ctx.propagate(n, [n])
+        assert ctx.filter_stats()[0] == kept[-1]
+    assert np.array_equal(last[0], full[-1])
+    stream = torch.cuda.Stream()
+    with Q.create_filtered(p, theta, 4 ** 9, stream=stream.cuda_stream) as ctx:
+        out = torch.zeros((n, 4, 2), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()                 # the fill is done before the context's stream writes
+        ctx.propagate_async(n, None, out.data_ptr())
+        stream.synchronize()
+        got = out.cpu().numpy().view(np.complex128).reshape(n, 2, 2)
+    assert np.array_equal(got, full[1:])
