@@ -5,11 +5,13 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <mutex>
 #include <string>
@@ -570,6 +572,11 @@ struct quapi_ctx {
     std::vector<double> rho0_h;
     // host copies of uploaded inputs (kept alive until the uploads complete)
     std::vector<double> s_h, H_h, pa_h, ph_h, tw_h, tJ_h, glx_h, glw_h;
+    // N = 16: the new points grouped by the classes of their oldest-point
+    // rows for the MFMA step (Cls16), when such a grouping exists
+    bool cls_ok = false;
+    unsigned long long cls_out = 0;
+    unsigned cls_rep = 0, cls_selb = 0;
     std::vector<int> pseg_h;
     std::string err;
     std::atomic<int> busy{0};
@@ -670,6 +677,86 @@ void step_tables(int L, int n, StepArgs &a) {
     }
 }
 
+// QUAPI_STEP16_CLASSES=0 in the environment at context creation keeps every
+// output's own row in the M = 4 MFMA step (for comparisons of the two forms).
+bool cls16_disabled() {
+    const char *v = std::getenv("QUAPI_STEP16_CLASSES");
+    return v && std::strcmp(v, "0") == 0;
+}
+
+// The new points o = (a, b) of M = 4 whose oldest-point influence rows are
+// equal (s_a - s_b equal to 8 ulps of the largest difference: the rows are
+// equal in exact arithmetic, and differ by rounding only), packed onto the
+// MFMA step's 4 lane groups of 4 outputs with at most 2 classes per group.
+// Returns false when no such packing exists (the step then contracts every
+// output's own row).
+bool pack_classes16(const std::vector<double> &s, unsigned long long *out, unsigned *rep, unsigned *selb) {
+    if (s.size() != 4) return false;
+    double del[16], scale = 0.0;
+    for (int o = 0; o < 16; ++o) {
+        del[o] = s[o / 4] - s[o % 4];
+        scale = std::max(scale, std::fabs(del[o]));
+    }
+    const double tol = 8.0 * DBL_EPSILON * scale;
+    int cls[16], reps[16], n_cls = 0;
+    for (int o = 0; o < 16; ++o) {
+        cls[o] = -1;
+        for (int k = 0; k < n_cls && cls[o] < 0; ++k)
+            if (std::fabs(del[o] - del[reps[k]]) <= tol) cls[o] = k;
+        if (cls[o] < 0) {
+            reps[n_cls] = o;
+            cls[o] = n_cls++;
+        }
+    }
+    // depth-first assignment of the outputs, class by class, to the groups
+    int order[16], n = 0;
+    for (int k = 0; k < n_cls; ++k)
+        for (int o = 0; o < 16; ++o)
+            if (cls[o] == k) order[n++] = o;
+    int grp[16], cnt[4] = {0, 0, 0, 0}, ca[4] = {-1, -1, -1, -1}, cb[4] = {-1, -1, -1, -1};
+    std::function<bool(int)> place = [&](int i) -> bool {
+        if (i == 16) return true;
+        const int k = cls[order[i]];
+        bool tried_empty = false;
+        for (int g = 0; g < 4; ++g) {
+            if (cnt[g] == 4) continue;
+            if (cnt[g] == 0) {
+                if (tried_empty) continue;          // empty groups are interchangeable
+                tried_empty = true;
+            }
+            const int sa = ca[g], sb = cb[g];
+            if (sa >= 0 && sa != k && sb >= 0 && sb != k) continue;
+            if (sa < 0) ca[g] = k;
+            else if (sa != k && sb < 0) cb[g] = k;
+            grp[i] = g;
+            ++cnt[g];
+            if (place(i + 1)) return true;
+            --cnt[g];
+            ca[g] = sa;
+            cb[g] = sb;
+        }
+        return false;
+    };
+    if (!place(0)) return false;
+    unsigned long long po = 0;
+    unsigned pr = 0, ps = 0;
+    int fill[4] = {0, 0, 0, 0};
+    for (int g = 0; g < 4; ++g) {
+        const int kb = cb[g] >= 0 ? cb[g] : ca[g];
+        pr |= (unsigned)reps[ca[g]] << (4 * (2 * g));
+        pr |= (unsigned)reps[kb] << (4 * (2 * g + 1));
+    }
+    for (int i = 0; i < 16; ++i) {
+        const int o = order[i], g = grp[i], q = fill[g]++;
+        po |= (unsigned long long)o << (4 * (4 * g + q));
+        if (cls[o] != ca[g]) ps |= 1u << (4 * g + q);
+    }
+    *out = po;
+    *rep = pr;
+    *selb = ps;
+    return true;
+}
+
 StepPlan plan_step(const quapi_ctx *c, int n) {
     const int N = c->N, L = c->L;
     StepPlan sp{};
@@ -684,6 +771,17 @@ StepPlan plan_step(const quapi_ctx *c, int n) {
     a.Q = sp.split.Q;
     a.bank = c->bank;
     a.bank_c = c->bank_f ? (const void *)c->bank_f : (const void *)c->bank;
+    if (c->cls_ok && !sp.grow) {
+        const BankLayout B{L};
+        a.cls_on = 1;
+        a.cls_tab = n == L ? B.init(L) : B.lag(L);
+        a.clsf_tab = n == L ? B.fin_init(L) : B.fin(L);
+        a.cls_self = B.self_int();
+        a.cls_selff = B.self_end();
+        a.cls_out = c->cls_out;
+        a.cls_rep = c->cls_rep;
+        a.cls_selb = c->cls_selb;
+    }
     return sp;
 }
 
@@ -1854,6 +1952,9 @@ quapi_status create_ctx(const quapi_params *p, void *hip_stream, void *workspace
     }
 
     c->s_h.assign(p->s, p->s + M);
+    // L = 1: the oldest-point tables carry K, whose rows are not shared
+    if (N == 16 && L >= 2 && !filtered && !cls16_disabled())
+        c->cls_ok = pack_classes16(c->s_h, &c->cls_out, &c->cls_rep, &c->cls_selb);
     c->H_h.assign(p->H, p->H + 2 * M * M);
     if (p->n_H > 0) c->Ht_h.assign(p->H_t, p->H_t + (size_t)2 * M * M * p->n_H);
     c->rho0_h.assign(p->rho0, p->rho0 + 2 * N);

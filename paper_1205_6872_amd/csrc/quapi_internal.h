@@ -76,6 +76,19 @@ struct StepArgs {
     const int *blk_hi;
     const int *low_list;
     int n_blk, n_canon, parts, q_span, part_base, mode, n_low;
+    // N = 16 full-window steps (L >= 2) with the new points grouped by their
+    // oldest-point rows (cls_on): the row of o is F_self(o) times the
+    // influence row of the oldest point, which depends on o = (a, b) only
+    // through s_a - s_b; outputs with equal s_a - s_b share one contraction
+    // with the influence table cls_tab (interior) / clsf_tab (final point),
+    // and the self factors (tables cls_self, cls_selff) scale the outputs.
+    // Lane group g of the MFMA form owns the outputs cls_out >> 4(4g + q)
+    // (q = 0..3, 4 bits each), which take the contraction of class slot
+    // (cls_selb >> (4g + q)) & 1; slot c of group g is the row of output
+    // cls_rep >> 4(2g + c).
+    int cls_on, cls_tab, clsf_tab, cls_self, cls_selff;
+    unsigned long long cls_out;
+    unsigned cls_rep, cls_selb;
 };
 
 // Two consecutive full-window steps n, n+1 (n > L, N = 4) in one pass:

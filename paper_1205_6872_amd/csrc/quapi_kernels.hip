@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "quapi_device.h"
 #include "quapi_internal.h"
@@ -818,6 +819,12 @@ __global__ void __launch_bounds__(kBlock) plan_tables_kernel(const PlanArgs a) {
 // kept in registers for the whole block (in LDS, read per item group, in the
 // rho form, which has twice as many), the inputs are B fragments loaded
 // straight from HBM, and each lane's accumulators hold 4 outputs of one item.
+// Class form (cls_on): the oldest-point row of o is F_self(o) times an
+// influence row that depends on o only through s_a - s_b, so outputs of equal
+// s_a - s_b share one contraction; the rows are then the distinct influence
+// rows a lane group needs, two per table (class slots 0, 1), in half the
+// blocks (one interior, one final point), and the self factors move into the
+// per-output multipliers.
 //
 // MFMA 16x16x4 lane layout (wave64): A[i][k] in lane i + 16k, B[k][j] in lane
 // j + 16k; D[i][j] in lane j + 16(i / 4), element i % 4 for f32, and in lane
@@ -857,13 +864,14 @@ __device__ __forceinline__ int diagonal_digits16(int x, int nd) {
 struct Step16Lds {
     unsigned tq, tqf, red, afr, total;
 };
-__host__ __device__ inline Step16Lds step16_lds_layout(int csize, bool rho, int Q) {
+// afr_lds: the A fragments in LDS (the rho form without classes)
+__host__ __device__ inline Step16Lds step16_lds_layout(int csize, bool rho, int Q, bool afr_lds) {
     Step16Lds l;
     unsigned off = 0;
     l.tq = lds_take(off, 16 * Q * csize);
     l.tqf = lds_take(off, rho ? 16 * Q * csize : 0);
     l.red = lds_take(off, rho ? (kBlock / 64) * 16 * 16 : 0);
-    l.afr = lds_take(off, rho ? 4 * 8 * 64 * (csize / 2) : 0);     // A fragments [4][8][lane]
+    l.afr = lds_take(off, afr_lds ? 4 * 8 * 64 * (csize / 2) : 0);     // A fragments [4][8][lane]
     l.total = off;
     return l;
 }
@@ -884,15 +892,18 @@ template <> struct Mfma16<double> {
     }
 };
 
-template <typename S, typename T, bool RHO, int MODE>
+template <typename S, typename T, bool RHO, int MODE, bool CLS>
 __global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfma_kernel(const StepArgs a) {
-    constexpr int N = 16, NB = RHO ? 4 : 2;
+    constexpr int N = 16, NB = CLS ? (RHO ? 2 : 1) : (RHO ? 4 : 2);
+    // A-fragment blocks held in registers; the rest are read from LDS per use
+    constexpr int kRegBlocks = !RHO ? NB : !CLS ? 0 : sizeof(T) == 8 ? 1 : NB;
+    constexpr bool kAfrLds = kRegBlocks < NB;
     using C = typename Cx<T>::type;
     using CS = typename Cx<S>::type;
     using V4 = typename Mfma16<T>::v4;
     extern __shared__ __align__(16) unsigned char smem[];
     const int Q = a.Q;                                  // R = 16: one item per lane column
-    const Step16Lds lay = step16_lds_layout((int)sizeof(C), RHO, Q);
+    const Step16Lds lay = step16_lds_layout((int)sizeof(C), RHO, Q, kAfrLds);
     C *s_tq = (C *)(smem + lay.tq);                      // [N][Q] mid x high products
     C *s_tqf = (C *)(smem + lay.tqf);
     double2 *s_red = (double2 *)(smem + lay.red);        // [waves][N]
@@ -908,10 +919,10 @@ __global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfm
         s_tq[idx] = from_d2<C>(cmul(a.t_hi[(size_t)o * a.grid + blk], a.t_mid[idx]));
         if (RHO) s_tqf[idx] = from_d2<C>(cmul(a.t_hif[(size_t)o * a.grid + blk], a.t_midf[idx]));
     }
-    // A fragments: row 16b + j, word 8g + s; those of the final-point table
-    // (blocks 2, 3) in LDS, read per use, to keep the registers of the rho
-    // form down
-    T afr[RHO ? 1 : 2][8];
+    // A fragments: row 16b + j, word 8g + s; in the rho form those of the
+    // final-point table in LDS, read per use, to keep the registers down (all
+    // blocks there without classes; the FP32 class form keeps all in registers)
+    T afr[kRegBlocks > 0 ? kRegBlocks : 1][8];
     {
         const C *bc = (const C *)a.bank_c;
 #pragma unroll
@@ -919,27 +930,45 @@ __global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfm
             // A row j of block b lands in D lane group gd as element vd
             const int gd = Mfma16<T>::kElemMajor ? (j & 3) : (j >> 2);
             const int vd = Mfma16<T>::kElemMajor ? (j >> 2) : (j & 3);
-            const int tb = b >= 2 ? a.oldf_tab : a.old_tab;
-            const int o = 8 * (b & 1) + 2 * gd + (vd >> 1), im_row = vd & 1;
+            const int im_row = vd & 1;
+            int tb, o;
+            if (CLS) {
+                // block 0 interior, block 1 final point; class slot vd / 2
+                tb = b == 1 ? a.clsf_tab : a.cls_tab;
+                o = (int)((a.cls_rep >> (4 * (2 * gd + (vd >> 1)))) & 15u);
+            } else {
+                tb = b >= 2 ? a.oldf_tab : a.old_tab;
+                o = 8 * (b & 1) + 2 * gd + (vd >> 1);
+            }
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 const int w = 8 * g + s, i = w / 2, im_word = w & 1;
                 const C c = bc[(size_t)tb * (N * N) + o * N + i];
                 // Re z = cr xr - ci xi ; Im z = ci xr + cr xi
                 const T v = im_row ? (im_word ? c.x : c.y) : (im_word ? -c.y : c.x);
-                if (!RHO) afr[b][s] = v;
+                if (b < kRegBlocks) afr[b < kRegBlocks ? b : 0][s] = v;
                 else if (wave == 0) s_afr[(b * 8 + s) * 64 + lane] = v;
             }
         }
     }
-    // per-lane digit-0 products (item j) of its four outputs
+    // per-lane digit-0 products (item j) of its four outputs (with the self
+    // factors in the class form)
     int oo[4] = {2 * g, 2 * g + 1, 8 + 2 * g, 9 + 2 * g};
+    bool slot1[4] = {false, false, false, false};
+    if (CLS) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            oo[q] = (int)((a.cls_out >> (4 * (4 * g + q))) & 15ull);
+            slot1[q] = (a.cls_selb >> (4 * g + q)) & 1u;
+        }
+    }
     C plo[4];
-    double2 plof[4], acc[4];
+    double2 acc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        plo[q] = from_d2<C>(a.t_lo[oo[q] * 16 + j]);
-        plof[q] = RHO ? a.t_lof[oo[q] * 16 + j] : make_double2(1.0, 0.0);
+        double2 lo = a.t_lo[oo[q] * 16 + j];
+        if (CLS) lo = cmul(lo, a.bank[(size_t)a.cls_self * (N * N) + oo[q] * N + oo[q]]);
+        plo[q] = from_d2<C>(lo);
         acc[q] = make_double2(0.0, 0.0);
     }
     __syncthreads();
@@ -961,8 +990,10 @@ __global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfm
         mb = MODE == 0 ? m : mirror16(m);
         return MODE == 0 || MODE == 1 || (MODE == 2 ? m < mb : j % 5 == 0);
     };
-    // a lane's 8 input words of the item of sweep index it
-    auto load = [&](int it, T *xw) {
+    // a lane's 8 input words of the item of sweep index it (as stored;
+    // mode 3 converts them, to conjugate the mirrored slots)
+    using LW = typename std::conditional<MODE == 3, T, S>::type;
+    auto load = [&](int it, LW *xw) {
         long long m, mb;
         const bool run = item(it, m, mb);
 #pragma unroll
@@ -972,42 +1003,53 @@ __global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfm
                 // their mirror come from the mirrored slot, conjugated
                 const int w = 8 * g + s, i = w >> 1, ib = mirror_digit16(i);
                 const bool flip = ib < i;
-                const T v = run ? (T)ain[32 * m + (flip ? 2 * ib + (w & 1) : w)] : T(0);
+                const LW v = run ? (LW)ain[32 * m + (flip ? 2 * ib + (w & 1) : w)] : LW(0);
                 xw[s] = flip && (w & 1) ? -v : v;
             } else {
-                xw[s] = (MODE != 2 || run) ? (T)ain[32 * m + 8 * g + s] : T(0);
+                xw[s] = (MODE != 2 || run) ? (LW)ain[32 * m + 8 * g + s] : LW(0);
             }
         }
     };
-    // the next item group's inputs are loaded before this group's products,
-    // so that their latency overlaps the MFMAs (loading two groups ahead
-    // costs a wave per SIMD and was slower: M = 4, L = 7, complex64 rho step
-    // 0.60 -> 0.65 ms)
-    T xw[8];
-    if (i0 < i1) load(i0, xw);
-    for (int it = i0; it < i1; it += kBlock / 64) {
-        const bool more = it + kBlock / 64 < i1;
-        T xn[8];
-        if (more) load(it + kBlock / 64, xn);
+    // the inputs of the next PF item groups are loaded before this group's
+    // products, so that their latency overlaps the MFMAs; the complex64
+    // tiers, whose groups are half as many bytes, load two groups ahead
+    constexpr int PF = (MODE == 3 || sizeof(S) == 8) ? 1 : 2;
+    constexpr int kStride = kBlock / 64;
+    LW xb[PF + 1][8];
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+        if (i0 + k * kStride < i1) load(i0 + k * kStride, xb[k]);
+    for (int it = i0; it < i1; it += kStride) {
+        if (it + PF * kStride < i1) load(it + PF * kStride, xb[PF]);
+        T xw[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) xw[s] = (T)xb[0][s];
         const int qm = MODE == 3 ? diagonal_digits16(it, dm) : it;
         long long m, mb;
         const bool run = item(it, m, mb);
         V4 d[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) d[b] = V4{0, 0, 0, 0};
-        if (RHO) asm volatile("" ::: "memory");   // the LDS fragments are read here, per item group
+        if (kAfrLds) asm volatile("" ::: "memory");   // the LDS fragments are read here, per item group
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)
-                d[b] = Mfma16<T>::run(RHO ? s_afr[(b * 8 + s) * 64 + lane] : afr[b][s], xw[s], d[b]);
+                d[b] = Mfma16<T>::run(b < kRegBlocks ? afr[b < kRegBlocks ? b : 0][s] : s_afr[(b * 8 + s) * 64 + lane],
+                                      xw[s], d[b]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int b = q / 2, e = 2 * (q % 2);
+            // the contraction of output q: block b, elements e, e + 1
+            const int b = CLS ? 0 : q / 2, e = CLS ? 0 : 2 * (q % 2);
             C z;
-            z.x = d[b][e];
-            z.y = d[b][e + 1];
+            if (CLS) {
+                z.x = slot1[q] ? d[0][2] : d[0][0];
+                z.y = slot1[q] ? d[0][3] : d[0][1];
+            } else {
+                z.x = d[b][e];
+                z.y = d[b][e + 1];
+            }
             const C p = cmul(plo[q], s_tq[oo[q] * Q + qm]);
             const C v = cmul(p, z);
             // an output above its mirror goes to the mirrored address as its
@@ -1020,23 +1062,31 @@ __global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfm
             if (MODE == 0 || MODE == 1 || (run && (MODE == 2 || direct))) *dst = conv<CS>(val);
             if (RHO && run) {
                 C zf;
-                zf.x = d[2 + b][e];
-                zf.y = d[2 + b][e + 1];
+                if (CLS) {
+                    zf.x = slot1[q] ? d[NB - 1][2] : d[NB - 1][0];
+                    zf.y = slot1[q] ? d[NB - 1][3] : d[NB - 1][1];
+                } else {
+                    zf.x = d[NB - 2 + b][e];
+                    zf.y = d[NB - 2 + b][e + 1];
+                }
                 const double2 v = to_d2(cmul(s_tqf[oo[q] * Q + qm], zf));
                 acc[q].x += v.x;
                 acc[q].y += v.y;
             }
         }
-        if (more) {
 #pragma unroll
-            for (int s = 0; s < 8; ++s) xw[s] = xn[s];
-        }
+        for (int k = 0; k < PF; ++k)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) xb[k][s] = xb[k + 1][s];
     }
     if (RHO) {
-        // sum over the 16 items of the lane group, then over the waves
+        // sum over the 16 items of the lane group, then over the waves (the
+        // digit-0 factors of the final-point table are read here, not held)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            double2 v = cmul(acc[q], plof[q]);
+            double2 plof = a.t_lof[oo[q] * 16 + j];
+            if (CLS) plof = cmul(plof, a.bank[(size_t)a.cls_selff * (N * N) + oo[q] * N + oo[q]]);
+            double2 v = cmul(acc[q], plof);
             for (int off = 8; off > 0; off >>= 1) {
                 v.x += __shfl_xor(v.x, off, 64);
                 v.y += __shfl_xor(v.y, off, 64);
@@ -1062,19 +1112,24 @@ __global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfm
     }
 }
 
-template <typename S, typename T, bool RHO>
-hipError_t launch_step16_t(const StepArgs &a, int grid, hipStream_t st) {
+template <typename S, typename T, bool RHO, bool CLS>
+hipError_t launch_step16_c(const StepArgs &a, int grid, hipStream_t st) {
     using C = typename Cx<T>::type;
-    const Step16Lds lay = step16_lds_layout((int)sizeof(C), RHO, a.Q);
+    const Step16Lds lay = step16_lds_layout((int)sizeof(C), RHO, a.Q, RHO && (!CLS || sizeof(T) == 8));
     const dim3 b(kBlock);
     switch (a.mode) {
-    case 0: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 0>), dim3(grid), b, lay.total, st, a); break;
-    case 1: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 1>), dim3(a.n_blk), b, lay.total, st, a); break;
-    case 2: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 2>), dim3(a.n_blk), b, lay.total, st, a); break;
-    case 3: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 3>), dim3(a.n_blk), b, lay.total, st, a); break;
+    case 0: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 0, CLS>), dim3(grid), b, lay.total, st, a); break;
+    case 1: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 1, CLS>), dim3(a.n_blk), b, lay.total, st, a); break;
+    case 2: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 2, CLS>), dim3(a.n_blk), b, lay.total, st, a); break;
+    case 3: hipLaunchKernelGGL((step16_mfma_kernel<S, T, RHO, 3, CLS>), dim3(a.n_blk), b, lay.total, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename S, typename T, bool RHO>
+hipError_t launch_step16_t(const StepArgs &a, int grid, hipStream_t st) {
+    return a.cls_on ? launch_step16_c<S, T, RHO, true>(a, grid, st) : launch_step16_c<S, T, RHO, false>(a, grid, st);
 }
 
 // The MFMA form runs the full-window steps of N = 16 whose thread digit split
@@ -1122,7 +1177,7 @@ hipError_t launch_step_dt(int N, bool rho, bool grow, const StepArgs &a, int gri
 }  // namespace
 
 size_t step_lds_bytes(int N, int prec, bool with_rho, bool grow, int R, int Q) {
-    if (use_step16(N, grow, R)) return step16_lds_layout(prec == kPrecC64 ? 8 : 16, with_rho, Q).total;
+    if (use_step16(N, grow, R)) return step16_lds_layout(prec == kPrecC64 ? 8 : 16, with_rho, Q, with_rho).total;
     return step_lds_layout(N, prec == kPrecC64 ? 8 : 16, with_rho, grow ? 1 : N, R, Q, N <= 4).total;
 }
 
