@@ -738,18 +738,32 @@ bool pack_classes16(const std::vector<double> &s, unsigned long long *out, unsig
         return false;
     };
     if (!place(0)) return false;
+    // per group: slot 0 the class of at least two outputs, listed first, then
+    // the other class (slot 1; slot 1 repeats slot 0 when there is one
+    // class).  The class counts are 4, 3 + 1 or 2 + 2, so outputs q = 0, 1
+    // always take slot 0 and q = 3 slot 1 (the kernel fixes those); only
+    // q = 2 is looked up
     unsigned long long po = 0;
     unsigned pr = 0, ps = 0;
-    int fill[4] = {0, 0, 0, 0};
     for (int g = 0; g < 4; ++g) {
-        const int kb = cb[g] >= 0 ? cb[g] : ca[g];
-        pr |= (unsigned)reps[ca[g]] << (4 * (2 * g));
+        int na = 0, nb = 0;
+        for (int i = 0; i < 16; ++i)
+            if (grp[i] == g) (cls[order[i]] == ca[g] ? na : nb)++;
+        const int ka = na >= nb ? ca[g] : cb[g];
+        const int kb = nb == 0 ? ka : (na >= nb ? cb[g] : ca[g]);
+        pr |= (unsigned)reps[ka] << (4 * (2 * g));
         pr |= (unsigned)reps[kb] << (4 * (2 * g + 1));
-    }
-    for (int i = 0; i < 16; ++i) {
-        const int o = order[i], g = grp[i], q = fill[g]++;
-        po |= (unsigned long long)o << (4 * (4 * g + q));
-        if (cls[o] != ca[g]) ps |= 1u << (4 * g + q);
+        int q = 0;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < 16; ++i) {
+                const int o = order[i];
+                if (grp[i] != g || (pass == 0) != (cls[o] == ka)) continue;
+                po |= (unsigned long long)o << (4 * (4 * g + q));
+                if (pass == 1) ps |= 1u << (4 * g + q);
+                ++q;
+            }
+        const unsigned gs = (ps >> (4 * g)) & 15u;
+        if ((gs & 3u) != 0 || (nb > 0 && !(gs & 8u))) return false;   // not the fixed pattern
     }
     *out = po;
     *rep = pr;

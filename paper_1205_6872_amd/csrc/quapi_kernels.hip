@@ -953,14 +953,14 @@ __global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfm
     }
     // per-lane digit-0 products (item j) of its four outputs (with the self
     // factors in the class form)
+    // (class form: the host orders each group's outputs so that q = 0, 1
+    // take class slot 0 and q = 3 slot 1; only q = 2 is looked up)
     int oo[4] = {2 * g, 2 * g + 1, 8 + 2 * g, 9 + 2 * g};
-    bool slot1[4] = {false, false, false, false};
+    bool slot1[4] = {false, false, false, true};
     if (CLS) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            oo[q] = (int)((a.cls_out >> (4 * (4 * g + q))) & 15ull);
-            slot1[q] = (a.cls_selb >> (4 * g + q)) & 1u;
-        }
+        for (int q = 0; q < 4; ++q) oo[q] = (int)((a.cls_out >> (4 * (4 * g + q))) & 15ull);
+        slot1[2] = (a.cls_selb >> (4 * g + 2)) & 1u;
     }
     C plo[4];
     double2 acc[4];
@@ -1015,15 +1015,17 @@ __global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfm
     // tiers, whose groups are half as many bytes, load two groups ahead
     constexpr int PF = (MODE == 3 || sizeof(S) == 8) ? 1 : 2;
     constexpr int kStride = kBlock / 64;
+    // Group k of the wave's sweep sits in buffer k % (PF + 1); at FP64 the
+    // loop is unrolled over the PF + 1 buffers so that no buffer is copied
+    // (M = 4, L = 7, complex128 rho step 0.970 -> 0.924 ms).
     LW xb[PF + 1][8];
 #pragma unroll
     for (int k = 0; k < PF; ++k)
         if (i0 + k * kStride < i1) load(i0 + k * kStride, xb[k]);
-    for (int it = i0; it < i1; it += kStride) {
-        if (it + PF * kStride < i1) load(it + PF * kStride, xb[PF]);
+    auto group = [&](int it, const LW *xs) {
         T xw[8];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) xw[s] = (T)xb[0][s];
+        for (int s = 0; s < 8; ++s) xw[s] = (T)xs[s];
         const int qm = MODE == 3 ? diagonal_digits16(it, dm) : it;
         long long m, mb;
         const bool run = item(it, m, mb);
@@ -1074,10 +1076,29 @@ __global__ void __launch_bounds__(kBlock, (RHO && MODE <= 1) ? 3 : 1) step16_mfm
                 acc[q].y += v.y;
             }
         }
+    };
+    if constexpr (sizeof(T) == 8) {
+        for (int base = i0; base < i1; base += (PF + 1) * kStride) {
 #pragma unroll
-        for (int k = 0; k < PF; ++k)
+            for (int u = 0; u <= PF; ++u) {
+                const int it = base + u * kStride;
+                if (it >= i1) break;
+                if (it + PF * kStride < i1) load(it + PF * kStride, xb[(u + PF) % (PF + 1)]);
+                group(it, xb[u]);
+            }
+        }
+    } else {
+        // FP32: the buffers rotate instead (the unrolled form needs more
+        // registers, a wave less per SIMD, and was slower: M = 4, L = 7,
+        // complex64 rho step 0.524 -> 0.540-0.547 ms)
+        for (int it = i0; it < i1; it += kStride) {
+            if (it + PF * kStride < i1) load(it + PF * kStride, xb[PF]);
+            group(it, xb[0]);
 #pragma unroll
-            for (int s = 0; s < 8; ++s) xb[k][s] = xb[k + 1][s];
+            for (int k = 0; k < PF; ++k)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) xb[k][s] = xb[k + 1][s];
+        }
     }
     if (RHO) {
         // sum over the 16 items of the lane group, then over the waves (the
