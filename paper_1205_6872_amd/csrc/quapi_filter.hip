@@ -125,17 +125,33 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
     constexpr int kOutUnroll = 1;
     // N <= 4: the upper factor levels of a segment are multiplied for every o
     // at once, before the outputs, so that their loads are in flight together
-    constexpr bool kHoist = N <= 4;
+    // (not in the FP64 count pass with rho, where the 2N held products cost a
+    // wave per SIMD: M = 2, L = 15, theta = 1e-10, complex128 step 0.670 ->
+    // 0.624 ms)
+    constexpr bool kHoist = N <= 4 && !(COUNT && RHO && sizeof(T) == 8);
+    // entries past a tile that a segment starting in it may reach
+    constexpr int kExt = N - 1;
+    // values staged with the keys (complex64 storage); complex128 values are
+    // read per segment from global memory (their registers in flight cost
+    // a wave per SIMD)
+    constexpr bool kStageVals = sizeof(CS) <= 8;
     extern __shared__ __align__(16) unsigned char f_smem[];
     double2 *s_acc = (double2 *)f_smem;
     __shared__ C s_old[N * N], s_oldf[N * N];
     __shared__ double2 s_t0[2 * LV::S0 * N];           // level 0 of the factor tables
-    __shared__ unsigned s_heads[kTile];                // tile offsets of the tile's segment heads
+    __shared__ unsigned short s_heads[kTile];          // tile offsets of the tile's segment heads
     __shared__ unsigned s_hw[kSpan][kWaves];           // heads per sub-tile and wave
     __shared__ unsigned s_kw[kWaves][N];               // write pass: kept outputs per wave and o
     __shared__ unsigned long long s_run[N];            // write pass: the block's next place per o
     __shared__ unsigned s_cnt[N];                      // count pass: the block's kept outputs per o
     __shared__ double2 s_red[kWaves][RHO ? N : 1];
+    // the staged tile: s_key[0] the key of the entry before it, s_key[1 + i]
+    // and s_val[i] key and value of entry base + i (i < kTile + kExt; keys
+    // past the last entry are ~0, which no segment matches), s_mask[i] its
+    // keep mask (write pass)
+    __shared__ unsigned long long s_key[kTile + kExt + 1];
+    __shared__ CS s_val[kStageVals ? kTile + kExt : 1];
+    __shared__ unsigned short s_mask[COUNT ? 1 : kTile];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const bool full = a.full != 0;
     const double2 *__restrict__ bank = a.bank;
@@ -154,20 +170,74 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
         if (COUNT) s_cnt[t] = 0;
         else s_run[t] = a.bofs[(size_t)t * gridDim.x + blockIdx.x];
     }
+    // |out| > theta as |out|^2 > theta^2 where theta^2 is a normal number
+    const bool squared = a.theta >= 1e-150;
+    const double theta2 = a.theta * a.theta;
     const unsigned long long n_in = *a.count_in;
     const unsigned long long chunk = (n_in + gridDim.x - 1) / gridDim.x;
     const unsigned long long lo = chunk * blockIdx.x;
     const unsigned long long hi = lo + chunk < n_in ? lo + chunk : n_in;
+
+    // The next tile's keys, values (and masks) are loaded into registers
+    // while the current tile, staged in LDS, is processed: one coalesced read
+    // per tile, and no global load waits on another.
+    unsigned long long pk[kSpan], pke = ~0ull, pprev = ~0ull;
+    CS pv[kStageVals ? kSpan : 1], pve = CS{};
+    unsigned short pm[kSpan];
+    auto fetch = [&](unsigned long long b) {
+#pragma unroll
+        for (int u = 0; u < kSpan; ++u) {
+            const unsigned long long k = b + (unsigned long long)u * kFB + t;
+            const bool in = k < n_in;
+            pk[u] = in ? keys[k] : ~0ull;
+            if (kStageVals) pv[kStageVals ? u : 0] = in ? vin[k] : CS{};
+            pm[u] = (!COUNT && k < hi) ? a.masks[k] : (unsigned short)0;
+        }
+        if (t < kExt) {
+            const unsigned long long k = b + kTile + t;
+            pke = k < n_in ? keys[k] : ~0ull;
+            if (kStageVals) pve = k < n_in ? vin[k] : CS{};
+        }
+        if (t == kFB - 1) pprev = b > 0 ? keys[b - 1] : ~0ull;
+    };
+    if (lo < hi) fetch(lo);
     __syncthreads();
+    // the oldest-point rows that are exactly one (the diagonal new points:
+    // every influence factor of a point with s_a = s_b is one): their
+    // contraction is a plain sum (interior and final-point tables alike)
+    unsigned ones = 0, ones_f = 0;
+    for (int o = 0; o < N; ++o) {
+        bool r = true, rf = true;
+        for (int i = 0; i < N; ++i) {
+            r = r && s_old[o * N + i].x == T(1) && s_old[o * N + i].y == T(0);
+            if (RHO) rf = rf && s_oldf[o * N + i].x == T(1) && s_oldf[o * N + i].y == T(0);
+        }
+        ones |= (unsigned)r << o;
+        ones_f |= (unsigned)(RHO && rf) << o;
+    }
 
     for (unsigned long long base = lo; base < hi; base += kTile) {
+#pragma unroll
+        for (int u = 0; u < kSpan; ++u) {
+            s_key[1 + u * kFB + t] = pk[u];
+            if (kStageVals) s_val[kStageVals ? u * kFB + t : 0] = pv[kStageVals ? u : 0];
+            if (!COUNT) s_mask[u * kFB + t] = pm[u];
+        }
+        if (t < kExt) {
+            s_key[1 + kTile + t] = pke;
+            if (kStageVals) s_val[kStageVals ? kTile + t : 0] = pve;
+        }
+        if (t == kFB - 1) s_key[0] = pprev;
+        if (base + kTile < hi) fetch(base + kTile);
+        __syncthreads();
         // the segment heads of the tile, gathered in key order (sub-tile u, then lane)
         bool head[kSpan];
         unsigned long long bal[kSpan];
 #pragma unroll
         for (int u = 0; u < kSpan; ++u) {
-            const unsigned long long k = base + (unsigned long long)u * kFB + t;
-            head[u] = k < hi && (k == 0 || seg_of<N>(keys[k - 1], full) != seg_of<N>(keys[k], full));
+            const int i = u * kFB + t;
+            head[u] = base + (unsigned long long)i < hi &&
+                      seg_of<N>(s_key[i], full) != seg_of<N>(s_key[1 + i], full);
             bal[u] = __ballot(head[u]);
             if (lane == 0) s_hw[u][wave] = (unsigned)__popcll(bal[u]);
         }
@@ -180,7 +250,7 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
                 if (w < wave) before += s_hw[u][w];
                 n_heads += s_hw[u][w];
             }
-            if (head[u]) s_heads[before + __popcll(bal[u] & lanes_below(lane))] = (unsigned)(u * kFB + t);
+            if (head[u]) s_heads[before + __popcll(bal[u] & lanes_below(lane))] = (unsigned short)(u * kFB + t);
         }
         __syncthreads();
 
@@ -194,43 +264,41 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
             unsigned mask = 0;
             unsigned lv[LV::kMax];                     // level indices of m
             if (active) {
-                kh = base + s_heads[r + t];
-                m = seg_of<N>(keys[kh], full);
+                const int h = s_heads[r + t];
+                kh = base + (unsigned long long)h;
+                m = seg_of<N>(s_key[1 + h], full);
                 if (full) {
                     // the segment's values by oldest digit (the dropped ones are zero)
-                    if constexpr (N <= 4) {
-                        // all N candidates loaded at once; those of the next segments are ignored
-                        unsigned long long kk[N];
+                    if constexpr (!kStageVals && N <= 4) {
+                        // all N candidates requested at once; those of the next segments are ignored
                         CS vv[N];
 #pragma unroll
-                        for (int e = 0; e < N; ++e) {
-                            const bool in = kh + e < n_in;
-                            kk[e] = in ? keys[kh + e] : ~0ull;
-                            vv[e] = in ? vin[kh + e] : CS{};
-                        }
+                        for (int e = 0; e < N; ++e)
+                            vv[e] = base + h + e < n_in ? vin[kh + e] : CS{};
 #pragma unroll
                         for (int e = 0; e < N; ++e) {
-                            if (seg_of<N>(kk[e], true) != m) continue;
-                            const int i = (int)(kk[e] % N);
+                            const unsigned long long key = s_key[1 + h + e];
+                            if (seg_of<N>(key, true) != m) continue;
+                            const int i = (int)(key % N);
 #pragma unroll
                             for (int ii = 0; ii < N; ++ii)
                                 if (ii == i) x[ii] = conv<C>(vv[e]);
                         }
                     } else {
-                        for (int e = 0; e < N && kh + e < n_in; ++e) {
-                            const unsigned long long key = keys[kh + e];
+                        for (int e = 0; e < N; ++e) {
+                            const unsigned long long key = s_key[1 + h + e];
                             if (seg_of<N>(key, true) != m) break;
                             const int i = (int)(key % N);
-                            const C v = conv<C>(vin[kh + e]);
+                            const C v = conv<C>(kStageVals ? s_val[kStageVals ? h + e : 0] : vin[kh + e]);
 #pragma unroll
                             for (int ii = 0; ii < N; ++ii)
                                 if (ii == i) x[ii] = v;
                         }
                     }
                 } else {
-                    x[0] = conv<C>(vin[kh]);
+                    x[0] = conv<C>(kStageVals ? s_val[kStageVals ? h : 0] : vin[kh]);
                 }
-                if (!COUNT) mask = a.masks[kh];
+                if (!COUNT) mask = s_mask[h];
             }
             {
                 lv[0] = (unsigned)(m % LV::S0);
@@ -304,10 +372,28 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
                     }
                     C sum = C{}, sumf = C{};
                     if (full) {
+                        // the plain sum serves the rows of ones (uniform over the wave: o is)
+                        C plain = C{};
+                        if ((ones | ones_f) >> o & 1u) {
 #pragma unroll
-                        for (int i = 0; i < N; ++i) {
-                            cmac(sum, s_old[o * N + i], x[i]);
-                            if (RHO) cmac(sumf, s_oldf[o * N + i], x[i]);
+                            for (int i = 0; i < N; ++i) {
+                                plain.x += x[i].x;
+                                plain.y += x[i].y;
+                            }
+                        }
+                        if (ones >> o & 1u) {
+                            sum = plain;
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < N; ++i) cmac(sum, s_old[o * N + i], x[i]);
+                        }
+                        if (RHO) {
+                            if (ones_f >> o & 1u) {
+                                sumf = plain;
+                            } else {
+#pragma unroll
+                                for (int i = 0; i < N; ++i) cmac(sumf, s_oldf[o * N + i], x[i]);
+                            }
                         }
                     } else {
                         sum = cmul(s_old[o * N], x[0]);
@@ -315,8 +401,8 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
                     }
                     const C out = cmul(from_d2<C>(p), sum);
                     if (COUNT) {
-                        const double re = out.x, im = out.y;
-                        if (sqrt(fma(re, re, im * im)) > a.theta) mask |= 1u << o;
+                        const double re = out.x, im = out.y, mag2 = fma(re, re, im * im);
+                        if (squared ? mag2 > theta2 : sqrt(mag2) > a.theta) mask |= 1u << o;
                         if (RHO) {
                             const double2 w = cmul(pf, to_d2(sumf));
                             double2 &acc = s_acc[o * kFB + t];
@@ -346,6 +432,7 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
                 __syncthreads();
             }
         }
+        __syncthreads();                               // the tile's LDS is read before the next is staged
     }
     if (COUNT) {
         __syncthreads();
