@@ -15,7 +15,10 @@ complex128 run is compared with the oracle the same way over its growth and
 7 full-window steps.  Also: theta = 0 equals the unfiltered oracle and keeps exactly the
 dense GPU tensor; results are bitwise reproducible and do not depend on how
 the steps are split into calls; an undersized capacity gives NOMEM and the
-overflow flag; a theta above every entry empties the tensor.
+overflow flag; a theta above every entry empties the tensor; M = 3 and 4 at
+sizes that give every block several tiles match the oracle exactly; complex64
+at L = 15 follows complex128; a theta below 1e-150 (square-root test) equals
+theta = 0.
 """
 import numpy as np
 import pytest
@@ -206,3 +209,47 @@ def test_selection_and_async_give_the_same_bits():
         stream.synchronize()
         got = out.cpu().numpy().view(np.complex128).reshape(n, 2, 2)
     assert np.array_equal(got, full[1:])
+
+
+@pytest.mark.parametrize("name", ["three_site_l8", "four_level_l6"])
+def test_blocks_of_several_tiles_against_oracle(name):
+    # a block walks its entries in tiles of 1024 staged a tile ahead; these
+    # sizes give each of the 2048 blocks several tiles (segments crossing
+    # tile and block edges, N = 9 and 16 reaching up to N - 1 entries past a
+    # tile)
+    if name == "three_site_l8":
+        w, n, theta = W.three_site_l8().with_(xi=0.3), 18, 1e-10
+    else:
+        rng = np.random.default_rng(5)
+        w = W.spin_boson_l7().with_(M=4, s=np.linspace(-1, 1, 4), H=W.random_hermitian(rng, 4),
+                                    rho0=np.diag([1.0, 0, 0, 0]).astype(complex), L=6, xi=0.3)
+        n, theta = 12, 1e-7
+    print(f"case {name}: M={w.M} L={w.L} steps={n} theta={theta:g}", flush=True)
+    ro, ko, margin = orun.oracle_run_filtered(w, n, theta)
+    assert margin > 1e-9, margin
+    assert ko[-1] > 2 * 1024 * 2048                # more than two tiles per block on average
+    rg, kg = gpu_filtered(w, n, theta)
+    assert list(kg) == list(ko)
+    err = (np.abs(rg - ro).reshape(n + 1, -1).max(axis=1) / np.abs(ro).reshape(n + 1, -1).max(axis=1)).max()
+    assert err <= 1e-12, err
+
+
+def test_complex64_staged_values_at_l15_against_complex128():
+    # complex64 storage stages its values with the keys (complex128 reads them
+    # per segment): at L = 15 (several tiles per block) its kept counts and
+    # rho follow the complex128 run, which the headline test pins to the oracle
+    w = W.spin_boson_l15("c128")
+    n, theta = w.L + 4, 1e-10
+    r128, k128 = gpu_filtered(w, n, theta, cap=2 ** 28)
+    r64, k64 = gpu_filtered(w, n, theta, dtype="c64", cap=2 ** 28)
+    assert np.all(np.abs(k64 - k128) <= 1e-3 * np.maximum(k128, 1)), np.abs(k64 - k128).max()
+    assert np.abs(r64 - r128).max() <= 2e-5, np.abs(r64 - r128).max()
+
+
+def test_tiny_theta_equals_theta_zero():
+    # theta below 1e-150 takes the square root in the threshold test (theta^2
+    # would not be a normal number); no entry here is below 1e-200
+    w = W.spin_boson_l7().with_(rho0=RHO_MIXED)
+    a, ka = gpu_filtered(w, 30, 0.0)
+    b, kb = gpu_filtered(w, 30, 1e-200)
+    assert np.array_equal(a, b) and np.array_equal(ka, kb)
