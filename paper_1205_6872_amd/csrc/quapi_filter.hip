@@ -460,17 +460,25 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
 }
 
 // Exclusive offsets of the n per-(o, block) counts in place (one block of
-// kFB threads, each owning a contiguous run), the total kept outputs, the new
-// entry count (at most the capacity) and the sticky overflow flag.
-__global__ void __launch_bounds__(kFB) filter_offsets_kernel(unsigned long long *bofs, int n,
-                                                             unsigned long long capacity,
-                                                             unsigned long long *count_out, int *overflow) {
-    __shared__ unsigned long long s_w[kWaves];
+// kOffB threads, each owning a contiguous run of at most kOffMax counts,
+// read once into registers), the total kept outputs, the new entry count (at
+// most the capacity) and the sticky overflow flag.
+constexpr int kOffB = 1024;
+constexpr int kOffMax = 16 * kFilterStepBlocks / kOffB;
+__global__ void __launch_bounds__(kOffB) filter_offsets_kernel(unsigned long long *bofs, int n,
+                                                               unsigned long long capacity,
+                                                               unsigned long long *count_out, int *overflow) {
+    __shared__ unsigned long long s_w[kOffB / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int per = (n + kFB - 1) / kFB;
+    const int per = (n + kOffB - 1) / kOffB;
     const int lo = std::min(n, t * per), hi = std::min(n, lo + per);
+    unsigned long long v[kOffMax];
     unsigned long long mine = 0;
-    for (int i = lo; i < hi; ++i) mine += bofs[i];
+#pragma unroll
+    for (int k = 0; k < kOffMax; ++k) {
+        v[k] = lo + k < hi ? bofs[lo + k] : 0ull;
+        mine += v[k];
+    }
     unsigned long long x = mine;
     for (int off = 1; off < 64; off <<= 1) {
         const unsigned long long y = __shfl_up(x, off, 64);
@@ -479,14 +487,14 @@ __global__ void __launch_bounds__(kFB) filter_offsets_kernel(unsigned long long 
     if (lane == 63) s_w[wave] = x;
     __syncthreads();
     unsigned long long run = x - mine, total = 0;
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < kOffB / 64; ++w) {
         if (w < wave) run += s_w[w];
         total += s_w[w];
     }
-    for (int i = lo; i < hi; ++i) {
-        const unsigned long long c = bofs[i];
-        bofs[i] = run;
-        run += c;
+#pragma unroll
+    for (int k = 0; k < kOffMax; ++k) {
+        if (lo + k < hi) bofs[lo + k] = run;
+        run += v[k];
     }
     if (t == 0) {
         *count_out = total < capacity ? total : capacity;
@@ -572,7 +580,8 @@ hipError_t launch_filter_step(int N, int prec, const FilterStepArgs &a, bool cou
 
 hipError_t launch_filter_offsets(int N, unsigned long long *bofs, unsigned long long capacity,
                                  unsigned long long *count_out, int *overflow, hipStream_t st) {
-    hipLaunchKernelGGL(filter_offsets_kernel, dim3(1), dim3(kFB), 0, st, bofs, N * kFilterStepBlocks, capacity,
+    if (N * kFilterStepBlocks > kOffB * kOffMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(filter_offsets_kernel, dim3(1), dim3(kOffB), 0, st, bofs, N * kFilterStepBlocks, capacity,
                        count_out, overflow);
     return hipGetLastError();
 }
