@@ -200,6 +200,33 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
         }
         if (t == kFB - 1) pprev = b > 0 ? keys[b - 1] : ~0ull;
     };
+    // The digits above level 1 change slowly along the sorted keys: the
+    // products of the levels >= 2 for the few values those digits take in
+    // the block's range are formed once, in LDS (at most kHiCache values;
+    // otherwise the segments multiply those levels from global memory).
+    constexpr int kHiCache = 4;
+    __shared__ double2 s_hi[kHiCache * N * 2];
+    const unsigned long long hdiv = (unsigned long long)LV::S0 * LV::S;
+    unsigned long long hv_lo = 0;
+    int n_hi = 0;
+    if (a.n_lv >= 3 && lo < hi) {
+        hv_lo = seg_of<N>(keys[lo], full) / hdiv;
+        const unsigned long long hv_hi = seg_of<N>(keys[hi - 1], full) / hdiv;
+        if (hv_hi - hv_lo < (unsigned long long)kHiCache) n_hi = (int)(hv_hi - hv_lo) + 1;
+    }
+    for (int idx = t; idx < n_hi * N; idx += kFB) {
+        const int o = idx % N;
+        unsigned long long v = hv_lo + (unsigned long long)(idx / N);
+        double2 p = make_double2(1.0, 0.0), pf = p;
+        for (int l = 2; l < a.n_lv; ++l) {
+            const double2 *q = a.t + 2 * (((size_t)LV::S0 + (size_t)(l - 1) * LV::S + v % LV::S) * N + o);
+            v /= LV::S;
+            p = cmul(p, q[0]);
+            if (RHO) pf = cmul(pf, q[1]);
+        }
+        s_hi[2 * idx] = p;
+        s_hi[2 * idx + 1] = pf;
+    }
     if (lo < hi) fetch(lo);
     __syncthreads();
     // the oldest-point rows that are exactly one (the diagonal new points:
@@ -318,19 +345,31 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
                 }
                 __syncthreads();
             }
+            // the segment's levels >= 2 from the block's LDS products (hc: their
+            // row there, -1 when they are not cached)
+            const unsigned long long hv = m / hdiv;
+            const int hc = hv >= hv_lo && hv - hv_lo < (unsigned long long)n_hi ? (int)(hv - hv_lo) : -1;
+            const int l_end = hc >= 0 ? 2 : LV::kMax;   // the global levels are 1 .. l_end - 1
             double2 up[kHoist ? N : 1], upf[kHoist ? N : 1];
             if constexpr (kHoist) {
 #pragma unroll
                 for (int o = 0; o < N; ++o) up[o] = upf[o] = make_double2(1.0, 0.0);
 #pragma unroll
                 for (int l = 1; l < LV::kMax; ++l) {
-                    if (l < a.n_lv && active) {
+                    if (l < a.n_lv && l < l_end && active) {
                         const double2 *q = a.t + 2 * (((size_t)LV::S0 + (size_t)(l - 1) * LV::S + lv[l]) * N);
 #pragma unroll
                         for (int o = 0; o < N; ++o) {
                             up[o] = cmul(up[o], q[2 * o]);
                             if (RHO) upf[o] = cmul(upf[o], q[2 * o + 1]);
                         }
+                    }
+                }
+                if (hc >= 0 && active) {
+#pragma unroll
+                    for (int o = 0; o < N; ++o) {
+                        up[o] = cmul(up[o], s_hi[2 * (hc * N + o)]);
+                        if (RHO) upf[o] = cmul(upf[o], s_hi[2 * (hc * N + o) + 1]);
                     }
                 }
             }
@@ -362,12 +401,16 @@ __global__ void __launch_bounds__(kFB) filter_step_kernel(const FilterStepArgs a
                     } else {
 #pragma unroll
                         for (int l = 1; l < LV::kMax; ++l) {
-                            if (l < a.n_lv) {
+                            if (l < a.n_lv && l < l_end) {
                                 const double2 *q =
                                     a.t + 2 * (((size_t)LV::S0 + (size_t)(l - 1) * LV::S + lv[l]) * N + o);
                                 p = cmul(p, q[0]);
                                 if (RHO) pf = cmul(pf, q[1]);
                             }
+                        }
+                        if (hc >= 0) {
+                            p = cmul(p, s_hi[2 * (hc * N + o)]);
+                            if (RHO) pf = cmul(pf, s_hi[2 * (hc * N + o) + 1]);
                         }
                     }
                     C sum = C{}, sumf = C{};
