@@ -135,7 +135,11 @@ size_t quapi_paper_pmc_bytes(int M, int dk_max);
  *               exceeds free device memory (or the QUAPI_FAKE_HBM_BYTES
  *               environment cap), the paper's "did not fit on the GPU".
  *   out         receives the context (NULL on failure).
- * Blocks until the setup has finished on the device. */
+ * Blocks until the setup has finished on the device.  For M = 4 the
+ * full-window steps contract the oldest point once per distinct s_a - s_b
+ * of the new point (a, b) where the levels allow it (evenly spaced levels
+ * do); QUAPI_STEP16_CLASSES=0 in the environment at creation keeps one
+ * contraction per new point (the results differ by rounding only). */
 quapi_status quapi_create(const quapi_params *p, void *hip_stream, void *workspace,
                           size_t ws_bytes, quapi_ctx **out);
 
