@@ -411,7 +411,7 @@ def main() -> int:
     ap.add_argument("--no-filtered", action="store_true", help="skip the path-filtered runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
               f"multi-GPU path", file=sys.stderr)
         return 2
 
