@@ -367,6 +367,25 @@ def test_maximum_size_m2_l17_fused_group_c64():
     _sampled_fused_check(w, "c64", 3e-5)
 
 
+@pytest.mark.parametrize("M,L,dtype,tol", [(3, 9, "c128", 1e-12), (4, 7, "c64f64", 1e-6)])
+def test_single_mirror_steps_at_large_sizes(M, L, dtype, tol):
+    # the single step in mirror mode (mode 1 with the N = 9 listed tail, or
+    # modes 1, 2 and the class form at N = 16, and mode 3) at M = 3, L = 9
+    # (3.9e8 entries) and M = 4, L = 7 (2.7e8): sampled entries of two
+    # full-window steps against the oracle's entry formula
+    rng = np.random.default_rng(31)
+    if M == 3:
+        w = W.three_site_l8().with_(L=L, xi=0.3)
+    else:
+        w = W.spin_boson_l7().with_(name="four_level_l7", M=4, s=np.linspace(-1, 1, 4),
+                                    H=W.random_hermitian(rng, 4), rho0=np.diag([1.0, 0, 0, 0]).astype(complex),
+                                    L=L, xi=0.3, dtype=dtype)
+    assert w.N ** L >= 2 ** 28
+    if not _fits(w, dtype):
+        pytest.skip("footprint exceeds free device memory")
+    _sampled_entry_check(w, dtype, tol)
+
+
 def test_maximum_size_m4_l8_single_steps_c64():
     # 16^8 = 4.3e9 entries, complex64 (2 x 34.4 GB); N = 16 runs single steps
     rng = np.random.default_rng(23)
